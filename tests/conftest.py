@@ -1,0 +1,41 @@
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+def make_scene(p, power, radius, normal=None, occ_logit=None, rgb=None, tex=None,
+               k=8, m=8, seed=0, sigma_scale=10.0, tau=20.0):
+    """Hand-built scene for closed-form tests (float32 arrays)."""
+    import workloads as W
+    rng = np.random.default_rng(seed)
+    p = np.asarray(p, dtype=np.float64).reshape(-1, 3)
+    n = p.shape[0]
+    if normal is None:
+        normal = rng.normal(size=(n, 3))
+        normal /= np.linalg.norm(normal, axis=1, keepdims=True)
+    if occ_logit is None:
+        occ_logit = rng.normal(size=n)
+    if rgb is None:
+        rgb = rng.uniform(size=(n, 3))
+    if tex is None:
+        tex = rng.normal(0, 0.1, size=(n, k, 3 + 6 * m))
+    f32 = lambda a: np.ascontiguousarray(np.asarray(a), dtype=np.float32)
+    return W.Scene(p=f32(p), power=f32(np.broadcast_to(power, (n,))), radius=f32(np.broadcast_to(radius, (n,))),
+                   normal=f32(np.asarray(normal).reshape(n, 3)), occ_logit=f32(np.broadcast_to(occ_logit, (n,))),
+                   rgb=f32(np.asarray(rgb).reshape(n, 3)), tex=f32(tex), sigma_scale=sigma_scale, tau=tau)
+
+
+@pytest.fixture
+def scene_factory():
+    return make_scene
