@@ -1,0 +1,183 @@
+/*
+ * powerfoam.h -- C ABI of the bounded-power-diagram renderer for gfx950.
+ *
+ * The library renders a scene of N cells.  Cell i is a site p_i with a power
+ * weight w_i and a sphere radius r_i; the rendered cell is the power cell
+ *   Pi_i = { x : |x-p_i|^2 - w_i <= |x-p_j|^2 - w_j  for all j }
+ * intersected with the sphere B(p_i, r_i) (Sec. 3.2 of the paper, power cell
+ * and bounded power diagram; appendix B, power distance).  Each cell is split
+ * by an oriented dipole face through p_i with normal n_i; the side the normal
+ * points away from is dense with density sigma_scale*softplus(lambda_i), the
+ * other side is empty (Sec. 3.3).  The face carries K detail sites with a
+ * soft-Voronoi displacement and Spherical-Voronoi radiance (Sec. 3.4,
+ * Eq. svdisp and Eq. svrad; Sec. 3.6).  A pixel's colour is the exact
+ * segment sum C = sum_k T_k alpha_k c_k over the cells its ray crosses, with
+ * A = 1 - T_end and a black background (Sec. 3.1).
+ *
+ * The same image is produced two ways: tile rasterisation with cells taken
+ * in increasing power distance from the camera centre, a valid painter's
+ * order for every ray through that centre (appendix B, theorem), and a
+ * cell-to-cell ray walk over the power-diagram adjacency clipped by the
+ * spheres (Sec. 3.2, ray tracing; appendix C).
+ *
+ * Conventions
+ *  - All array pointers are DEVICE pointers (gfx950 HBM) unless marked
+ *    "(host)".  float arrays are IEEE binary32, C-contiguous, row-major.
+ *  - Every call is stream-ordered on the caller's hipStream_t, passed as
+ *    void* (NULL = the null stream).  Calls that must size buffers from
+ *    device results synchronise that stream; this is stated per call.
+ *  - Every call returns a pf_status.  On a non-OK status, pf_last_error()
+ *    returns a thread-local message; outputs are unspecified and no handle
+ *    is created.  The library never aborts or exits.
+ *  - Parameters, images and gradients are caller-owned; the library keeps
+ *    pointers to the parameter arrays inside a scene, so they must stay
+ *    allocated and unchanged until pf_scene_destroy (re-build after changing
+ *    them).  Library-owned memory (adjacency, per-view lists, forward state)
+ *    is released by pf_scene_destroy / pf_state_release.
+ *  - Images: a call with ncam cameras writes ncam images back to back into
+ *    rgba, image c at float offset 4*sum_{c'<c} W_c'*H_c', each [H][W][4]
+ *    (R, G, B, A), pixel (x, y) at row y, column x, sampled at its centre.
+ */
+#ifndef POWERFOAM_H
+#define POWERFOAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PF_OK = 0,
+  PF_ERR_INVALID = 1,      /* bad argument: nothing was launched            */
+  PF_ERR_OOM = 2,          /* device allocation failed; the scene is intact */
+  PF_ERR_HIP = 3,          /* HIP runtime error (incl. earlier async faults) */
+  PF_ERR_UNSUPPORTED = 4,  /* valid but not built (e.g. K, M other than 8)  */
+  PF_ERR_OVERFLOW = 5      /* a fixed per-cell capacity was exceeded        */
+} pf_status;
+
+typedef struct pf_scene pf_scene;          /* opaque, library-owned */
+typedef struct pf_fwd_state pf_fwd_state;  /* opaque, library-owned */
+
+/* Cell parameters, structure of arrays (Sec. 3.2-3.4, 3.6).
+   tex[i][k] = (s.x, s.y, d, a_0.xyz .. a_{M-1}.xyz, c_0.rgb .. c_{M-1}.rgb):
+   detail-site position in the face frame, displacement along the normal,
+   M Spherical-Voronoi axes and their colours. */
+typedef struct {
+  int64_t n;                 /* number of cells, >= 1                         */
+  int32_t k_detail;          /* K detail sites per face (must be 8)           */
+  int32_t m_axes;            /* M SV axes per detail site (must be 8)         */
+  const float* p;            /* [n][3] sites                                  */
+  const float* power;        /* [n]    power weights w_i                      */
+  const float* radius;       /* [n]    sphere radii r_i (> 0)                 */
+  const float* normal;       /* [n][3] dipole normals (normalised on use)     */
+  const float* occ_logit;    /* [n]    density logits lambda_i                */
+  const float* rgb;          /* [n][3] base colours                           */
+  const float* tex;          /* [n][K][3+6M] detail-site texture              */
+  float sigma_scale;         /* density per world unit at softplus = 1        */
+  float tau;                 /* soft-Voronoi temperature per world unit       */
+} pf_params;
+
+/* A central camera.  c2w is row-major 3x4 camera-to-world (OpenCV axes: x
+   right, y down, z forward); column 3 is the centre every ray starts from
+   (t >= 0).  model 0 = pinhole (fx, fy, cx, cy in pixels); model 1 =
+   equidistant fisheye: polar angle = image radius / f_fish, pixels with angle
+   > theta_max render as 0. */
+typedef struct {
+  int32_t model;
+  int32_t width, height;
+  float c2w[12];
+  float fx, fy, cx, cy;
+  float f_fish, theta_max;
+} pf_camera;
+
+typedef struct {
+  /* Domain box for the ray walk.  If box_min[0] > box_max[0], the box is the
+     bounding box of all spheres grown by box_pad of its extent; otherwise the
+     given box is grown to contain the spheres.  Trace cameras must lie
+     inside it. */
+  float box_min[3], box_max[3];
+  float box_pad;             /* relative padding, default 0.01                */
+} pf_build_opts;
+
+typedef struct {
+  float t_min;               /* stop a ray once T < t_min (default 1e-6)      */
+  int32_t max_steps;         /* ray-walk step cap (default 4096)              */
+} pf_render_opts;
+
+typedef struct {
+  int64_t n;
+  int64_t n_faces;           /* total directed faces in the adjacency         */
+  int64_t n_hidden;          /* cells whose bounded cell is empty             */
+  int64_t n_overflow;        /* cells whose build exceeded a capacity (0)     */
+  float box_min[3], box_max[3];
+} pf_scene_info;
+
+/* Gradient outputs, same shapes as pf_params; the library ADDS into them
+   (the caller zeroes them).  Any pointer may be NULL to skip it. */
+typedef struct {
+  float *p, *power, *radius, *normal, *occ_logit, *rgb, *tex;
+} pf_grads;
+
+/* Builds the face adjacency of the power diagram clipped to the domain box
+   (the regular-triangulation adjacency the walk needs, appendix C; the
+   raster uses the subset of faces within each cell's sphere, Sec. 3.2),
+   per-cell cull radii bounding the non-empty part of each bounded cell, and
+   empty-cell flags.  params (host) is copied; its arrays are referenced.
+   opts (host) may be NULL.  Synchronises the stream (sizes the adjacency).
+   Errors: INVALID (n < 1, NULL array, K/M mismatch, non-positive radius),
+   UNSUPPORTED (K or M != 8), OOM, HIP, OVERFLOW (a cell exceeded the face
+   capacity; the scene is not created). */
+pf_status pf_build_scene(const pf_params* params, const pf_build_opts* opts,
+                         void* stream, pf_scene** out);
+
+/* Scene statistics (host struct). */
+pf_status pf_scene_info_get(const pf_scene* scene, pf_scene_info* info);
+
+/* Copies the adjacency out: row [n+1] int32 (CSR offsets) and col
+   [n_faces] int32 (neighbour index, or -1-f for face f of the domain box:
+   0 +x, 1 -x, 2 +y, 3 -y, 4 +z, 5 -z).  Device pointers, caller-owned. */
+pf_status pf_scene_adjacency(const pf_scene* scene, int32_t* row, int32_t* col, void* stream);
+
+void pf_scene_destroy(pf_scene* scene);
+
+/* Tile rasteriser (Sec. 3.2, rasterization; appendix B order): per camera,
+   cull each cell's bound into 16x16 tiles, sort each tile's cells by power
+   distance from the camera centre (ties: lower index), composite front to
+   back.  cams (host) [ncam]; opts (host) may be NULL; rgba as in the
+   conventions.  If state is non-NULL, *state receives a forward state for
+   pf_backward (stores per-pixel contribution records).  Synchronises the
+   stream once per camera (pair-list sizing).
+   Errors: INVALID (ncam < 1, bad camera), OOM, HIP. */
+pf_status pf_render_raster(pf_scene* scene, const pf_camera* cams, int32_t ncam,
+                           const pf_render_opts* opts, float* rgba,
+                           pf_fwd_state** state, void* stream);
+
+/* Ray walk (Sec. 3.2, ray tracing; appendix C): per pixel, start in the
+   cell of least power distance from the camera centre, cross faces of the
+   power diagram until the ray leaves the domain box, clip each cell by its
+   sphere.  Same image as pf_render_raster up to rounding.  Rays cut by
+   max_steps are counted in *truncated (host, may be NULL; the count is read
+   back, which synchronises the stream).
+   Errors: INVALID (also: camera centre outside the domain box), OOM, HIP. */
+pf_status pf_render_trace(pf_scene* scene, const pf_camera* cams, int32_t ncam,
+                          const pf_render_opts* opts, float* rgba,
+                          int64_t* truncated, void* stream);
+
+/* Gradients of L with respect to all cell parameters given dL/dRGBA
+   (d_rgba, same layout as the forward's rgba), for the forward recorded in
+   state.  Adds into grads (host struct of device pointers).
+   Errors: INVALID (NULL state/scene mismatch), OOM, HIP. */
+pf_status pf_backward(pf_scene* scene, const pf_fwd_state* state, const float* d_rgba,
+                      const pf_grads* grads, void* stream);
+
+void pf_state_release(pf_fwd_state* state);
+
+/* Thread-local message for the last non-OK status on this thread. */
+const char* pf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POWERFOAM_H */

@@ -1,0 +1,92 @@
+"""ctypes view of include/powerfoam.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpowerfoam.so")
+
+PF_OK, PF_ERR_INVALID, PF_ERR_OOM, PF_ERR_HIP, PF_ERR_UNSUPPORTED, PF_ERR_OVERFLOW = range(6)
+STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "OOM", 3: "HIP", 4: "UNSUPPORTED", 5: "OVERFLOW"}
+
+EXPORTS = ("pf_build_scene", "pf_scene_info_get", "pf_scene_adjacency", "pf_scene_destroy",
+           "pf_render_raster", "pf_render_trace", "pf_backward", "pf_state_release", "pf_last_error")
+
+
+class PfParams(C.Structure):
+    _fields_ = [("n", C.c_int64), ("k_detail", C.c_int32), ("m_axes", C.c_int32),
+                ("p", C.c_void_p), ("power", C.c_void_p), ("radius", C.c_void_p),
+                ("normal", C.c_void_p), ("occ_logit", C.c_void_p), ("rgb", C.c_void_p),
+                ("tex", C.c_void_p), ("sigma_scale", C.c_float), ("tau", C.c_float)]
+
+
+class PfCamera(C.Structure):
+    _fields_ = [("model", C.c_int32), ("width", C.c_int32), ("height", C.c_int32),
+                ("c2w", C.c_float * 12), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("f_fish", C.c_float),
+                ("theta_max", C.c_float)]
+
+
+class PfBuildOpts(C.Structure):
+    _fields_ = [("box_min", C.c_float * 3), ("box_max", C.c_float * 3), ("box_pad", C.c_float)]
+
+
+class PfRenderOpts(C.Structure):
+    _fields_ = [("t_min", C.c_float), ("max_steps", C.c_int32)]
+
+
+class PfSceneInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_faces", C.c_int64), ("n_hidden", C.c_int64),
+                ("n_overflow", C.c_int64), ("box_min", C.c_float * 3), ("box_max", C.c_float * 3)]
+
+
+class PfGrads(C.Structure):
+    _fields_ = [("p", C.c_void_p), ("power", C.c_void_p), ("radius", C.c_void_p),
+                ("normal", C.c_void_p), ("occ_logit", C.c_void_p), ("rgb", C.c_void_p),
+                ("tex", C.c_void_p)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Loads the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libpowerfoam.so not found at {path}; build it with "
+                           f"`python -m paper_2604_24994_amd.build`")
+    lib = C.CDLL(path)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    lib.pf_build_scene.argtypes = [C.POINTER(PfParams), C.POINTER(PfBuildOpts), vp, C.POINTER(vp)]
+    lib.pf_scene_info_get.argtypes = [vp, C.POINTER(PfSceneInfo)]
+    lib.pf_scene_adjacency.argtypes = [vp, vp, vp, vp]
+    lib.pf_scene_destroy.argtypes = [vp]
+    lib.pf_scene_destroy.restype = None
+    lib.pf_render_raster.argtypes = [vp, C.POINTER(PfCamera), i32, C.POINTER(PfRenderOpts), vp,
+                                     C.POINTER(vp), vp]
+    lib.pf_render_trace.argtypes = [vp, C.POINTER(PfCamera), i32, C.POINTER(PfRenderOpts), vp,
+                                    C.POINTER(i64), vp]
+    lib.pf_backward.argtypes = [vp, vp, vp, C.POINTER(PfGrads), vp]
+    lib.pf_state_release.argtypes = [vp]
+    lib.pf_state_release.restype = None
+    lib.pf_last_error.argtypes = []
+    lib.pf_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("pf_scene_destroy", "pf_state_release", "pf_last_error"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+class PowerFoamError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def check(status: int) -> None:
+    if status != PF_OK:
+        raise PowerFoamError(status, load().pf_last_error().decode(errors="replace"))

@@ -1,0 +1,191 @@
+// C ABI entry points: argument checks, error text, handle lifetime.
+#include <cmath>
+#include <new>
+#include <string>
+
+#include "pf_internal.hpp"
+#include "pf_render.hpp"
+
+struct pf_scene {
+  pf::Scene s;
+};
+
+struct pf_fwd_state {
+  const pf_scene* scene = nullptr;
+};
+
+namespace pf {
+
+static thread_local std::string g_error;
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+}  // namespace pf
+
+namespace {
+
+pf_status invalid(const std::string& msg) {
+  pf::set_error(msg);
+  return PF_ERR_INVALID;
+}
+
+int64_t image_floats(const pf_camera* cams, int32_t ncam) {
+  int64_t t = 0;
+  for (int c = 0; c < ncam; ++c) t += 4ll * cams[c].width * cams[c].height;
+  return t;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pf_last_error(void) { return pf::g_error.c_str(); }
+
+pf_status pf_build_scene(const pf_params* params, const pf_build_opts* opts, void* stream, pf_scene** out) {
+  if (!out) return invalid("pf_build_scene: out is NULL");
+  *out = nullptr;
+  if (!params) return invalid("pf_build_scene: params is NULL");
+  const pf_params& p = *params;
+  if (p.n < 1) return invalid("pf_build_scene: n must be >= 1");
+  if (p.n >= (1ll << 30)) return invalid("pf_build_scene: n must be < 2^30");
+  if (!p.p || !p.power || !p.radius || !p.normal || !p.occ_logit || !p.rgb || !p.tex)
+    return invalid("pf_build_scene: a parameter array is NULL");
+  if (p.k_detail < 1 || p.m_axes < 1) return invalid("pf_build_scene: k_detail and m_axes must be >= 1");
+  if (p.k_detail != pf::KD || p.m_axes != pf::MA) {
+    pf::set_error("pf_build_scene: only k_detail = 8 and m_axes = 8 are built");
+    return PF_ERR_UNSUPPORTED;
+  }
+  if (!std::isfinite(p.sigma_scale) || !(p.sigma_scale >= 0) || !std::isfinite(p.tau))
+    return invalid("pf_build_scene: sigma_scale and tau must be finite, sigma_scale >= 0");
+  pf_build_opts o{};
+  o.box_min[0] = 1.0f;
+  o.box_max[0] = -1.0f;
+  o.box_pad = 0.01f;
+  if (opts) o = *opts;
+  pf_scene* sc = new (std::nothrow) pf_scene();
+  if (!sc) {
+    pf::set_error("pf_build_scene: host allocation failed");
+    return PF_ERR_OOM;
+  }
+  pf_status st = pf::build_scene_impl(p, o, (hipStream_t)stream, &sc->s);
+  if (st != PF_OK) {
+    pf::free_scene(&sc->s);
+    delete sc;
+    return st;
+  }
+  *out = sc;
+  return PF_OK;
+}
+
+pf_status pf_scene_info_get(const pf_scene* scene, pf_scene_info* info) {
+  if (!scene || !info) return invalid("pf_scene_info_get: NULL argument");
+  info->n = scene->s.n;
+  info->n_faces = scene->s.n_faces;
+  info->n_hidden = scene->s.n_hidden;
+  info->n_overflow = scene->s.n_overflow;
+  for (int a = 0; a < 3; ++a) {
+    info->box_min[a] = scene->s.box_min[a];
+    info->box_max[a] = scene->s.box_max[a];
+  }
+  return PF_OK;
+}
+
+pf_status pf_scene_adjacency(const pf_scene* scene, int32_t* row, int32_t* col, void* stream) {
+  if (!scene || !row || !col) return invalid("pf_scene_adjacency: NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  PF_HIP_TRY(hipMemcpyAsync(row, scene->s.row, sizeof(int32_t) * (scene->s.n + 1), hipMemcpyDeviceToDevice, s));
+  if (scene->s.n_faces)
+    PF_HIP_TRY(hipMemcpyAsync(col, scene->s.col, sizeof(int32_t) * scene->s.n_faces, hipMemcpyDeviceToDevice, s));
+  return PF_OK;
+}
+
+void pf_scene_destroy(pf_scene* scene) {
+  if (!scene) return;
+  pf::free_scene(&scene->s);
+  delete scene;
+}
+
+static pf_status check_render(pf_scene* scene, const pf_camera* cams, int32_t ncam, const float* rgba,
+                              const char* who) {
+  if (!scene) return invalid(std::string(who) + ": scene is NULL");
+  if (!cams || ncam < 1) return invalid(std::string(who) + ": need ncam >= 1 cameras");
+  if (!rgba) return invalid(std::string(who) + ": rgba is NULL");
+  for (int c = 0; c < ncam; ++c) {
+    std::string why;
+    if (!pf::camera_ok(cams[c], &why)) return invalid(std::string(who) + ": camera " + std::to_string(c) + ": " + why);
+  }
+  return PF_OK;
+}
+
+pf_status pf_render_raster(pf_scene* scene, const pf_camera* cams, int32_t ncam, const pf_render_opts* opts,
+                           float* rgba, pf_fwd_state** state, void* stream) {
+  if (state) *state = nullptr;
+  pf_status st = check_render(scene, cams, ncam, rgba, "pf_render_raster");
+  if (st != PF_OK) return st;
+  if (state) {
+    pf::set_error("pf_render_raster: forward state is not available in this build");
+    return PF_ERR_UNSUPPORTED;
+  }
+  const float t_min = (opts && opts->t_min > 0) ? opts->t_min : 1e-6f;
+  hipStream_t s = (hipStream_t)stream;
+  int64_t off = 0;
+  for (int c = 0; c < ncam; ++c) {
+    st = pf::raster_view(scene->s, cams[c], t_min, rgba + off, s);
+    if (st != PF_OK) return st;
+    off += 4ll * cams[c].width * cams[c].height;
+  }
+  return PF_OK;
+}
+
+pf_status pf_render_trace(pf_scene* scene, const pf_camera* cams, int32_t ncam, const pf_render_opts* opts,
+                          float* rgba, int64_t* truncated, void* stream) {
+  pf_status st = check_render(scene, cams, ncam, rgba, "pf_render_trace");
+  if (st != PF_OK) return st;
+  for (int c = 0; c < ncam; ++c) {
+    const float* m = cams[c].c2w;
+    const float o[3] = {m[3], m[7], m[11]};
+    for (int a = 0; a < 3; ++a)
+      if (!(o[a] >= scene->s.box_min[a] && o[a] <= scene->s.box_max[a]))
+        return invalid("pf_render_trace: camera " + std::to_string(c) +
+                       " centre lies outside the domain box; rebuild the scene with a box containing it");
+  }
+  const float t_min = (opts && opts->t_min > 0) ? opts->t_min : 1e-6f;
+  const int max_steps = (opts && opts->max_steps > 0) ? opts->max_steps : 4096;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long* trunc = nullptr;
+  PF_HIP_TRY(hipMallocAsync((void**)&trunc, sizeof(unsigned long long), s));
+  hipError_t e = hipMemsetAsync(trunc, 0, sizeof(unsigned long long), s);
+  if (e != hipSuccess) {
+    (void)hipFreeAsync(trunc, s);
+    PF_HIP_TRY(e);
+  }
+  int64_t off = 0;
+  for (int c = 0; c < ncam && st == PF_OK; ++c) {
+    st = pf::trace_view(scene->s, cams[c], t_min, max_steps, rgba + off, trunc, s);
+    off += 4ll * cams[c].width * cams[c].height;
+  }
+  if (st == PF_OK && truncated) {
+    unsigned long long h = 0;
+    e = hipMemcpyAsync(&h, trunc, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      (void)hipFreeAsync(trunc, s);
+      PF_HIP_TRY(e);
+    }
+    *truncated = (int64_t)h;
+  }
+  (void)hipFreeAsync(trunc, s);
+  return st;
+}
+
+pf_status pf_backward(pf_scene* scene, const pf_fwd_state* state, const float* d_rgba, const pf_grads* grads,
+                      void* stream) {
+  (void)stream;
+  if (!scene || !state || !d_rgba || !grads) return invalid("pf_backward: NULL argument");
+  pf::set_error("pf_backward: not available in this build");
+  return PF_ERR_UNSUPPORTED;
+}
+
+void pf_state_release(pf_fwd_state* state) { delete state; }
+
+}  // extern "C"

@@ -1,0 +1,1007 @@
+// Scene build: face adjacency of the power diagram clipped to the domain
+// box, tight cull radii and hidden-cell flags.
+//
+// What is computed: for every cell i the faces of
+//   Pi_i = { x : |x-p_i|^2 - w_i <= |x-p_j|^2 - w_j }  (appendix B)
+// inside the domain box; these are the regular-triangulation edges the ray
+// walk crosses (appendix C).  Faces whose plane lies within r_i of p_i are
+// listed first: only they can cut the bounded cell Pi_i n B(p_i, r_i) that
+// the rasteriser composites (Sec. 3.2).
+//
+// How (gfx950): sites are Morton-sorted and grouped into an implicit 64-ary
+// tree (leaves of 64 consecutive sites; each node keeps an AABB and the
+// largest weight below it).  One wave64 owns one cell and holds its convex
+// polytope in registers as up to 128 vertices, two per lane, each vertex the
+// intersection of three planes with positive orientation det(m_a,m_b,m_c).
+// Clipping by a plane removes the vertices beyond it and re-triangulates the
+// cavity: every edge (a,b) from a removed vertex to a kept one yields the new
+// vertex (a,b,k).  An LDS table maps directed edges to vertex slots.
+// Candidates come nearest-first from the cell's own leaf, then from a tree
+// walk that prunes a node when no site in its box can be closer in power
+// than p_i to any current vertex:  dist(v,box)^2 - maxw >= |v-p_i|^2 - w_i.
+// Everything in the clipper is float64 in cell-local coordinates (FP64 runs
+// at the unpacked FP32 rate on CDNA).
+#include "pf_internal.hpp"
+
+#include <type_traits>
+#include <vector>
+
+namespace pf {
+namespace {
+
+constexpr int PM_BIG = 256;       // plane capacity of the high-degree pass
+constexpr int SPL_BIG = 8;        // vertex slots per lane of the high-degree pass
+constexpr int STACK = 512;
+constexpr int MAXLVL = 8;
+// Upper bound on candidate clips plus node visits per cell; a cell that
+// reaches it is reported as over capacity instead of running on.
+constexpr int WORK_LIMIT = 1 << 22;
+
+struct Levels {
+  int n;                          // number of node levels (>= 1)
+  long long off[MAXLVL];          // offset of level L (1-based) in the node arrays
+  long long cnt[MAXLVL + 1];      // cnt[0] = sites, cnt[L] = nodes at level L
+};
+
+__device__ inline uint32_t spread10(uint32_t v) {
+  v &= 1023u;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+__device__ inline float wave_min(float x) {
+  for (int o = 32; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o, 64));
+  return x;
+}
+__device__ inline float wave_max(float x) {
+  for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
+  return x;
+}
+__device__ inline double wave_max_d(double x) {
+  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
+// Per-block partial bounds of the spheres and weights:
+// [minx,miny,minz,maxx,maxy,maxz,maxw,minr] per block.
+__global__ void __launch_bounds__(256) k_bounds(const float* __restrict__ p, const float* __restrict__ w,
+                                                const float* __restrict__ r, int64_t n,
+                                                float* __restrict__ part) {
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  float wmax = -INFINITY, rmin = INFINITY;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    float ri = r[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float c = p[3 * i + a];
+      lo[a] = fminf(lo[a], c - ri);
+      hi[a] = fmaxf(hi[a], c + ri);
+    }
+    wmax = fmaxf(wmax, w[i]);
+    rmin = fminf(rmin, ri);
+  }
+  __shared__ float red[4][8];
+  float v[8] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], wmax, rmin};
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    bool is_min = (q < 3) || (q == 7);
+    v[q] = is_min ? wave_min(v[q]) : wave_max(v[q]);
+    if (lane == 0) red[wv][q] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    int q = threadIdx.x;
+    bool is_min = (q < 3) || (q == 7);
+    float a = red[0][q];
+    for (int k = 1; k < 4; ++k) a = is_min ? fminf(a, red[k][q]) : fmaxf(a, red[k][q]);
+    part[blockIdx.x * 8 + q] = a;
+  }
+}
+
+__global__ void k_morton(const float* __restrict__ p, int64_t n, float3 lo, float3 inv,
+                         uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t q[3];
+  float l[3] = {lo.x, lo.y, lo.z}, s[3] = {inv.x, inv.y, inv.z};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float t = (p[3 * i + a] - l[a]) * s[a];
+    t = fminf(fmaxf(t, 0.0f), 1023.0f);
+    q[a] = (uint32_t)t;
+  }
+  keys[i] = spread10(q[0]) | (spread10(q[1]) << 1) | (spread10(q[2]) << 2);
+  vals[i] = (uint32_t)i;
+}
+
+__global__ void k_gather_sites(const float* __restrict__ p, const float* __restrict__ w,
+                               const uint32_t* __restrict__ order, int64_t n, float4* __restrict__ sp,
+                               int32_t* __restrict__ sidx) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  uint32_t i = order[k];
+  sp[k] = make_float4(p[3 * i], p[3 * i + 1], p[3 * i + 2], w[i]);
+  sidx[k] = (int32_t)i;
+}
+
+// One wave per parent node: AABB and max weight of up to 64 children.
+__global__ void __launch_bounds__(64) k_tree_level(const float4* __restrict__ sp, const float4* __restrict__ clo,
+                                                   const float4* __restrict__ chi, int64_t nchild,
+                                                   float4* __restrict__ olo, float4* __restrict__ ohi) {
+  const int lane = threadIdx.x;
+  const int64_t c = (int64_t)blockIdx.x * 64 + lane;
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, w = -INFINITY;
+  if (c < nchild) {
+    if (sp) {
+      float4 s = sp[c];
+      lo[0] = hi[0] = s.x;
+      lo[1] = hi[1] = s.y;
+      lo[2] = hi[2] = s.z;
+      w = s.w;
+    } else {
+      float4 a = clo[c], b = chi[c];
+      lo[0] = a.x; lo[1] = a.y; lo[2] = a.z; w = a.w;
+      hi[0] = b.x; hi[1] = b.y; hi[2] = b.z;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = wave_min(lo[a]);
+    hi[a] = wave_max(hi[a]);
+  }
+  w = wave_max(w);
+  if (lane == 0) {
+    olo[blockIdx.x] = make_float4(lo[0], lo[1], lo[2], w);
+    ohi[blockIdx.x] = make_float4(hi[0], hi[1], hi[2], 0.0f);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Clipper of one cell, run by one wave.  SPL vertex slots per lane (64*SPL
+// vertices), PM plane capacity; the directed-edge -> vertex-slot table has
+// PM*PM entries of type EOT and lives in LDS (small variant) or in a per-cell
+// HBM workspace (large variant, for the few cells of very high degree).
+
+template <int SPL, int PM>
+struct Shared {
+  double pl[PM][4];               // planes (m.x, m.y, m.z, h), cell-local
+  int nb[PM];                     // neighbour (original index) or -1-f
+  int tid[64 * SPL];              // repack staging: packed plane triple
+  double tpos[64 * SPL][3];
+  int stack[STACK];
+  unsigned char used[PM];
+  unsigned short remap[PM];
+  unsigned long long omask[SPL];  // removed-vertex masks of the current clip
+};
+
+enum ClipResult { NOCUT = 0, CUT = 1, EMPTY = 2, OVER = 3 };
+
+template <int SPL>
+struct Poly {
+  int id[SPL];                    // packed (a | b<<8 | c<<16), slot lane + 64*s
+  double x[SPL], y[SPL], z[SPL];  // vertex positions
+  int ntri;                       // wave-uniform vertex count
+  double r2;                      // max |v|^2 (ball around p_i)
+  double cx, cy, cz, rc2;         // ball around the vertex centroid
+};
+
+__device__ inline void unpack(int id, int& a, int& b, int& c) {
+  a = id & 255;
+  b = (id >> 8) & 255;
+  c = (id >> 16) & 255;
+}
+
+__device__ inline double wave_sum_d(double x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+template <int PM, typename EOT>
+__device__ inline void reg_edges(EOT* eo, int id, int slot) {
+  int a, b, c;
+  unpack(id, a, b, c);
+  eo[a * PM + b] = (EOT)slot;
+  eo[b * PM + c] = (EOT)slot;
+  eo[c * PM + a] = (EOT)slot;
+}
+
+template <int SPL, int PM>
+__device__ inline void plane_triple(const Shared<SPL, PM>& S, int a, int b, double mx, double my, double mz,
+                                    double h, double& x, double& y, double& z) {
+  const double ax = S.pl[a][0], ay = S.pl[a][1], az = S.pl[a][2], ah = S.pl[a][3];
+  const double bx = S.pl[b][0], by = S.pl[b][1], bz = S.pl[b][2], bh = S.pl[b][3];
+  // c23 = b x k, c31 = k x a, c12 = a x b
+  const double c23x = by * mz - bz * my, c23y = bz * mx - bx * mz, c23z = bx * my - by * mx;
+  const double c31x = my * az - mz * ay, c31y = mz * ax - mx * az, c31z = mx * ay - my * ax;
+  const double c12x = ay * bz - az * by, c12y = az * bx - ax * bz, c12z = ax * by - ay * bx;
+  const double det = ax * c23x + ay * c23y + az * c23z;
+  const double inv = 1.0 / det;
+  x = (ah * c23x + bh * c31x + h * c12x) * inv;
+  y = (ah * c23y + bh * c31y + h * c12y) * inv;
+  z = (ah * c23z + bh * c31z + h * c12z) * inv;
+}
+
+template <int SPL>
+__device__ inline void update_bounds(Poly<SPL>& P) {
+  const int lane = threadIdx.x;
+  double m = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    if (lane + 64 * s < P.ntri) {
+      m = fmax(m, P.x[s] * P.x[s] + P.y[s] * P.y[s] + P.z[s] * P.z[s]);
+      sx += P.x[s];
+      sy += P.y[s];
+      sz += P.z[s];
+    }
+  }
+  P.r2 = wave_max_d(m);
+  const double inv = 1.0 / (double)P.ntri;
+  P.cx = wave_sum_d(sx) * inv;
+  P.cy = wave_sum_d(sy) * inv;
+  P.cz = wave_sum_d(sz) * inv;
+  double mc = 0.0;
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    if (lane + 64 * s < P.ntri) {
+      const double dx = P.x[s] - P.cx, dy = P.y[s] - P.cy, dz = P.z[s] - P.cz;
+      mc = fmax(mc, dx * dx + dy * dy + dz * dz);
+    }
+  }
+  P.rc2 = wave_max_d(mc);
+}
+
+// Clip the polytope by plane kp (already stored in S.pl[kp]).
+template <int SPL, int PM, typename EOT>
+__device__ ClipResult clip(Shared<SPL, PM>& S, EOT* eo, Poly<SPL>& P, int kp, double mx, double my, double mz,
+                           double h) {
+  constexpr int NT = 64 * SPL;
+  const int lane = threadIdx.x;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  bool in[SPL], out[SPL];
+  uint64_t ob[SPL];
+  int nout = 0;
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    in[s] = lane + 64 * s < P.ntri;
+    out[s] = in[s] && (mx * P.x[s] + my * P.y[s] + mz * P.z[s] > h);
+    ob[s] = __ballot(out[s]);
+    nout += __popcll(ob[s]);
+  }
+  if (nout == 0) return NOCUT;
+  if (nout == P.ntri) return EMPTY;
+  if (lane == 0) {
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) S.omask[s] = ob[s];
+  }
+  __syncthreads();
+
+  // new vertices: each edge from a removed vertex to a kept one
+  bool e[3 * SPL];
+  int ex[3 * SPL], ey[3 * SPL];
+  int my_new = 0;
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    int a, b, c;
+    unpack(P.id[s], a, b, c);
+    const int xs[3] = {a, b, c}, ys[3] = {b, c, a};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      ex[3 * s + q] = xs[q];
+      ey[3 * s + q] = ys[q];
+      bool keep_opp = false;
+      if (out[s]) {
+        const int opp = (int)eo[ys[q] * PM + xs[q]] & (NT - 1);
+        keep_opp = ((S.omask[opp >> 6] >> (opp & 63)) & 1ull) == 0ull;
+      }
+      e[3 * s + q] = out[s] && keep_opp;
+      my_new += e[3 * s + q] ? 1 : 0;
+    }
+  }
+  int incl = my_new;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += v;
+  }
+  const int total_new = __shfl(incl, 63, 64);
+  const int nkeep = P.ntri - nout;
+  if (nkeep + total_new > NT) return OVER;
+
+  int kbase = 0;
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    const bool keep = in[s] && !out[s];
+    const uint64_t kb = __ballot(keep);
+    if (keep) {
+      const int pos = kbase + __popcll(kb & lt);
+      S.tid[pos] = P.id[s];
+      S.tpos[pos][0] = P.x[s]; S.tpos[pos][1] = P.y[s]; S.tpos[pos][2] = P.z[s];
+    }
+    kbase += __popcll(kb);
+  }
+  int pos = nkeep + incl - my_new;
+#pragma unroll
+  for (int q = 0; q < 3 * SPL; ++q) {
+    if (e[q]) {
+      double x, y, z;
+      plane_triple(S, ex[q], ey[q], mx, my, mz, h, x, y, z);
+      S.tid[pos] = ex[q] | (ey[q] << 8) | (kp << 16);
+      S.tpos[pos][0] = x; S.tpos[pos][1] = y; S.tpos[pos][2] = z;
+      ++pos;
+    }
+  }
+  __syncthreads();
+  P.ntri = nkeep + total_new;
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    const int t = lane + 64 * s;
+    if (t < P.ntri) {
+      P.id[s] = S.tid[t];
+      P.x[s] = S.tpos[t][0]; P.y[s] = S.tpos[t][1]; P.z[s] = S.tpos[t][2];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < SPL; ++s)
+    if (lane + 64 * s < P.ntri) reg_edges<PM>(eo, P.id[s], lane + 64 * s);
+  __syncthreads();
+  update_bounds(P);
+  return CUT;
+}
+
+// Whether the bisector plane (m, h) can reach the polytope: it must come
+// within the bounding ball around the vertex centroid (or p_i coincides
+// with the other site).
+template <int SPL>
+__device__ inline bool may_cut(const Poly<SPL>& P, double mx, double my, double mz, double mm, double h) {
+  const double t = h - (mx * P.cx + my * P.cy + mz * P.cz);
+  return t < 0.0 || t * t < P.rc2 * mm || mm == 0.0;
+}
+
+struct Cand {
+  double mx, my, mz, mm, h;
+  int orig;
+  bool ok;
+};
+
+__device__ inline Cand load_cand(const float4* __restrict__ sp, const int32_t* __restrict__ sidx, int64_t j,
+                                 bool valid, double px, double py, double pz, double wi) {
+  Cand c;
+  c.ok = valid;
+  c.mx = c.my = c.mz = c.mm = c.h = 0.0;
+  c.orig = -1;
+  if (valid) {
+    float4 s = sp[j];
+    c.mx = (double)s.x - px;
+    c.my = (double)s.y - py;
+    c.mz = (double)s.z - pz;
+    c.mm = c.mx * c.mx + c.my * c.my + c.mz * c.mz;
+    c.h = 0.5 * (c.mm + wi - (double)s.w);
+    c.orig = sidx[j];
+  }
+  return c;
+}
+
+// Drops planes that no longer bound the polytope and renumbers the rest,
+// so that the plane capacity limits live faces only.  Returns the new plane
+// count.
+template <int SPL, int PM, typename EOT>
+__device__ int compact_planes(Shared<SPL, PM>& S, EOT* eo, Poly<SPL>& P, int nplanes) {
+  constexpr int NR = (PM + 63) / 64;
+  const int lane = threadIdx.x;
+  for (int q = lane; q < PM; q += 64) S.used[q] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    if (lane + 64 * s < P.ntri) {
+      int a, b, c;
+      unpack(P.id[s], a, b, c);
+      S.used[a] = 1; S.used[b] = 1; S.used[c] = 1;
+    }
+  }
+  __syncthreads();
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  bool u[NR];
+  int dst[NR];
+  double pl[NR][4];
+  int nbv[NR];
+  int base = 0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int q = lane + 64 * r;
+    u[r] = q < nplanes && q < PM && S.used[q];
+    const uint64_t m = __ballot(u[r]);
+    dst[r] = base + __popcll(m & lt);
+    base += __popcll(m);
+    if (u[r]) {
+      for (int c = 0; c < 4; ++c) pl[r][c] = S.pl[q][c];
+      nbv[r] = S.nb[q];
+      S.remap[q] = (unsigned short)dst[r];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (u[r]) {
+      for (int c = 0; c < 4; ++c) S.pl[dst[r]][c] = pl[r][c];
+      S.nb[dst[r]] = nbv[r];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    if (lane + 64 * s < P.ntri) {
+      int a, b, c;
+      unpack(P.id[s], a, b, c);
+      P.id[s] = S.remap[a] | (S.remap[b] << 8) | (S.remap[c] << 16);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < SPL; ++s)
+    if (lane + 64 * s < P.ntri) reg_edges<PM>(eo, P.id[s], lane + 64 * s);
+  __syncthreads();
+  return base;
+}
+
+// Sorts the 64 lanes' candidate slots by squared distance (bitonic network
+// over lanes) and loads the candidates in that order.
+__device__ inline Cand sorted_cands(const float4* __restrict__ sp, const int32_t* __restrict__ sidx, int64_t j,
+                                   bool valid, double px, double py, double pz, double wi) {
+  const int lane = threadIdx.x;
+  double key = INFINITY;
+  if (valid) {
+    const float4 s = sp[j];
+    const double dx = (double)s.x - px, dy = (double)s.y - py, dz = (double)s.z - pz;
+    key = dx * dx + dy * dy + dz * dz;
+  }
+  int64_t jj = j;
+  for (int kk = 2; kk <= 64; kk <<= 1) {
+    for (int st = kk >> 1; st > 0; st >>= 1) {
+      const double ok = __shfl_xor(key, st, 64);
+      const int64_t oj = __shfl_xor(jj, st, 64);
+      const bool up = (lane & kk) == 0;
+      const bool lower = (lane & st) == 0;
+      const bool take = lower ? (up ? (ok < key) : (ok > key)) : (up ? (ok > key) : (ok < key));
+      if (take) { key = ok; jj = oj; }
+    }
+  }
+  return load_cand(sp, sidx, jj, key != INFINITY, px, py, pz, wi);
+}
+
+// Processes the candidates of this wave's lanes in lane order.  Returns
+// false when the cell became empty or overflowed (state in status).
+template <int SPL, int PM, typename EOT>
+__device__ bool process_cands(Shared<SPL, PM>& S, EOT* eo, Poly<SPL>& P, int& nplanes, int& status, const Cand& c,
+                              int self_orig, int& work) {
+  uint64_t mask = __ballot(c.ok && may_cut(P, c.mx, c.my, c.mz, c.mm, c.h));
+  while (mask) {
+    if (++work > WORK_LIMIT) {
+      status = OVER;
+      return false;
+    }
+    const int t = __ffsll((long long)mask) - 1;
+    mask &= mask - 1;
+    const double mx = __shfl(c.mx, t, 64), my = __shfl(c.my, t, 64), mz = __shfl(c.mz, t, 64);
+    const double mm = __shfl(c.mm, t, 64), h = __shfl(c.h, t, 64);
+    const int orig = __shfl(c.orig, t, 64);
+    if (mm == 0.0) {
+      // coincident sites: the one with the smaller weight (or, on a tie,
+      // the larger index) owns nothing
+      if (h < 0.0 || (h == 0.0 && orig < self_orig)) {
+        status = EMPTY;
+        return false;
+      }
+      continue;
+    }
+    if (!may_cut(P, mx, my, mz, mm, h)) continue;
+    if (nplanes == PM) {
+      nplanes = compact_planes(S, eo, P, nplanes);
+      if (nplanes == PM) {
+        status = OVER;
+        return false;
+      }
+    }
+    if (threadIdx.x == 0) {
+      S.pl[nplanes][0] = mx; S.pl[nplanes][1] = my; S.pl[nplanes][2] = mz; S.pl[nplanes][3] = h;
+      S.nb[nplanes] = orig;
+    }
+    __syncthreads();
+    const ClipResult res = clip(S, eo, P, nplanes, mx, my, mz, h);
+    if (res == CUT) {
+      ++nplanes;
+    } else if (res == EMPTY || res == OVER) {
+      status = res;
+      return false;
+    }
+  }
+  return true;
+}
+
+// BIG = false: all cells, sorted position k = blockIdx.x, faces at stride
+// FACE_CAP by original index, edge table in LDS.  BIG = true: the cells
+// listed in klist, faces at stride PM by list slot, edge table in HBM.
+template <int SPL, int PM, bool BIG>
+__global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, const int32_t* __restrict__ sidx,
+                                             int64_t n, const float4* __restrict__ nlo,
+                                             const float4* __restrict__ nhi, Levels lv, float3 bmin,
+                                             float3 bmax, const float* __restrict__ radius,
+                                             const int32_t* __restrict__ klist, unsigned short* __restrict__ eo_g,
+                                             int32_t* __restrict__ faces, int32_t* __restrict__ bigslot,
+                                             int32_t* __restrict__ counts, int32_t* __restrict__ nrast,
+                                             float* __restrict__ cull, int32_t* __restrict__ flags) {
+  using EOT = typename std::conditional<BIG, unsigned short, unsigned char>::type;
+  __shared__ Shared<SPL, PM> S;
+  __shared__ unsigned char eo_lds[BIG ? 1 : PM * PM];
+  EOT* eo;
+  if constexpr (BIG) eo = eo_g + (int64_t)blockIdx.x * PM * PM;
+  else eo = eo_lds;
+  const int lane = threadIdx.x;
+  const int64_t k = BIG ? (int64_t)klist[blockIdx.x] : (int64_t)blockIdx.x;
+  const float4 me = sp[k];
+  const int32_t self = sidx[k];
+  const double px = me.x, py = me.y, pz = me.z, wi = me.w;
+  const double ri = radius[self];
+
+  // domain box as the initial polytope
+  const double bh[6] = {(double)bmax.x - px, px - (double)bmin.x, (double)bmax.y - py,
+                        py - (double)bmin.y, (double)bmax.z - pz, pz - (double)bmin.z};
+  if (lane < 6) {
+    const int ax = lane >> 1;
+    const double sgn = (lane & 1) ? -1.0 : 1.0;
+    S.pl[lane][0] = ax == 0 ? sgn : 0.0;
+    S.pl[lane][1] = ax == 1 ? sgn : 0.0;
+    S.pl[lane][2] = ax == 2 ? sgn : 0.0;
+    S.pl[lane][3] = bh[lane];
+    S.nb[lane] = -1 - lane;
+  }
+  Poly<SPL> P;
+  P.ntri = 8;
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    P.id[s] = 0;
+    P.x[s] = P.y[s] = P.z[s] = 0.0;
+  }
+  if (lane < 8) {
+    const int sx = (lane & 1) ? -1 : 1, sy = (lane & 2) ? -1 : 1, sz = (lane & 4) ? -1 : 1;
+    const int X = sx > 0 ? 0 : 1, Y = sy > 0 ? 2 : 3, Z = sz > 0 ? 4 : 5;
+    // orientation det(m_X, m_Y, m_Z) = sx*sy*sz
+    P.id[0] = (sx * sy * sz > 0) ? (X | (Y << 8) | (Z << 16)) : (Y | (X << 8) | (Z << 16));
+    P.x[0] = sx > 0 ? bh[0] : -bh[1];
+    P.y[0] = sy > 0 ? bh[2] : -bh[3];
+    P.z[0] = sz > 0 ? bh[4] : -bh[5];
+  }
+  __syncthreads();
+  if (lane < 8) reg_edges<PM>(eo, P.id[0], lane);
+  __syncthreads();
+  update_bounds(P);
+  int nplanes = 6;
+  int status = CUT;
+  int work = 0;
+
+  // phase 1: own leaf, nearest first
+  const int64_t leaf = k / LEAF;
+  {
+    const int64_t j = leaf * LEAF + lane;
+    const Cand c = sorted_cands(sp, sidx, j, j < n && j != k, px, py, pz, wi);
+    process_cands(S, eo, P, nplanes, status, c, self, work);
+  }
+
+  // phase 2: tree walk, nearest children first
+  if (status == CUT) {
+    int top = 0;
+    const int topL = lv.n;
+    if (lane == 0) S.stack[0] = (topL << 24) | 0;
+    top = 1;
+    __syncthreads();
+    while (top > 0 && status == CUT) {
+      if (++work > WORK_LIMIT) {
+        status = OVER;
+        break;
+      }
+      const int ent = S.stack[top - 1];
+      --top;
+      const int L = ent >> 24;
+      const long long idx = ent & 0xFFFFFF;
+      if (L == 1) {
+        if (idx == leaf) continue;
+        const int64_t j = idx * LEAF + lane;
+        const Cand c = sorted_cands(sp, sidx, j, j < n, px, py, pz, wi);
+        if (!process_cands(S, eo, P, nplanes, status, c, self, work)) break;
+        continue;
+      }
+      // children are nodes of level L-1
+      const long long cnum = lv.cnt[L - 1];
+      const long long cidx = idx * 64 + lane;
+      const bool valid = cidx < cnum;
+      double lx = 0, ly = 0, lz = 0, hx = 0, hy = 0, hz = 0, W = 0;
+      bool keep = false;
+      double dkey = INFINITY;
+      if (valid) {
+        const float4 a = nlo[lv.off[L - 1] + cidx], b = nhi[lv.off[L - 1] + cidx];
+        lx = (double)a.x - px; ly = (double)a.y - py; lz = (double)a.z - pz; W = a.w;
+        hx = (double)b.x - px; hy = (double)b.y - py; hz = (double)b.z - pz;
+        // ball around p_i
+        const double dx = fmax(0.0, fmax(lx, -hx)), dy = fmax(0.0, fmax(ly, -hy)), dz = fmax(0.0, fmax(lz, -hz));
+        const double D = sqrt(dx * dx + dy * dy + dz * dz);
+        const double R = sqrt(P.r2);
+        const bool far0 = D > R && (D - R) * (D - R) - W >= P.r2 - wi;
+        // ball around the vertex centroid
+        const double ex = fmax(0.0, fmax(lx - P.cx, P.cx - hx)), ey = fmax(0.0, fmax(ly - P.cy, P.cy - hy));
+        const double ez = fmax(0.0, fmax(lz - P.cz, P.cz - hz));
+        const double Dc = sqrt(ex * ex + ey * ey + ez * ez), Rc = sqrt(P.rc2);
+        const double cn = sqrt(P.cx * P.cx + P.cy * P.cy + P.cz * P.cz) + Rc;
+        const bool far1 = Dc > Rc && (Dc - Rc) * (Dc - Rc) - W >= cn * cn - wi;
+        keep = !(far0 || far1);
+        if (keep) dkey = dx * dx + dy * dy + dz * dz;
+      }
+      // order the surviving children by box distance, nearest last on the stack
+      int dlane = lane;
+      for (int kk = 2; kk <= 64; kk <<= 1) {
+        for (int st = kk >> 1; st > 0; st >>= 1) {
+          const double ok = __shfl_xor(dkey, st, 64);
+          const int ol = __shfl_xor(dlane, st, 64);
+          const bool up = (lane & kk) == 0;
+          const bool lower = (lane & st) == 0;
+          const bool take = lower ? (up ? (ok < dkey) : (ok > dkey)) : (up ? (ok > dkey) : (ok < dkey));
+          if (take) { dkey = ok; dlane = ol; }
+        }
+      }
+      const int nkeep = __popcll(__ballot(keep));
+      for (int r = nkeep - 1; r >= 0; --r) {
+        const int t = __shfl(dlane, r, 64);
+        const double blx = __shfl(lx, t, 64), bly = __shfl(ly, t, 64), blz = __shfl(lz, t, 64);
+        const double bhx = __shfl(hx, t, 64), bhy = __shfl(hy, t, 64), bhz = __shfl(hz, t, 64);
+        const double bw = __shfl(W, t, 64);
+        // exact per-vertex test: can any site in the box beat p_i at a vertex?
+        bool cut = false;
+#pragma unroll
+        for (int s = 0; s < SPL; ++s) {
+          if (lane + 64 * s >= P.ntri) continue;
+          const double vx = P.x[s], vy = P.y[s], vz = P.z[s];
+          const double dx = fmax(0.0, fmax(blx - vx, vx - bhx));
+          const double dy = fmax(0.0, fmax(bly - vy, vy - bhy));
+          const double dz = fmax(0.0, fmax(blz - vz, vz - bhz));
+          const double pw_box = dx * dx + dy * dy + dz * dz - bw;
+          const double pw_me = vx * vx + vy * vy + vz * vz - wi;
+          cut |= pw_box < pw_me;
+        }
+        if (__ballot(cut) != 0ull) {
+          if (top >= STACK) { status = OVER; break; }
+          if (lane == 0) S.stack[top] = ((L - 1) << 24) | (int)(idx * 64 + t);
+          ++top;
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // --- outputs
+  int32_t* out = BIG ? faces + (int64_t)blockIdx.x * PM : faces + (int64_t)self * FACE_CAP;
+  if (BIG && lane == 0) bigslot[self] = (int32_t)blockIdx.x;
+  if (status == EMPTY || status == OVER) {
+    if (lane == 0) {
+      counts[self] = 0;
+      nrast[self] = 0;
+      cull[self] = -1.0f;
+      flags[self] = status == EMPTY ? FLAG_EMPTY_POWER : FLAG_OVERFLOW;
+    }
+    return;
+  }
+  for (int q = lane; q < PM; q += 64) S.used[q] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    if (lane + 64 * s < P.ntri) {
+      int a, b, c;
+      unpack(P.id[s], a, b, c);
+      S.used[a] = 1; S.used[b] = 1; S.used[c] = 1;
+    }
+  }
+  __syncthreads();
+  // categories: 0 raster neighbour face, 1 other neighbour face, 2 box face
+  constexpr int NR = (PM + 63) / 64;
+  int cat[NR];
+  double viol = -INFINITY;  // max over faces of the signed distance of p_i outside
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int q = lane + 64 * r;
+    cat[r] = 3;
+    if (q < nplanes && S.used[q]) {
+      if (S.nb[q] < 0) {
+        cat[r] = 2;
+      } else {
+        const double mx = S.pl[q][0], my = S.pl[q][1], mz = S.pl[q][2], h = S.pl[q][3];
+        const double mn = sqrt(mx * mx + my * my + mz * mz);
+        cat[r] = (fabs(h) <= ri * mn * (1.0 + 1e-6)) ? 0 : 1;
+        viol = fmax(viol, -h / mn);
+      }
+    }
+  }
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int base = 0, nr = 0;
+  for (int ccat = 0; ccat < 3; ++ccat) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const uint64_t m = __ballot(cat[r] == ccat);
+      if (cat[r] == ccat) out[base + __popcll(m & lt)] = S.nb[lane + 64 * r];
+      base += __popcll(m);
+    }
+    if (ccat == 0) nr = base;
+  }
+  viol = wave_max_d(viol);
+  const double R = sqrt(P.r2);
+  if (lane == 0) {
+    counts[self] = base;
+    nrast[self] = nr;
+    const bool hidden = viol > ri;
+    cull[self] = hidden ? -1.0f : (float)fmin(ri, R * (1.0 + 1e-6));
+    flags[self] = 0;
+  }
+}
+
+__global__ void k_list_overflow(const int32_t* __restrict__ flags, const int32_t* __restrict__ spos, int64_t n,
+                                int32_t* __restrict__ klist, unsigned int* __restrict__ nlist) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && (flags[i] & FLAG_OVERFLOW)) klist[atomicAdd(nlist, 1u)] = spos[i];
+}
+
+__global__ void k_inverse(const int32_t* __restrict__ sidx, int64_t n, int32_t* __restrict__ spos) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) spos[sidx[k]] = (int32_t)k;
+}
+
+__global__ void k_fill(const float* __restrict__ p, const float* __restrict__ w, int64_t n,
+                       const int32_t* __restrict__ faces_tmp, const int32_t* __restrict__ faces_big,
+                       const int32_t* __restrict__ bigslot, const uint32_t* __restrict__ row,
+                       const int32_t* __restrict__ counts, float3 bmin, float3 bmax,
+                       int32_t* __restrict__ col, float4* __restrict__ plane) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double px = p[3 * i], py = p[3 * i + 1], pz = p[3 * i + 2], wi = w[i];
+  const int c = counts[i];
+  const uint32_t off = row[i];
+  for (int f = 0; f < c; ++f) {
+    const int b = bigslot[i];
+    const int v = b >= 0 ? faces_big[(int64_t)b * PM_BIG + f] : faces_tmp[i * FACE_CAP + f];
+    float4 pl;
+    if (v >= 0) {
+      const double mx = (double)p[3 * v] - px, my = (double)p[3 * v + 1] - py, mz = (double)p[3 * v + 2] - pz;
+      const double h = 0.5 * (mx * mx + my * my + mz * mz + wi - (double)w[v]);
+      pl = make_float4((float)mx, (float)my, (float)mz, (float)h);
+    } else {
+      const int bf = -1 - v, ax = bf >> 1;
+      const float sgn = (bf & 1) ? -1.0f : 1.0f;
+      const double lim = (bf & 1) ? -((ax == 0 ? (double)bmin.x : ax == 1 ? (double)bmin.y : (double)bmin.z) -
+                                      (ax == 0 ? px : ax == 1 ? py : pz))
+                                  : (ax == 0 ? (double)bmax.x : ax == 1 ? (double)bmax.y : (double)bmax.z) -
+                                        (ax == 0 ? px : ax == 1 ? py : pz);
+      pl = make_float4(ax == 0 ? sgn : 0.0f, ax == 1 ? sgn : 0.0f, ax == 2 ? sgn : 0.0f, (float)lim);
+    }
+    col[off + f] = v;
+    plane[off + f] = pl;
+  }
+}
+
+__device__ inline float softplus_f(float x) { return x > 20.0f ? x : log1pf(expf(x)); }
+
+__global__ void k_prep(const float* __restrict__ p, const float* __restrict__ r, const float* __restrict__ nrm,
+                       const float* __restrict__ lam, float sigma_scale, int64_t n, float4* __restrict__ geo,
+                       float4* __restrict__ onrm) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  geo[i] = make_float4(p[3 * i], p[3 * i + 1], p[3 * i + 2], r[i]);
+  const float nx = nrm[3 * i], ny = nrm[3 * i + 1], nz = nrm[3 * i + 2];
+  const float inv = 1.0f / sqrtf(nx * nx + ny * ny + nz * nz);
+  onrm[i] = make_float4(nx * inv, ny * inv, nz * inv, sigma_scale * softplus_f(lam[i]));
+}
+
+__global__ void k_count_flags(const int32_t* __restrict__ flags, const float* __restrict__ cull, int64_t n,
+                              unsigned long long* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool hid = false, ovf = false;
+  if (i < n) {
+    hid = cull[i] < 0.0f;
+    ovf = (flags[i] & FLAG_OVERFLOW) != 0;
+  }
+  const uint64_t bh = __ballot(hid), bo = __ballot(ovf);
+  if ((threadIdx.x & 63) == 0) {
+    if (bh) atomicAdd(&out[0], (unsigned long long)__popcll(bh));
+    if (bo) atomicAdd(&out[1], (unsigned long long)__popcll(bo));
+  }
+}
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  hipStream_t s;
+  explicit DevBuf(hipStream_t st) : s(st) {}
+  ~DevBuf() { if (p) (void)hipFreeAsync(p, s); }
+  hipError_t alloc(size_t count) { return hipMallocAsync((void**)&p, sizeof(T) * (count ? count : 1), s); }
+};
+
+}  // namespace
+
+void free_scene(Scene* sc) {
+  void* ptrs[] = {sc->geo, sc->nrm, sc->cull, sc->flags, sc->row, sc->nrast, sc->col, sc->plane};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  sc->geo = sc->nrm = nullptr;
+  sc->cull = nullptr;
+  sc->flags = sc->row = sc->nrast = sc->col = nullptr;
+  sc->plane = nullptr;
+}
+
+pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipStream_t s, Scene* sc) {
+  const int64_t n = prm.n;
+  sc->n = n;
+  sc->prm = prm;
+
+  // bounds of the spheres
+  const int nbk = (int)std::min<int64_t>(1024, (n + 255) / 256);
+  DevBuf<float> part(s);
+  PF_HIP_TRY(part.alloc((size_t)nbk * 8));
+  k_bounds<<<nbk, 256, 0, s>>>(prm.p, prm.power, prm.radius, n, part.p);
+  PF_HIP_TRY(hipGetLastError());
+  std::vector<float> hp((size_t)nbk * 8);
+  PF_HIP_TRY(hipMemcpyAsync(hp.data(), part.p, sizeof(float) * hp.size(), hipMemcpyDeviceToHost, s));
+  PF_HIP_TRY(hipStreamSynchronize(s));
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  float rmin = INFINITY;
+  for (int b = 0; b < nbk; ++b) {
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], hp[b * 8 + a]);
+      hi[a] = std::max(hi[a], hp[b * 8 + 3 + a]);
+    }
+    rmin = std::min(rmin, hp[b * 8 + 7]);
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (!std::isfinite(lo[a]) || !std::isfinite(hi[a])) {
+      set_error("pf_build_scene: non-finite site or radius");
+      return PF_ERR_INVALID;
+    }
+  }
+  if (!(rmin > 0.0f)) {
+    set_error("pf_build_scene: radii must be positive");
+    return PF_ERR_INVALID;
+  }
+  const bool user_box = opt.box_min[0] <= opt.box_max[0];
+  const float pad = opt.box_pad > 0.0f ? opt.box_pad : 0.01f;
+  for (int a = 0; a < 3; ++a) {
+    float l = lo[a], h = hi[a];
+    if (user_box) {
+      l = std::min(l, opt.box_min[a]);
+      h = std::max(h, opt.box_max[a]);
+    }
+    const float ext = std::max(h - l, 1e-6f);
+    sc->box_min[a] = l - pad * ext;
+    sc->box_max[a] = h + pad * ext;
+  }
+  const float3 bmin = make_float3(sc->box_min[0], sc->box_min[1], sc->box_min[2]);
+  const float3 bmax = make_float3(sc->box_max[0], sc->box_max[1], sc->box_max[2]);
+
+  // Morton order of the sites
+  DevBuf<uint32_t> keys(s), order(s);
+  PF_HIP_TRY(keys.alloc(n));
+  PF_HIP_TRY(order.alloc(n));
+  const float3 inv = make_float3(1024.0f / (bmax.x - bmin.x), 1024.0f / (bmax.y - bmin.y),
+                                 1024.0f / (bmax.z - bmin.z));
+  const unsigned g256 = (unsigned)((n + 255) / 256);
+  k_morton<<<g256, 256, 0, s>>>(prm.p, n, bmin, inv, keys.p, order.p);
+  PF_HIP_TRY(hipGetLastError());
+  PF_HIP_TRY(radix_sort_u32(keys.p, order.p, n, 30, s));
+  DevBuf<float4> sp(s);
+  DevBuf<int32_t> sidx(s);
+  PF_HIP_TRY(sp.alloc(n));
+  PF_HIP_TRY(sidx.alloc(n));
+  k_gather_sites<<<g256, 256, 0, s>>>(prm.p, prm.power, order.p, n, sp.p, sidx.p);
+  PF_HIP_TRY(hipGetLastError());
+
+  // implicit 64-ary tree
+  Levels lv{};
+  lv.cnt[0] = n;
+  long long total_nodes = 0;
+  int L = 0;
+  do {
+    ++L;
+    if (L > MAXLVL) {
+      set_error("pf_build_scene: too many sites for the build tree");
+      return PF_ERR_UNSUPPORTED;
+    }
+    lv.cnt[L] = (lv.cnt[L - 1] + 63) / 64;
+    lv.off[L] = total_nodes;
+    total_nodes += lv.cnt[L];
+  } while (lv.cnt[L] > 1);
+  lv.n = L;
+  // off[] is indexed by level; shift so that lv.off[L-1] addresses level L-1
+  // for L-1 >= 1 (level 0 = sites is never read through the node arrays).
+  DevBuf<float4> nlo(s), nhi(s);
+  PF_HIP_TRY(nlo.alloc(total_nodes));
+  PF_HIP_TRY(nhi.alloc(total_nodes));
+  for (int l = 1; l <= lv.n; ++l) {
+    const bool from_sites = l == 1;
+    k_tree_level<<<(unsigned)lv.cnt[l], 64, 0, s>>>(from_sites ? sp.p : nullptr,
+                                                    from_sites ? nullptr : nlo.p + lv.off[l - 1],
+                                                    from_sites ? nullptr : nhi.p + lv.off[l - 1],
+                                                    lv.cnt[l - 1], nlo.p + lv.off[l], nhi.p + lv.off[l]);
+    PF_HIP_TRY(hipGetLastError());
+  }
+
+  // per-cell clipping
+  PF_HIP_TRY(hipMalloc((void**)&sc->cull, sizeof(float) * n));
+  PF_HIP_TRY(hipMalloc((void**)&sc->flags, sizeof(int32_t) * n));
+  PF_HIP_TRY(hipMalloc((void**)&sc->nrast, sizeof(int32_t) * n));
+  PF_HIP_TRY(hipMalloc((void**)&sc->row, sizeof(int32_t) * (n + 1)));
+  PF_HIP_TRY(hipMalloc((void**)&sc->geo, sizeof(float4) * n));
+  PF_HIP_TRY(hipMalloc((void**)&sc->nrm, sizeof(float4) * n));
+  DevBuf<int32_t> faces_tmp(s), counts(s), bigslot(s), spos(s), klist(s), faces_big(s);
+  DevBuf<unsigned short> eo_big(s);
+  DevBuf<unsigned int> nbig_d(s);
+  PF_HIP_TRY(faces_tmp.alloc((size_t)n * FACE_CAP));
+  PF_HIP_TRY(counts.alloc(n + 1));
+  PF_HIP_TRY(bigslot.alloc(n));
+  PF_HIP_TRY(hipMemsetAsync(bigslot.p, 0xFF, sizeof(int32_t) * n, s));
+  k_clip<2, FACE_CAP, false><<<(unsigned)n, 64, 0, s>>>(sp.p, sidx.p, n, nlo.p, nhi.p, lv, bmin, bmax, prm.radius,
+                                                         nullptr, nullptr, faces_tmp.p, nullptr, counts.p,
+                                                         sc->nrast, sc->cull, sc->flags);
+  PF_HIP_TRY(hipGetLastError());
+  // second pass with larger capacity for the cells of very high degree
+  PF_HIP_TRY(spos.alloc(n));
+  PF_HIP_TRY(klist.alloc(n));
+  PF_HIP_TRY(nbig_d.alloc(1));
+  PF_HIP_TRY(hipMemsetAsync(nbig_d.p, 0, sizeof(unsigned int), s));
+  k_inverse<<<g256, 256, 0, s>>>(sidx.p, n, spos.p);
+  PF_HIP_TRY(hipGetLastError());
+  k_list_overflow<<<g256, 256, 0, s>>>(sc->flags, spos.p, n, klist.p, nbig_d.p);
+  PF_HIP_TRY(hipGetLastError());
+  unsigned int nbig = 0;
+  PF_HIP_TRY(hipMemcpyAsync(&nbig, nbig_d.p, sizeof(nbig), hipMemcpyDeviceToHost, s));
+  PF_HIP_TRY(hipStreamSynchronize(s));
+  sc->n_big = nbig;
+  if (nbig) {
+    PF_HIP_TRY(faces_big.alloc((size_t)nbig * PM_BIG));
+    PF_HIP_TRY(eo_big.alloc((size_t)nbig * PM_BIG * PM_BIG));
+    k_clip<SPL_BIG, PM_BIG, true><<<nbig, 64, 0, s>>>(sp.p, sidx.p, n, nlo.p, nhi.p, lv, bmin, bmax, prm.radius,
+                                                      klist.p, eo_big.p, faces_big.p, bigslot.p, counts.p,
+                                                      sc->nrast, sc->cull, sc->flags);
+    PF_HIP_TRY(hipGetLastError());
+  }
+
+  DevBuf<unsigned long long> cnt(s);
+  PF_HIP_TRY(cnt.alloc(2));
+  PF_HIP_TRY(hipMemsetAsync(cnt.p, 0, 2 * sizeof(unsigned long long), s));
+  k_count_flags<<<g256, 256, 0, s>>>(sc->flags, sc->cull, n, cnt.p);
+  PF_HIP_TRY(hipGetLastError());
+  PF_HIP_TRY(hipMemsetAsync(counts.p + n, 0, sizeof(int32_t), s));
+  PF_HIP_TRY(exclusive_scan_u32((const uint32_t*)counts.p, (uint32_t*)sc->row, n + 1, nullptr, s));
+  uint32_t total = 0;
+  unsigned long long hc[2] = {0, 0};
+  PF_HIP_TRY(hipMemcpyAsync(&total, sc->row + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  PF_HIP_TRY(hipMemcpyAsync(hc, cnt.p, sizeof(hc), hipMemcpyDeviceToHost, s));
+  PF_HIP_TRY(hipStreamSynchronize(s));
+  sc->n_faces = total;
+  sc->n_hidden = (int64_t)hc[0];
+  sc->n_overflow = (int64_t)hc[1];
+  if (sc->n_overflow) {
+    set_error("pf_build_scene: " + std::to_string(sc->n_overflow) +
+              " cells exceeded the per-cell face/vertex capacity");
+    return PF_ERR_OVERFLOW;
+  }
+  PF_HIP_TRY(hipMalloc((void**)&sc->col, sizeof(int32_t) * (total ? total : 1)));
+  PF_HIP_TRY(hipMalloc((void**)&sc->plane, sizeof(float4) * (total ? total : 1)));
+  k_fill<<<g256, 256, 0, s>>>(prm.p, prm.power, n, faces_tmp.p, faces_big.p, bigslot.p, (const uint32_t*)sc->row,
+                              counts.p, bmin, bmax,
+                              sc->col, sc->plane);
+  PF_HIP_TRY(hipGetLastError());
+  k_prep<<<g256, 256, 0, s>>>(prm.p, prm.radius, prm.normal, prm.occ_logit, prm.sigma_scale, n, sc->geo,
+                              sc->nrm);
+  PF_HIP_TRY(hipGetLastError());
+  PF_HIP_TRY(hipStreamSynchronize(s));
+  return PF_OK;
+}
+
+}  // namespace pf

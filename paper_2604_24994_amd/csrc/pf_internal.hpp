@@ -1,0 +1,77 @@
+// Internal declarations shared by the HIP translation units of libpowerfoam.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "powerfoam.h"
+
+namespace pf {
+
+constexpr int KD = 8;              // detail sites per face (built variant)
+constexpr int MA = 8;              // Spherical-Voronoi axes per detail site
+constexpr int TEXW = 3 + 6 * MA;   // floats per (cell, detail site)
+constexpr int TILE = 16;           // raster tile edge in pixels
+constexpr int FACE_CAP = 96;       // faces per cell incl. domain-box faces
+constexpr int LEAF = 64;           // sites per leaf of the build tree
+
+// Per-cell flags written by the build.
+constexpr int FLAG_EMPTY_POWER = 1;   // the power cell itself is empty
+constexpr int FLAG_OVERFLOW = 2;      // build capacity exceeded
+
+struct Scene {
+  int64_t n = 0;
+  pf_params prm{};                 // caller arrays (device) and constants
+  float box_min[3]{}, box_max[3]{};
+  // packed per-cell records
+  float4* geo = nullptr;           // (p, r)
+  float4* nrm = nullptr;           // (unit normal, sigma)
+  float* cull = nullptr;           // radius of a ball at p bounding the
+                                   // non-empty bounded cell; < 0: hidden
+  int32_t* flags = nullptr;
+  // adjacency, CSR; per cell: raster faces, other neighbour faces, box faces
+  int32_t* row = nullptr;          // [n+1]
+  int32_t* nrast = nullptr;        // [n] faces that can cut the sphere
+  int32_t* col = nullptr;          // [E] neighbour, or -1-f for box face f
+  float4* plane = nullptr;         // [E] (m, h): (x - p_i).m <= h
+  int64_t n_faces = 0, n_hidden = 0, n_overflow = 0, n_big = 0;
+};
+
+struct ViewOut;  // forward-state record sets (render)
+
+// Thread-local error text.
+void set_error(const std::string& msg);
+
+// Device allocation helpers (stream-ordered); return false on failure with
+// the error text set.
+bool dmalloc(void** p, size_t bytes, hipStream_t s, const char* what);
+void dfree(void* p, hipStream_t s);
+
+// --- scan / sort utilities (pf_util.hip) ---------------------------------
+// Exclusive prefix sum of n uint32 values; out may alias in.  Returns the
+// total through *total_dev (device, may be null).  Scratch is allocated on
+// the stream.
+hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n,
+                              uint32_t* total_dev, hipStream_t s);
+// Stable LSD radix sort of (key, value) pairs on the low `bits` bits of key.
+hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int bits,
+                          hipStream_t s);
+
+// --- build (pf_build.hip) -------------------------------------------------
+pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt,
+                           hipStream_t s, Scene* sc);
+void free_scene(Scene* sc);
+
+}  // namespace pf
+
+#define PF_HIP_TRY(expr)                                                    \
+  do {                                                                      \
+    hipError_t _e = (expr);                                                 \
+    if (_e != hipSuccess) {                                                 \
+      pf::set_error(std::string("HIP error ") + hipGetErrorString(_e) +    \
+                    " at " + __FILE__ + ":" + std::to_string(__LINE__));    \
+      return _e == hipErrorOutOfMemory ? PF_ERR_OOM : PF_ERR_HIP;           \
+    }                                                                       \
+  } while (0)

@@ -1,0 +1,534 @@
+// Rendering: tile rasteriser and ray walk over a built scene.
+//
+// Raster, per view (Sec. 3.2, rasterization; appendix B order):
+//   k_view_count  per cell: power distance from the camera centre (the sort
+//                 key) and the tile rectangle of its cull ball
+//   scan          cell offsets into the pair list
+//   k_view_emit   (tile, key<<32 | cell) pairs + tile histogram
+//   scan/scatter  counting sort by tile
+//   k_tile_sort   per tile, sort by (key, cell) in LDS (bitonic, global
+//                 memory fallback for long lists)
+//   k_raster      one 256-thread workgroup per 16x16 tile, one lane per
+//                 pixel, each wave an 8x8 quadrant walking the tile's list
+//                 front to back with wave-uniform cell loads
+// Trace, per view (Sec. 3.2, ray tracing; appendix C):
+//   k_start_*     argmin power distance from the camera centre
+//   k_trace       one lane per ray; per step the piece of the current cell
+//                 (same device code as the rasteriser) and the exit face
+#include "pf_internal.hpp"
+#include "pf_render.hpp"
+#include "pf_shade.hpp"
+
+#include <cmath>
+#include <vector>
+
+namespace pf {
+namespace {
+
+__device__ inline uint32_t order_key(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// Tile rectangle of a ball (camera-space centre X,Y,Z, radius rho).
+__device__ bool ball_rect(const pf_camera& c, double X, double Y, double Z, double rho, int tiles_x, int tiles_y,
+                          int& x0, int& x1, int& y0, int& y1) {
+  const double W = c.width, H = c.height;
+  double ulo, uhi, vlo, vhi;
+  bool full = false;
+  if (c.model == 0) {
+    if (Z + rho <= 0.0) return false;
+    if (Z - rho <= 1e-9 * (1.0 + fabs(Z))) {
+      full = true;
+    } else {
+      const double zz = Z * Z - rho * rho;
+      const double sx = rho * sqrt(fmax(0.0, X * X + zz));
+      const double sy = rho * sqrt(fmax(0.0, Y * Y + zz));
+      const double kxl = (X * Z - sx) / zz, kxh = (X * Z + sx) / zz;
+      const double kyl = (Y * Z - sy) / zz, kyh = (Y * Z + sy) / zz;
+      ulo = (double)c.fx * kxl + (double)c.cx;
+      uhi = (double)c.fx * kxh + (double)c.cx;
+      vlo = (double)c.fy * kyl + (double)c.cy;
+      vhi = (double)c.fy * kyh + (double)c.cy;
+    }
+  } else {
+    const double Lc = sqrt(X * X + Y * Y + Z * Z);
+    if (Lc <= rho * (1.0 + 1e-9)) {
+      full = true;
+    } else {
+      const double beta = asin(fmin(1.0, rho / Lc));
+      const double thc = acos(fmax(-1.0, fmin(1.0, Z / Lc)));
+      const double tmax = (double)c.theta_max;
+      if (thc - beta > tmax) return false;
+      const double f = (double)c.f_fish;
+      const double thi = fmin(tmax, thc + beta);
+      const double rhi = f * thi;
+      if (thc <= beta || thc + beta >= M_PI) {
+        ulo = c.cx - rhi; uhi = c.cx + rhi;
+        vlo = c.cy - rhi; vhi = c.cy + rhi;
+      } else {
+        const double tlo = fmax(0.0, thc - beta);
+        const double rlo = f * tlo;
+        const double phc = atan2(Y, X);
+        const double dph = asin(fmin(1.0, sin(beta) / sin(thc)));
+        const double pa = phc - dph, pb = phc + dph;
+        ulo = vlo = INFINITY;
+        uhi = vhi = -INFINITY;
+        const double ph[2] = {pa, pb}, rr[2] = {rlo, rhi};
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j) {
+            const double u = c.cx + rr[j] * cos(ph[i]), v = c.cy + rr[j] * sin(ph[i]);
+            ulo = fmin(ulo, u); uhi = fmax(uhi, u);
+            vlo = fmin(vlo, v); vhi = fmax(vhi, v);
+          }
+        // axis-aligned extremes of the outer arc inside [pa, pb]
+        for (int q = -4; q <= 4; ++q) {
+          const double a = q * (M_PI / 2);
+          if (a > pa && a < pb) {
+            const double u = c.cx + rhi * cos(a), v = c.cy + rhi * sin(a);
+            ulo = fmin(ulo, u); uhi = fmax(uhi, u);
+            vlo = fmin(vlo, v); vhi = fmax(vhi, v);
+          }
+        }
+      }
+    }
+  }
+  if (full) {
+    x0 = 0; x1 = tiles_x - 1;
+    y0 = 0; y1 = tiles_y - 1;
+    return true;
+  }
+  // pixels whose centre (p + 1/2) may lie in [lo, hi], padded by one pixel
+  const double pxl = ceil(ulo - 0.5) - 1.0, pxh = floor(uhi - 0.5) + 1.0;
+  const double pyl = ceil(vlo - 0.5) - 1.0, pyh = floor(vhi - 0.5) + 1.0;
+  if (!(pxh >= 0.0 && pyh >= 0.0 && pxl <= W - 1 && pyl <= H - 1)) return false;
+  x0 = (int)fmax(0.0, floor(fmax(pxl, 0.0) / TILE));
+  x1 = (int)fmin((double)(tiles_x - 1), floor(fmin(pxh, W - 1) / TILE));
+  y0 = (int)fmax(0.0, floor(fmax(pyl, 0.0) / TILE));
+  y1 = (int)fmin((double)(tiles_y - 1), floor(fmin(pyh, H - 1) / TILE));
+  return x0 <= x1 && y0 <= y1;
+}
+
+struct ViewArgs {
+  pf_camera cam;
+  int tiles_x, tiles_y;
+};
+
+__device__ inline bool cell_rect(const ViewArgs& v, const float4 g, float rho, int& x0, int& x1, int& y0, int& y1) {
+  if (!(rho >= 0.0f)) return false;
+  const float* m = v.cam.c2w;
+  const double ex = (double)g.x - m[3], ey = (double)g.y - m[7], ez = (double)g.z - m[11];
+  const double X = m[0] * ex + m[4] * ey + m[8] * ez;
+  const double Y = m[1] * ex + m[5] * ey + m[9] * ez;
+  const double Z = m[2] * ex + m[6] * ey + m[10] * ez;
+  return ball_rect(v.cam, X, Y, Z, (double)rho * (1.0 + 1e-5) + 1e-7, v.tiles_x, v.tiles_y, x0, x1, y0, y1);
+}
+
+__global__ void k_view_count(ViewArgs v, const float4* __restrict__ geo, const float* __restrict__ cull,
+                             const float* __restrict__ power, int64_t n, uint32_t* __restrict__ cnt,
+                             uint32_t* __restrict__ key) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float4 g = geo[i];
+  int x0, x1, y0, y1;
+  uint32_t c = 0;
+  if (cell_rect(v, g, cull[i], x0, x1, y0, y1)) c = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+  cnt[i] = c;
+  const float* m = v.cam.c2w;
+  const double ex = (double)m[3] - g.x, ey = (double)m[7] - g.y, ez = (double)m[11] - g.z;
+  key[i] = order_key((float)(ex * ex + ey * ey + ez * ez - (double)power[i]));
+}
+
+__global__ void k_view_emit(ViewArgs v, const float4* __restrict__ geo, const float* __restrict__ cull,
+                            int64_t n, const uint32_t* __restrict__ off, const uint32_t* __restrict__ key,
+                            uint32_t* __restrict__ ptile, unsigned long long* __restrict__ pval,
+                            uint32_t* __restrict__ tile_cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int x0, x1, y0, y1;
+  if (!cell_rect(v, geo[i], cull[i], x0, x1, y0, y1)) return;
+  uint32_t o = off[i];
+  const unsigned long long val = ((unsigned long long)key[i] << 32) | (uint32_t)i;
+  for (int ty = y0; ty <= y1; ++ty)
+    for (int tx = x0; tx <= x1; ++tx) {
+      const uint32_t t = (uint32_t)(ty * v.tiles_x + tx);
+      ptile[o] = t;
+      pval[o] = val;
+      atomicAdd(&tile_cnt[t], 1u);
+      ++o;
+    }
+}
+
+__global__ void k_tile_scatter(const uint32_t* __restrict__ ptile, const unsigned long long* __restrict__ pval,
+                               int64_t np, const uint32_t* __restrict__ tile_off, uint32_t* __restrict__ fill,
+                               unsigned long long* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const uint32_t t = ptile[i];
+  const uint32_t pos = tile_off[t] + atomicAdd(&fill[t], 1u);
+  out[pos] = pval[i];
+}
+
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_LDS = 4096;
+
+// Ascending sort of one tile's segment.  Bitonic network in its "flip"
+// form (every comparator puts the smaller value at the lower index), so a
+// length that is not a power of two is sorted with the missing tail treated
+// as +infinity and never touched.
+__global__ void __launch_bounds__(SORT_THREADS) k_tile_sort(unsigned long long* __restrict__ vals,
+                                                            const uint32_t* __restrict__ tile_off) {
+  __shared__ unsigned long long sh[SORT_LDS];
+  const uint32_t a = tile_off[blockIdx.x], b = tile_off[blockIdx.x + 1];
+  const uint32_t n = b - a;
+  if (n <= 1) return;
+  uint32_t n2 = 1;
+  while (n2 < n) n2 <<= 1;
+  const bool lds = n2 <= SORT_LDS;
+  unsigned long long* buf = lds ? sh : vals + a;
+  if (lds) {
+    for (uint32_t i = threadIdx.x; i < n; i += SORT_THREADS) sh[i] = vals[a + i];
+    __syncthreads();
+  }
+  for (uint32_t k = 2; k <= n2; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t t = threadIdx.x; t < n2 / 2; t += SORT_THREADS) {
+        // t-th comparator of this stage: lower index i has bit j clear
+        const uint32_t i = ((t / j) * 2 * j) + (t % j);
+        const uint32_t p = (j == (k >> 1)) ? (i ^ (k - 1)) : (i + j);
+        if (p < n) {
+          const unsigned long long x = buf[i], y = buf[p];
+          if (y < x) {
+            buf[i] = y;
+            buf[p] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (lds)
+    for (uint32_t i = threadIdx.x; i < n; i += SORT_THREADS) vals[a + i] = sh[i];
+}
+
+struct SceneDev {
+  const float4* geo;
+  const float4* nrm;
+  const float* cull;
+  const int32_t* row;
+  const int32_t* nrast;
+  const int32_t* col;
+  const float4* plane;
+  const float* rgb;
+  const float* tex;
+  float tau;
+};
+
+// One contribution of cell ci to the lane's pixel; returns false when the
+// lane's ray misses the cell's cull ball.
+__device__ inline void contribute(const SceneDev& S, const RayD& R, int ci, bool live, float& T, float& cr,
+                                  float& cg, float& cb) {
+  const float4 g = S.geo[ci];
+  const float rho = S.cull[ci];
+  const Local L = make_local(R, g.x, g.y, g.z);
+  const bool hit = live && (rho >= 0.0f) && (L.qq < (double)rho * (double)rho);
+  if (!__any(hit)) return;
+  const float* tx = S.tex + (int64_t)ci * (KD * TEXW);
+  if (hit) {
+    const int r0 = S.row[ci];
+    const Piece P = piece_geometry(R, L, g.w, S.plane + r0, S.nrast[ci], S.nrm[ci], tx, S.tau);
+    if (P.alpha > 0.0f) {
+      float r, gg, b;
+      radiance(tx, S.rgb + 3 * (int64_t)ci, P.ux, P.uy, R.fx, R.fy, R.fz, S.tau, r, gg, b);
+      const float wgt = T * P.alpha;
+      cr += wgt * r;
+      cg += wgt * gg;
+      cb += wgt * b;
+      T *= (1.0f - P.alpha);
+    }
+  }
+}
+
+__device__ inline void tile_pixel(int tiles_x, int& px, int& py) {
+  const int tile = blockIdx.x;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  px = tx * TILE + (w & 1) * 8 + (lane & 7);
+  py = ty * TILE + (w >> 1) * 8 + (lane >> 3);
+}
+
+__global__ void __launch_bounds__(256) k_raster(ViewArgs v, SceneDev S, const unsigned long long* __restrict__ list,
+                                                const uint32_t* __restrict__ tile_off, float t_min,
+                                                float* __restrict__ rgba) {
+  int px, py;
+  tile_pixel(v.tiles_x, px, py);
+  const bool inside = px < v.cam.width && py < v.cam.height;
+  const RayD R = make_ray(v.cam, px + 0.5, py + 0.5);
+  bool live = inside && R.valid;
+  float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
+  const uint32_t e0 = tile_off[blockIdx.x], e1 = tile_off[blockIdx.x + 1];
+  for (uint32_t e = e0; e < e1; ++e) {
+    if (!__any(live)) break;
+    const int ci = __builtin_amdgcn_readfirstlane((int)(uint32_t)list[e]);
+    contribute(S, R, ci, live, T, cr, cg, cb);
+    live = live && (T >= t_min);
+  }
+  if (inside) {
+    float* o = rgba + 4 * ((int64_t)py * v.cam.width + px);
+    o[0] = cr;
+    o[1] = cg;
+    o[2] = cb;
+    o[3] = 1.0f - T;
+  }
+}
+
+// argmin over cells with a non-empty power cell of pow(o, p_i) in float64;
+// ties go to the lower index.  Stage 1: per block; stage 2: one block.
+__global__ void __launch_bounds__(256) k_start_partial(const float* __restrict__ p, const float* __restrict__ w,
+                                                       const int32_t* __restrict__ flags, int64_t n, double ox,
+                                                       double oy, double oz, double* __restrict__ pk,
+                                                       long long* __restrict__ pi) {
+  double best = INFINITY;
+  long long bi = -1;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (flags[i] & FLAG_EMPTY_POWER) continue;
+    const double ex = ox - p[3 * i], ey = oy - p[3 * i + 1], ez = oz - p[3 * i + 2];
+    const double k = ex * ex + ey * ey + ez * ez - (double)w[i];
+    if (k < best || (k == best && (bi < 0 || i < bi))) {
+      best = k;
+      bi = i;
+    }
+  }
+  __shared__ double sk[256];
+  __shared__ long long si[256];
+  sk[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      const double k2 = sk[threadIdx.x + s];
+      const long long i2 = si[threadIdx.x + s];
+      if (i2 >= 0 && (si[threadIdx.x] < 0 || k2 < sk[threadIdx.x] || (k2 == sk[threadIdx.x] && i2 < si[threadIdx.x]))) {
+        sk[threadIdx.x] = k2;
+        si[threadIdx.x] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    pk[blockIdx.x] = sk[0];
+    pi[blockIdx.x] = si[0];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_start_final(const double* __restrict__ pk, const long long* __restrict__ pi,
+                                                     int nb, int32_t* __restrict__ out) {
+  __shared__ double sk[256];
+  __shared__ long long si[256];
+  double best = INFINITY;
+  long long bi = -1;
+  for (int b = threadIdx.x; b < nb; b += 256) {
+    if (pi[b] >= 0 && (bi < 0 || pk[b] < best || (pk[b] == best && pi[b] < bi))) {
+      best = pk[b];
+      bi = pi[b];
+    }
+  }
+  sk[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      const double k2 = sk[threadIdx.x + s];
+      const long long i2 = si[threadIdx.x + s];
+      if (i2 >= 0 && (si[threadIdx.x] < 0 || k2 < sk[threadIdx.x] || (k2 == sk[threadIdx.x] && i2 < si[threadIdx.x]))) {
+        sk[threadIdx.x] = k2;
+        si[threadIdx.x] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = (int32_t)si[0];
+}
+
+__global__ void __launch_bounds__(256) k_trace(ViewArgs v, SceneDev S, const int32_t* __restrict__ start,
+                                               float t_min, int max_steps, float* __restrict__ rgba,
+                                               unsigned long long* __restrict__ truncated) {
+  int px, py;
+  tile_pixel(v.tiles_x, px, py);
+  const bool inside = px < v.cam.width && py < v.cam.height;
+  const RayD R = make_ray(v.cam, px + 0.5, py + 0.5);
+  bool live = inside && R.valid;
+  float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
+  int cell = start[0];
+  int prev = -1;
+  double t_cur = 0.0;
+  bool cut = false;
+  if (live && cell >= 0) {
+    int step = 0;
+    for (; step < max_steps; ++step) {
+      const float4 g = S.geo[cell];
+      const Local L = make_local(R, g.x, g.y, g.z);
+      // contribution of this cell (identical code to the rasteriser)
+      const float rho = S.cull[cell];
+      if (rho >= 0.0f && L.qq < (double)rho * (double)rho) {
+        const float* tx = S.tex + (int64_t)cell * (KD * TEXW);
+        const int r0 = S.row[cell];
+        const Piece P = piece_geometry(R, L, g.w, S.plane + r0, S.nrast[cell], S.nrm[cell], tx, S.tau);
+        if (P.alpha > 0.0f) {
+          float r, gg, b;
+          radiance(tx, S.rgb + 3 * (int64_t)cell, P.ux, P.uy, R.fx, R.fy, R.fz, S.tau, r, gg, b);
+          const float wgt = T * P.alpha;
+          cr += wgt * r;
+          cg += wgt * gg;
+          cb += wgt * b;
+          T *= (1.0f - P.alpha);
+        }
+      }
+      if (T < t_min) break;
+      // exit: nearest face ahead of the current position that the ray leaves through
+      const float s_cur = (float)(t_cur + L.b);
+      const int f0 = S.row[cell], f1 = S.row[cell + 1];
+      float best = INFINITY, best_any = INFINITY;
+      int bf = -1, bf_any = -1;
+      for (int f = f0; f < f1; ++f) {
+        const int nbr = S.col[f];
+        if (nbr == prev) continue;
+        const float4 pl = S.plane[f];
+        const float a = R.fx * pl.x + R.fy * pl.y + R.fz * pl.z;
+        if (!(a > 0.0f)) continue;
+        const float s = (pl.w - (L.qx * pl.x + L.qy * pl.y + L.qz * pl.z)) * frcp(a);
+        if (s < best_any) { best_any = s; bf_any = f; }
+        if (s >= s_cur - 1e-6f * (1.0f + fabsf(s_cur)) && s < best) { best = s; bf = f; }
+      }
+      if (bf < 0) { bf = bf_any; best = best_any; }
+      if (bf < 0) break;
+      t_cur = fmax(t_cur, (double)best - L.b);
+      const int nx = S.col[bf];
+      if (nx < 0) break;   // left the domain box
+      prev = cell;
+      cell = nx;
+    }
+    cut = step == max_steps;
+  }
+  if (inside) {
+    float* o = rgba + 4 * ((int64_t)py * v.cam.width + px);
+    o[0] = cr;
+    o[1] = cg;
+    o[2] = cb;
+    o[3] = 1.0f - T;
+  }
+  const uint64_t bc = __ballot(cut);
+  if ((threadIdx.x & 63) == 0 && bc) atomicAdd(truncated, (unsigned long long)__popcll(bc));
+}
+
+SceneDev scene_dev(const Scene& sc) {
+  SceneDev d;
+  d.geo = sc.geo;
+  d.nrm = sc.nrm;
+  d.cull = sc.cull;
+  d.row = sc.row;
+  d.nrast = sc.nrast;
+  d.col = sc.col;
+  d.plane = sc.plane;
+  d.rgb = sc.prm.rgb;
+  d.tex = sc.prm.tex;
+  d.tau = sc.prm.tau;
+  return d;
+}
+
+template <typename T>
+struct Buf {
+  T* p = nullptr;
+  hipStream_t s;
+  explicit Buf(hipStream_t st) : s(st) {}
+  ~Buf() { if (p) (void)hipFreeAsync(p, s); }
+  hipError_t alloc(size_t count) { return hipMallocAsync((void**)&p, sizeof(T) * (count ? count : 1), s); }
+};
+
+}  // namespace
+
+bool camera_ok(const pf_camera& c, std::string* why) {
+  if (c.model != 0 && c.model != 1) { *why = "camera model must be 0 or 1"; return false; }
+  if (c.width < 1 || c.height < 1 || (int64_t)c.width * c.height > (1ll << 31) / 4) {
+    *why = "camera size out of range"; return false;
+  }
+  for (int i = 0; i < 12; ++i)
+    if (!std::isfinite(c.c2w[i])) { *why = "non-finite camera matrix"; return false; }
+  if (c.model == 0 && !(c.fx > 0 && c.fy > 0 && std::isfinite(c.cx) && std::isfinite(c.cy))) {
+    *why = "pinhole intrinsics must be finite with fx, fy > 0"; return false;
+  }
+  if (c.model == 1 && !(c.f_fish > 0 && c.theta_max > 0 && c.theta_max <= 3.14159274f)) {
+    *why = "fisheye needs f_fish > 0 and 0 < theta_max <= pi"; return false;
+  }
+  return true;
+}
+
+pf_status raster_view(const Scene& sc, const pf_camera& cam, float t_min, float* rgba, hipStream_t s) {
+  const int64_t n = sc.n;
+  ViewArgs v;
+  v.cam = cam;
+  v.tiles_x = (cam.width + TILE - 1) / TILE;
+  v.tiles_y = (cam.height + TILE - 1) / TILE;
+  const int64_t ntiles = (int64_t)v.tiles_x * v.tiles_y;
+  const unsigned g = (unsigned)((n + 255) / 256);
+  Buf<uint32_t> cnt(s), key(s), off(s), tcnt(s), toff(s), fill(s);
+  PF_HIP_TRY(cnt.alloc(n + 1));
+  PF_HIP_TRY(key.alloc(n));
+  PF_HIP_TRY(off.alloc(n + 1));
+  PF_HIP_TRY(tcnt.alloc(ntiles + 1));
+  PF_HIP_TRY(toff.alloc(ntiles + 1));
+  PF_HIP_TRY(fill.alloc(ntiles));
+  k_view_count<<<g, 256, 0, s>>>(v, sc.geo, sc.cull, sc.prm.power, n, cnt.p, key.p);
+  PF_HIP_TRY(hipGetLastError());
+  PF_HIP_TRY(hipMemsetAsync(cnt.p + n, 0, sizeof(uint32_t), s));
+  PF_HIP_TRY(exclusive_scan_u32(cnt.p, off.p, n + 1, nullptr, s));
+  uint32_t np = 0;
+  PF_HIP_TRY(hipMemcpyAsync(&np, off.p + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  PF_HIP_TRY(hipStreamSynchronize(s));
+  Buf<uint32_t> ptile(s);
+  Buf<unsigned long long> pval(s), sorted(s);
+  PF_HIP_TRY(ptile.alloc(np));
+  PF_HIP_TRY(pval.alloc(np));
+  PF_HIP_TRY(sorted.alloc(np));
+  PF_HIP_TRY(hipMemsetAsync(tcnt.p, 0, sizeof(uint32_t) * (ntiles + 1), s));
+  PF_HIP_TRY(hipMemsetAsync(fill.p, 0, sizeof(uint32_t) * ntiles, s));
+  k_view_emit<<<g, 256, 0, s>>>(v, sc.geo, sc.cull, n, off.p, key.p, ptile.p, pval.p, tcnt.p);
+  PF_HIP_TRY(hipGetLastError());
+  PF_HIP_TRY(exclusive_scan_u32(tcnt.p, toff.p, ntiles + 1, nullptr, s));
+  if (np) {
+    k_tile_scatter<<<(unsigned)((np + 255) / 256), 256, 0, s>>>(ptile.p, pval.p, np, toff.p, fill.p, sorted.p);
+    PF_HIP_TRY(hipGetLastError());
+    k_tile_sort<<<(unsigned)ntiles, SORT_THREADS, 0, s>>>(sorted.p, toff.p);
+    PF_HIP_TRY(hipGetLastError());
+  }
+  k_raster<<<(unsigned)ntiles, 256, 0, s>>>(v, scene_dev(sc), sorted.p, toff.p, t_min, rgba);
+  PF_HIP_TRY(hipGetLastError());
+  return PF_OK;
+}
+
+pf_status trace_view(const Scene& sc, const pf_camera& cam, float t_min, int max_steps, float* rgba,
+                     unsigned long long* trunc_dev, hipStream_t s) {
+  const int64_t n = sc.n;
+  ViewArgs v;
+  v.cam = cam;
+  v.tiles_x = (cam.width + TILE - 1) / TILE;
+  v.tiles_y = (cam.height + TILE - 1) / TILE;
+  const int64_t ntiles = (int64_t)v.tiles_x * v.tiles_y;
+  const int nb = (int)std::min<int64_t>(1024, (n + 255) / 256);
+  Buf<double> pk(s);
+  Buf<long long> pi(s);
+  Buf<int32_t> start(s);
+  PF_HIP_TRY(pk.alloc(nb));
+  PF_HIP_TRY(pi.alloc(nb));
+  PF_HIP_TRY(start.alloc(1));
+  k_start_partial<<<nb, 256, 0, s>>>(sc.prm.p, sc.prm.power, sc.flags, n, cam.c2w[3], cam.c2w[7], cam.c2w[11],
+                                     pk.p, pi.p);
+  PF_HIP_TRY(hipGetLastError());
+  k_start_final<<<1, 256, 0, s>>>(pk.p, pi.p, nb, start.p);
+  PF_HIP_TRY(hipGetLastError());
+  k_trace<<<(unsigned)ntiles, 256, 0, s>>>(v, scene_dev(sc), start.p, t_min, max_steps, rgba, trunc_dev);
+  PF_HIP_TRY(hipGetLastError());
+  return PF_OK;
+}
+
+}  // namespace pf

@@ -1,0 +1,15 @@
+// Host entry points of the render translation unit.
+#pragma once
+
+#include <string>
+
+#include "pf_internal.hpp"
+
+namespace pf {
+
+bool camera_ok(const pf_camera& c, std::string* why);
+pf_status raster_view(const Scene& sc, const pf_camera& cam, float t_min, float* rgba, hipStream_t s);
+pf_status trace_view(const Scene& sc, const pf_camera& cam, float t_min, int max_steps, float* rgba,
+                     unsigned long long* trunc_dev, hipStream_t s);
+
+}  // namespace pf

@@ -1,0 +1,261 @@
+// Per-(ray, cell) device math shared by the rasteriser, the ray walk and the
+// backward pass, so that the two renderers evaluate every contribution with
+// the same instructions.
+//
+// Numerics: the ray is generated in float64 and, per cell, re-expressed in
+// the cell's local frame in float64: q = closest-approach offset from p_i,
+// s = t - t_closest, so that x(t) - p_i = q + s d.  All lengths below are
+// then small numbers near the cell, computed in float32 (IEEE division is
+// replaced by the hardware reciprocal, <= 1 ulp).  The sphere discriminant is
+// formed in float64 (it cancels near tangency).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pf_internal.hpp"
+
+namespace pf {
+
+struct RayD {
+  double ox, oy, oz;   // camera centre
+  double dx, dy, dz;   // unit direction
+  float fx, fy, fz;    // direction rounded to float
+  bool valid;
+};
+
+// Ray through pixel-centre coordinates (u, v).
+__device__ inline RayD make_ray(const pf_camera& c, double u, double v) {
+  RayD r;
+  double dcx, dcy, dcz;
+  r.valid = true;
+  if (c.model == 0) {
+    dcx = (u - (double)c.cx) / (double)c.fx;
+    dcy = (v - (double)c.cy) / (double)c.fy;
+    dcz = 1.0;
+  } else {
+    const double ex = u - (double)c.cx, ey = v - (double)c.cy;
+    const double rho = sqrt(ex * ex + ey * ey);
+    const double th = rho / (double)c.f_fish;
+    r.valid = th <= (double)c.theta_max;
+    const double st = sin(th);
+    if (rho > 0.0) {
+      dcx = st * ex / rho;
+      dcy = st * ey / rho;
+    } else {
+      dcx = 0.0;
+      dcy = 0.0;
+    }
+    dcz = cos(th);
+  }
+  const float* m = c.c2w;
+  double wx = (double)m[0] * dcx + (double)m[1] * dcy + (double)m[2] * dcz;
+  double wy = (double)m[4] * dcx + (double)m[5] * dcy + (double)m[6] * dcz;
+  double wz = (double)m[8] * dcx + (double)m[9] * dcy + (double)m[10] * dcz;
+  const double inv = 1.0 / sqrt(wx * wx + wy * wy + wz * wz);
+  r.dx = wx * inv;
+  r.dy = wy * inv;
+  r.dz = wz * inv;
+  r.ox = m[3];
+  r.oy = m[7];
+  r.oz = m[11];
+  r.fx = (float)r.dx;
+  r.fy = (float)r.dy;
+  r.fz = (float)r.dz;
+  return r;
+}
+
+__device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Local frame of the ray at a cell: q (float), beta = s at t = 0, and the
+// squared closest-approach distance in float64.
+struct Local {
+  float qx, qy, qz;
+  float beta;
+  double qq;
+  double b;   // float64 beta
+};
+
+__device__ inline Local make_local(const RayD& R, float px, float py, float pz) {
+  Local L;
+  const double ocx = R.ox - (double)px, ocy = R.oy - (double)py, ocz = R.oz - (double)pz;
+  const double b = ocx * R.dx + ocy * R.dy + ocz * R.dz;
+  const double qx = ocx - b * R.dx, qy = ocy - b * R.dy, qz = ocz - b * R.dz;
+  L.qx = (float)qx;
+  L.qy = (float)qy;
+  L.qz = (float)qz;
+  L.qq = qx * qx + qy * qy + qz * qz;
+  L.b = b;
+  L.beta = (float)b;
+  return L;
+}
+
+// Duff et al., "Building an Orthonormal Basis, Revisited" (JCGT 2017).
+__device__ inline void onb(float nx, float ny, float nz, float& t1x, float& t1y, float& t1z, float& t2x,
+                           float& t2y, float& t2z) {
+  const float sign = copysignf(1.0f, nz);
+  const float a = -1.0f / (sign + nz);
+  const float b = nx * ny * a;
+  t1x = 1.0f + sign * nx * nx * a;
+  t1y = sign * b;
+  t1z = -sign * nx;
+  t2x = b;
+  t2y = sign + ny * ny * a;
+  t2z = -ny;
+}
+
+// Soft-Voronoi weights over the K detail sites at face point u (Sec. 3.4,
+// Eq. svdisp / Eq. svrad).  The logits are shifted by tau*|u| and written as
+//   |u - s_k| - |u| = (|s_k|^2 - 2 u.s_k) / (|u - s_k| + |u|),
+// which keeps them accurate when u is far from the sites (grazing rays).
+__device__ inline void sv_weights(const float* __restrict__ tx, float ux, float uy, float tau, float* w) {
+  const float un = sqrtf(ux * ux + uy * uy);
+  float mx = -INFINITY;
+#pragma unroll
+  for (int k = 0; k < KD; ++k) {
+    const float sx = tx[k * TEXW + 0], sy = tx[k * TEXW + 1];
+    const float ex = ux - sx, ey = uy - sy;
+    const float dist = sqrtf(ex * ex + ey * ey);
+    const float num = sx * sx + sy * sy - 2.0f * (ux * sx + uy * sy);
+    const float den = dist + un;
+    const float e = den > 0.0f ? num * frcp(den) : 0.0f;
+    w[k] = -tau * e;
+    mx = fmaxf(mx, w[k]);
+  }
+  float sum = 0.0f;
+#pragma unroll
+  for (int k = 0; k < KD; ++k) {
+    w[k] = __expf(w[k] - mx);
+    sum += w[k];
+  }
+  const float inv = frcp(sum);
+#pragma unroll
+  for (int k = 0; k < KD; ++k) w[k] *= inv;
+}
+
+// Geometry of one (ray, cell) piece: bounded interval, dipole split and
+// opacity.  faces/nfaces: the cell's raster faces.  Returns alpha (0 when
+// the piece is empty) and the texture point u, plus what the backward needs.
+struct Piece {
+  float alpha;
+  float ux, uy;       // texture point in the face frame
+  float s0, s1;       // bounded interval (local s)
+  float j0, j1;       // dense part
+  int bind0, bind1;   // binding constraint of s0 / s1: -1 sphere, -2 camera, f >= 0 face index
+  float den, sx, sbar, delta;
+  float t1x, t1y, t1z, t2x, t2y, t2z;
+};
+
+__device__ inline Piece piece_geometry(const RayD& R, const Local& L, float r, const float4* __restrict__ faces,
+                                       int nfaces, float4 nrm, const float* __restrict__ tx, float tau) {
+  Piece P;
+  P.alpha = 0.0f;
+  P.ux = P.uy = 0.0f;
+  P.bind0 = P.bind1 = -1;
+  const double D = (double)r * (double)r - L.qq;
+  P.s0 = 1.0f;
+  P.s1 = 0.0f;
+  if (D <= 0.0) return P;
+  const float sq = sqrtf((float)D);
+  float s0 = -sq, s1 = sq;
+  int b0 = -1, b1 = -1;
+  const float fx = R.fx, fy = R.fy, fz = R.fz;
+  for (int f = 0; f < nfaces; ++f) {
+    const float4 pl = faces[f];
+    const float a = fx * pl.x + fy * pl.y + fz * pl.z;
+    const float bb = pl.w - (L.qx * pl.x + L.qy * pl.y + L.qz * pl.z);
+    if (a > 0.0f) {
+      const float s = bb * frcp(a);
+      if (s < s1) { s1 = s; b1 = f; }
+    } else if (a < 0.0f) {
+      const float s = bb * frcp(a);
+      if (s > s0) { s0 = s; b0 = f; }
+    } else if (bb < 0.0f) {
+      s1 = -INFINITY;
+    }
+  }
+  if (L.beta > s0) { s0 = L.beta; b0 = -2; }
+  P.s0 = s0;
+  P.s1 = s1;
+  P.bind0 = b0;
+  P.bind1 = b1;
+  if (!(s0 < s1)) return P;
+
+  // dipole face with displacement (Sec. 3.3, Sec. 3.4)
+  const float nx = nrm.x, ny = nrm.y, nz = nrm.z;
+  onb(nx, ny, nz, P.t1x, P.t1y, P.t1z, P.t2x, P.t2y, P.t2z);
+  const float den = fx * nx + fy * ny + fz * nz;
+  const float qn = L.qx * nx + L.qy * ny + L.qz * nz;
+  const float qt1 = L.qx * P.t1x + L.qy * P.t1y + L.qz * P.t1z;
+  const float qt2 = L.qx * P.t2x + L.qy * P.t2y + L.qz * P.t2z;
+  const float dt1 = fx * P.t1x + fy * P.t1y + fz * P.t1z;
+  const float dt2 = fx * P.t2x + fy * P.t2y + fz * P.t2z;
+  P.den = den;
+  float j0 = s0, j1 = s1;
+  if (den != 0.0f) {
+    const float idn = 1.0f / den;
+    const float sbar = -qn * idn;
+    float w[KD];
+    sv_weights(tx, qt1 + sbar * dt1, qt2 + sbar * dt2, tau, w);
+    float delta = 0.0f;
+#pragma unroll
+    for (int k = 0; k < KD; ++k) delta += w[k] * tx[k * TEXW + 2];
+    const float sxx = (delta - qn) * idn;
+    if (den > 0.0f) j1 = fminf(s1, sxx);
+    else j0 = fmaxf(s0, sxx);
+    P.ux = qt1 + sxx * dt1;
+    P.uy = qt2 + sxx * dt2;
+    P.sx = sxx;
+    P.sbar = sbar;
+    P.delta = delta;
+  } else {
+    const float sm = 0.5f * (s0 + s1);
+    P.ux = qt1 + sm * dt1;
+    P.uy = qt2 + sm * dt2;
+    P.sx = 0.0f;
+    P.sbar = 0.0f;
+    P.delta = 0.0f;
+    if (!(qn < 0.0f)) j1 = j0;
+  }
+  P.j0 = j0;
+  P.j1 = j1;
+  const float ell = fmaxf(j1 - j0, 0.0f);
+  P.alpha = 1.0f - __expf(-nrm.w * ell);
+  return P;
+}
+
+// Radiance at texture point u for direction d: base colour plus the
+// soft-Voronoi blend of the detail sites' Spherical-Voronoi colours.
+__device__ inline void radiance(const float* __restrict__ tx, const float* __restrict__ rgb, float ux, float uy,
+                                float fx, float fy, float fz, float tau, float& cr, float& cg, float& cb) {
+  float w[KD];
+  sv_weights(tx, ux, uy, tau, w);
+  cr = rgb[0];
+  cg = rgb[1];
+  cb = rgb[2];
+#pragma unroll
+  for (int k = 0; k < KD; ++k) {
+    const float* t = tx + k * TEXW;
+    float lg[MA];
+    float mx = -INFINITY;
+#pragma unroll
+    for (int m = 0; m < MA; ++m) {
+      lg[m] = t[3 + 3 * m] * fx + t[4 + 3 * m] * fy + t[5 + 3 * m] * fz;
+      mx = fmaxf(mx, lg[m]);
+    }
+    float sum = 0.0f, sr = 0.0f, sg = 0.0f, sb = 0.0f;
+#pragma unroll
+    for (int m = 0; m < MA; ++m) {
+      const float e = __expf(lg[m] - mx);
+      sum += e;
+      sr += e * t[3 + 3 * MA + 3 * m];
+      sg += e * t[4 + 3 * MA + 3 * m];
+      sb += e * t[5 + 3 * MA + 3 * m];
+    }
+    const float sc = w[k] * frcp(sum);
+    cr += sc * sr;
+    cg += sc * sg;
+    cb += sc * sb;
+  }
+}
+
+}  // namespace pf
