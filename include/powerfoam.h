@@ -174,6 +174,21 @@ pf_status pf_backward(pf_scene* scene, const pf_fwd_state* state, const float* d
 
 void pf_state_release(pf_fwd_state* state);
 
+/* Kernel timing for measurement.  While enabled (on != 0), every kernel the
+   library launches is bracketed by HIP events on its stream; pf_profile_read
+   waits for those events and returns, per kernel name, the launch count and
+   the summed elapsed milliseconds since the last read, then clears them.
+   Disabled by default; enabling costs two event records per launch.
+   out (host) [max_entries]; *n_out receives the number of entries written. */
+typedef struct {
+  char name[48];
+  int64_t launches;
+  double total_ms;
+} pf_profile_entry;
+
+pf_status pf_profile_enable(int32_t on);
+pf_status pf_profile_read(pf_profile_entry* out, int32_t max_entries, int32_t* n_out);
+
 /* Thread-local message for the last non-OK status on this thread. */
 const char* pf_last_error(void);
 

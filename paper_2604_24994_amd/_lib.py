@@ -11,7 +11,8 @@ PF_OK, PF_ERR_INVALID, PF_ERR_OOM, PF_ERR_HIP, PF_ERR_UNSUPPORTED, PF_ERR_OVERFL
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "OOM", 3: "HIP", 4: "UNSUPPORTED", 5: "OVERFLOW"}
 
 EXPORTS = ("pf_build_scene", "pf_scene_info_get", "pf_scene_adjacency", "pf_scene_destroy",
-           "pf_render_raster", "pf_render_trace", "pf_backward", "pf_state_release", "pf_last_error")
+           "pf_render_raster", "pf_render_trace", "pf_backward", "pf_state_release", "pf_last_error",
+           "pf_profile_enable", "pf_profile_read")
 
 
 class PfParams(C.Structure):
@@ -39,6 +40,10 @@ class PfRenderOpts(C.Structure):
 class PfSceneInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_faces", C.c_int64), ("n_hidden", C.c_int64),
                 ("n_overflow", C.c_int64), ("box_min", C.c_float * 3), ("box_max", C.c_float * 3)]
+
+
+class PfProfileEntry(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double)]
 
 
 class PfGrads(C.Structure):
@@ -72,6 +77,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.pf_backward.argtypes = [vp, vp, vp, C.POINTER(PfGrads), vp]
     lib.pf_state_release.argtypes = [vp]
     lib.pf_state_release.restype = None
+    lib.pf_profile_enable.argtypes = [i32]
+    lib.pf_profile_read.argtypes = [C.POINTER(PfProfileEntry), i32, C.POINTER(i32)]
     lib.pf_last_error.argtypes = []
     lib.pf_last_error.restype = C.c_char_p
     for name in EXPORTS:
@@ -79,6 +86,19 @@ def load(path: str = LIB_PATH) -> C.CDLL:
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
+
+
+def profile_enable(on: bool = True) -> None:
+    check(load().pf_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    """{kernel name: (launches, total ms)} since the last read (waits for
+    the recorded events)."""
+    buf = (PfProfileEntry * 64)()
+    n = C.c_int32(0)
+    check(load().pf_profile_read(buf, 64, C.byref(n)))
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(n.value)}
 
 
 class PowerFoamError(RuntimeError):

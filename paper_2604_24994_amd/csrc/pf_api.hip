@@ -1,7 +1,12 @@
 // C ABI entry points: argument checks, error text, handle lifetime.
+#include <atomic>
 #include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "pf_internal.hpp"
 #include "pf_render.hpp"
@@ -19,6 +24,36 @@ namespace pf {
 static thread_local std::string g_error;
 
 void set_error(const std::string& msg) { g_error = msg; }
+
+namespace {
+struct ProfRec {
+  std::string name;
+  hipEvent_t e0, e1;
+};
+std::mutex g_prof_mu;
+std::atomic<bool> g_prof_on{false};
+std::vector<ProfRec> g_prof;
+}  // namespace
+
+bool profiling() { return g_prof_on.load(std::memory_order_relaxed); }
+
+int prof_begin(const char* name, hipStream_t s) {
+  ProfRec r{name, nullptr, nullptr};
+  if (hipEventCreate(&r.e0) != hipSuccess) return -1;
+  if (hipEventCreate(&r.e1) != hipSuccess) {
+    (void)hipEventDestroy(r.e0);
+    return -1;
+  }
+  (void)hipEventRecord(r.e0, s);
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.push_back(r);
+  return (int)g_prof.size() - 1;
+}
+
+void prof_end(int token, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (token >= 0 && token < (int)g_prof.size()) (void)hipEventRecord(g_prof[token].e1, s);
+}
 
 }  // namespace pf
 
@@ -187,5 +222,44 @@ pf_status pf_backward(pf_scene* scene, const pf_fwd_state* state, const float* d
 }
 
 void pf_state_release(pf_fwd_state* state) { delete state; }
+
+pf_status pf_profile_enable(int32_t on) {
+  pf::g_prof_on.store(on != 0);
+  return PF_OK;
+}
+
+pf_status pf_profile_read(pf_profile_entry* out, int32_t max_entries, int32_t* n_out) {
+  if (!n_out || (max_entries > 0 && !out)) return invalid("pf_profile_read: NULL argument");
+  std::vector<pf::ProfRec> recs;
+  {
+    std::lock_guard<std::mutex> lk(pf::g_prof_mu);
+    recs.swap(pf::g_prof);
+  }
+  std::map<std::string, std::pair<int64_t, double>> acc;
+  hipError_t first = hipSuccess;
+  for (auto& r : recs) {
+    hipError_t e = hipEventSynchronize(r.e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.e0, r.e1);
+    if (e != hipSuccess && first == hipSuccess) first = e;
+    auto& a = acc[r.name];
+    a.first += 1;
+    a.second += ms;
+    (void)hipEventDestroy(r.e0);
+    (void)hipEventDestroy(r.e1);
+  }
+  int32_t k = 0;
+  for (auto& kv : acc) {
+    if (k >= max_entries) break;
+    std::memset(out[k].name, 0, sizeof(out[k].name));
+    std::strncpy(out[k].name, kv.first.c_str(), sizeof(out[k].name) - 1);
+    out[k].launches = kv.second.first;
+    out[k].total_ms = kv.second.second;
+    ++k;
+  }
+  *n_out = k;
+  PF_HIP_TRY(first);
+  return PF_OK;
+}
 
 }  // extern "C"

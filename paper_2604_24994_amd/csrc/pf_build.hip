@@ -179,7 +179,9 @@ struct Shared {
   unsigned long long omask[SPL];  // removed-vertex masks of the current clip
 };
 
-enum ClipResult { NOCUT = 0, CUT = 1, EMPTY = 2, OVER = 3 };
+enum ClipResult { NOCUT = 0, CUT = 1, EMPTY = 2, OVER_V = 3, OVER_P = 4, OVER_W = 5, OVER_S = 6 };
+
+__device__ inline bool is_over(int st) { return st >= OVER_V; }
 
 template <int SPL>
 struct Poly {
@@ -309,7 +311,7 @@ __device__ ClipResult clip(Shared<SPL, PM>& S, EOT* eo, Poly<SPL>& P, int kp, do
   }
   const int total_new = __shfl(incl, 63, 64);
   const int nkeep = P.ntri - nout;
-  if (nkeep + total_new > NT) return OVER;
+  if (nkeep + total_new > NT) return OVER_V;
 
   int kbase = 0;
 #pragma unroll
@@ -481,7 +483,7 @@ __device__ bool process_cands(Shared<SPL, PM>& S, EOT* eo, Poly<SPL>& P, int& np
   uint64_t mask = __ballot(c.ok && may_cut(P, c.mx, c.my, c.mz, c.mm, c.h));
   while (mask) {
     if (++work > WORK_LIMIT) {
-      status = OVER;
+      status = OVER_W;
       return false;
     }
     const int t = __ffsll((long long)mask) - 1;
@@ -502,7 +504,7 @@ __device__ bool process_cands(Shared<SPL, PM>& S, EOT* eo, Poly<SPL>& P, int& np
     if (nplanes == PM) {
       nplanes = compact_planes(S, eo, P, nplanes);
       if (nplanes == PM) {
-        status = OVER;
+        status = OVER_P;
         return false;
       }
     }
@@ -514,7 +516,7 @@ __device__ bool process_cands(Shared<SPL, PM>& S, EOT* eo, Poly<SPL>& P, int& np
     const ClipResult res = clip(S, eo, P, nplanes, mx, my, mz, h);
     if (res == CUT) {
       ++nplanes;
-    } else if (res == EMPTY || res == OVER) {
+    } else if (res == EMPTY || is_over(res)) {
       status = res;
       return false;
     }
@@ -585,22 +587,35 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
 
   // phase 1: own leaf, nearest first
   const int64_t leaf = k / LEAF;
+  double dmax;
   {
     const int64_t j = leaf * LEAF + lane;
-    const Cand c = sorted_cands(sp, sidx, j, j < n && j != k, px, py, pz, wi);
+    const bool ok = j < n && j != k;
+    double d2 = 0.0;
+    if (ok) {
+      const float4 q = sp[j];
+      const double dx = (double)q.x - px, dy = (double)q.y - py, dz = (double)q.z - pz;
+      d2 = dx * dx + dy * dy + dz * dz;
+    }
+    dmax = fmax(sqrt(wave_max_d(d2)), 1e-6);
+    const Cand c = sorted_cands(sp, sidx, j, ok, px, py, pz, wi);
     process_cands(S, eo, P, nplanes, status, c, self, work);
   }
 
-  // phase 2: tree walk, nearest children first
-  if (status == CUT) {
-    int top = 0;
-    const int topL = lv.n;
-    if (lane == 0) S.stack[0] = (topL << 24) | 0;
-    top = 1;
+  // phase 2: the other sites in rings of doubling radius [dmin, dmax) around
+  // p_i, so that candidates come roughly nearest first across the whole tree
+  // (this keeps the transient polytope small).  Each ring walks the tree
+  // depth first, nearest child first, pruning by the current polytope; a
+  // ring that left no prunable work beyond dmax ends the search.
+  double dmin = 0.0;
+  while (status == CUT) {
+    bool skipped = false;
+    int top = 1;
+    if (lane == 0) S.stack[0] = (lv.n << 24) | 0;
     __syncthreads();
     while (top > 0 && status == CUT) {
       if (++work > WORK_LIMIT) {
-        status = OVER;
+        status = OVER_W;
         break;
       }
       const int ent = S.stack[top - 1];
@@ -610,7 +625,13 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
       if (L == 1) {
         if (idx == leaf) continue;
         const int64_t j = idx * LEAF + lane;
-        const Cand c = sorted_cands(sp, sidx, j, j < n, px, py, pz, wi);
+        const bool ok = j < n;
+        const Cand c0 = load_cand(sp, sidx, j, ok, px, py, pz, wi);
+        const bool beyond = ok && c0.mm >= dmax * dmax;
+        if (__ballot(beyond && may_cut(P, c0.mx, c0.my, c0.mz, c0.mm, c0.h)) != 0ull) skipped = true;
+        const bool inring = ok && !beyond && c0.mm >= dmin * dmin;
+        if (__ballot(inring) == 0ull) continue;
+        const Cand c = sorted_cands(sp, sidx, j, inring, px, py, pz, wi);
         if (!process_cands(S, eo, P, nplanes, status, c, self, work)) break;
         continue;
       }
@@ -637,8 +658,13 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
         const double cn = sqrt(P.cx * P.cx + P.cy * P.cy + P.cz * P.cz) + Rc;
         const bool far1 = Dc > Rc && (Dc - Rc) * (Dc - Rc) - W >= cn * cn - wi;
         keep = !(far0 || far1);
+        if (keep && D >= dmax) {
+          skipped = true;   // wait for a later ring
+          keep = false;
+        }
         if (keep) dkey = dx * dx + dy * dy + dz * dz;
       }
+      if (__ballot(valid && skipped) != 0ull) skipped = true;
       // order the surviving children by box distance, nearest last on the stack
       int dlane = lane;
       for (int kk = 2; kk <= 64; kk <<= 1) {
@@ -671,24 +697,29 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
           cut |= pw_box < pw_me;
         }
         if (__ballot(cut) != 0ull) {
-          if (top >= STACK) { status = OVER; break; }
+          if (top >= STACK) { status = OVER_S; break; }
           if (lane == 0) S.stack[top] = ((L - 1) << 24) | (int)(idx * 64 + t);
           ++top;
         }
       }
       __syncthreads();
     }
+    if (!skipped) break;
+    dmin = dmax;
+    dmax *= 2.0;
   }
 
   // --- outputs
   int32_t* out = BIG ? faces + (int64_t)blockIdx.x * PM : faces + (int64_t)self * FACE_CAP;
   if (BIG && lane == 0) bigslot[self] = (int32_t)blockIdx.x;
-  if (status == EMPTY || status == OVER) {
+  if (status == EMPTY || is_over(status)) {
     if (lane == 0) {
       counts[self] = 0;
       nrast[self] = 0;
       cull[self] = -1.0f;
-      flags[self] = status == EMPTY ? FLAG_EMPTY_POWER : FLAG_OVERFLOW;
+      const int why = status == OVER_V ? FLAG_OVER_VERTS : status == OVER_P ? FLAG_OVER_PLANES
+                    : status == OVER_W ? FLAG_OVER_WORK : FLAG_OVER_STACK;
+      flags[self] = status == EMPTY ? FLAG_EMPTY_POWER : (FLAG_OVERFLOW | why);
     }
     return;
   }
@@ -800,18 +831,17 @@ __global__ void k_prep(const float* __restrict__ p, const float* __restrict__ r,
   onrm[i] = make_float4(nx * inv, ny * inv, nz * inv, sigma_scale * softplus_f(lam[i]));
 }
 
+// out: [hidden, overflow, over-vertices, over-planes, over-work, over-stack]
 __global__ void k_count_flags(const int32_t* __restrict__ flags, const float* __restrict__ cull, int64_t n,
                               unsigned long long* __restrict__ out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool hid = false, ovf = false;
-  if (i < n) {
-    hid = cull[i] < 0.0f;
-    ovf = (flags[i] & FLAG_OVERFLOW) != 0;
-  }
-  const uint64_t bh = __ballot(hid), bo = __ballot(ovf);
-  if ((threadIdx.x & 63) == 0) {
-    if (bh) atomicAdd(&out[0], (unsigned long long)__popcll(bh));
-    if (bo) atomicAdd(&out[1], (unsigned long long)__popcll(bo));
+  const int f = i < n ? flags[i] : 0;
+  const bool b[6] = {i < n && cull[i] < 0.0f, (f & FLAG_OVERFLOW) != 0, (f & FLAG_OVER_VERTS) != 0,
+                     (f & FLAG_OVER_PLANES) != 0, (f & FLAG_OVER_WORK) != 0, (f & FLAG_OVER_STACK) != 0};
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const uint64_t m = __ballot(b[q]);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(&out[q], (unsigned long long)__popcll(m));
   }
 }
 
@@ -945,9 +975,12 @@ pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipSt
   PF_HIP_TRY(counts.alloc(n + 1));
   PF_HIP_TRY(bigslot.alloc(n));
   PF_HIP_TRY(hipMemsetAsync(bigslot.p, 0xFF, sizeof(int32_t) * n, s));
-  k_clip<2, FACE_CAP, false><<<(unsigned)n, 64, 0, s>>>(sp.p, sidx.p, n, nlo.p, nhi.p, lv, bmin, bmax, prm.radius,
+  {
+    ProfScope ps_clip("k_clip", s);
+    k_clip<2, FACE_CAP, false><<<(unsigned)n, 64, 0, s>>>(sp.p, sidx.p, n, nlo.p, nhi.p, lv, bmin, bmax, prm.radius,
                                                          nullptr, nullptr, faces_tmp.p, nullptr, counts.p,
                                                          sc->nrast, sc->cull, sc->flags);
+  }
   PF_HIP_TRY(hipGetLastError());
   // second pass with larger capacity for the cells of very high degree
   PF_HIP_TRY(spos.alloc(n));
@@ -972,14 +1005,14 @@ pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipSt
   }
 
   DevBuf<unsigned long long> cnt(s);
-  PF_HIP_TRY(cnt.alloc(2));
-  PF_HIP_TRY(hipMemsetAsync(cnt.p, 0, 2 * sizeof(unsigned long long), s));
+  PF_HIP_TRY(cnt.alloc(6));
+  PF_HIP_TRY(hipMemsetAsync(cnt.p, 0, 6 * sizeof(unsigned long long), s));
   k_count_flags<<<g256, 256, 0, s>>>(sc->flags, sc->cull, n, cnt.p);
   PF_HIP_TRY(hipGetLastError());
   PF_HIP_TRY(hipMemsetAsync(counts.p + n, 0, sizeof(int32_t), s));
   PF_HIP_TRY(exclusive_scan_u32((const uint32_t*)counts.p, (uint32_t*)sc->row, n + 1, nullptr, s));
   uint32_t total = 0;
-  unsigned long long hc[2] = {0, 0};
+  unsigned long long hc[6] = {0, 0, 0, 0, 0, 0};
   PF_HIP_TRY(hipMemcpyAsync(&total, sc->row + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   PF_HIP_TRY(hipMemcpyAsync(hc, cnt.p, sizeof(hc), hipMemcpyDeviceToHost, s));
   PF_HIP_TRY(hipStreamSynchronize(s));
@@ -987,8 +1020,10 @@ pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipSt
   sc->n_hidden = (int64_t)hc[0];
   sc->n_overflow = (int64_t)hc[1];
   if (sc->n_overflow) {
-    set_error("pf_build_scene: " + std::to_string(sc->n_overflow) +
-              " cells exceeded the per-cell face/vertex capacity");
+    set_error("pf_build_scene: " + std::to_string(sc->n_overflow) + " of " + std::to_string(n) +
+              " cells exceeded a per-cell capacity (vertices " + std::to_string(hc[2]) + ", planes " +
+              std::to_string(hc[3]) + ", work " + std::to_string(hc[4]) + ", stack " + std::to_string(hc[5]) +
+              "; " + std::to_string(sc->n_big) + " cells took the high-degree pass)");
     return PF_ERR_OVERFLOW;
   }
   PF_HIP_TRY(hipMalloc((void**)&sc->col, sizeof(int32_t) * (total ? total : 1)));

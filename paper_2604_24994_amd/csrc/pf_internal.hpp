@@ -19,7 +19,11 @@ constexpr int LEAF = 64;           // sites per leaf of the build tree
 
 // Per-cell flags written by the build.
 constexpr int FLAG_EMPTY_POWER = 1;   // the power cell itself is empty
-constexpr int FLAG_OVERFLOW = 2;      // build capacity exceeded
+constexpr int FLAG_OVERFLOW = 2;      // build capacity exceeded (reason below)
+constexpr int FLAG_OVER_VERTS = 4;    //   vertex slots
+constexpr int FLAG_OVER_PLANES = 8;   //   live planes
+constexpr int FLAG_OVER_WORK = 16;    //   work limit
+constexpr int FLAG_OVER_STACK = 32;   //   traversal stack
 
 struct Scene {
   int64_t n = 0;
@@ -63,6 +67,20 @@ hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int bits,
 pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt,
                            hipStream_t s, Scene* sc);
 void free_scene(Scene* sc);
+
+// --- kernel timing (pf_api.hip) ----------------------------------------
+bool profiling();
+// Records an event pair around a launch; call prof_begin before and
+// prof_end after the launch on the same stream.
+int prof_begin(const char* name, hipStream_t s);
+void prof_end(int token, hipStream_t s);
+
+struct ProfScope {
+  int tok;
+  hipStream_t s;
+  ProfScope(const char* name, hipStream_t st) : tok(profiling() ? prof_begin(name, st) : -1), s(st) {}
+  ~ProfScope() { if (tok >= 0) prof_end(tok, s); }
+};
 
 }  // namespace pf
 

@@ -498,10 +498,14 @@ pf_status raster_view(const Scene& sc, const pf_camera& cam, float t_min, float*
   if (np) {
     k_tile_scatter<<<(unsigned)((np + 255) / 256), 256, 0, s>>>(ptile.p, pval.p, np, toff.p, fill.p, sorted.p);
     PF_HIP_TRY(hipGetLastError());
+    ProfScope ps("k_tile_sort", s);
     k_tile_sort<<<(unsigned)ntiles, SORT_THREADS, 0, s>>>(sorted.p, toff.p);
     PF_HIP_TRY(hipGetLastError());
   }
-  k_raster<<<(unsigned)ntiles, 256, 0, s>>>(v, scene_dev(sc), sorted.p, toff.p, t_min, rgba);
+  {
+    ProfScope ps("k_raster", s);
+    k_raster<<<(unsigned)ntiles, 256, 0, s>>>(v, scene_dev(sc), sorted.p, toff.p, t_min, rgba);
+  }
   PF_HIP_TRY(hipGetLastError());
   return PF_OK;
 }
@@ -526,6 +530,7 @@ pf_status trace_view(const Scene& sc, const pf_camera& cam, float t_min, int max
   PF_HIP_TRY(hipGetLastError());
   k_start_final<<<1, 256, 0, s>>>(pk.p, pi.p, nb, start.p);
   PF_HIP_TRY(hipGetLastError());
+  ProfScope ps("k_trace", s);
   k_trace<<<(unsigned)ntiles, 256, 0, s>>>(v, scene_dev(sc), start.p, t_min, max_steps, rgba, trunc_dev);
   PF_HIP_TRY(hipGetLastError());
   return PF_OK;

@@ -97,7 +97,7 @@ def _attributes(rng: np.random.Generator, n: int, k: int, m: int):
     rgb = rng.uniform(0.0, 1.0, size=(n, 3))
     nrm = rng.normal(0.0, 1.0, size=(n, 3))
     nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
-    tex = rng.normal(0.0, 0.1, size=(n, k, tex_width(m)))
+    tex = rng.standard_normal(size=(n, k, tex_width(m)), dtype=np.float32) * np.float32(0.1)
     return s, lam, rgb, nrm, tex
 
 
