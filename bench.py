@@ -5,9 +5,14 @@ Workload: 1,048,576 cells (80% on 64 flattened Gaussians, 20% in a background
 shell), 8 pinhole views of 1600x1066 on random poses on a sphere of radius 4,
 FP32, synthetic seeded inputs resident in HBM before timing starts.
 
-One step = rebuild the scene's adjacency (pf_build_scene) and rasterise the 8
-views (pf_render_raster); with ``--backward`` (once available) the step also
-takes the L2 loss against seeded noise targets and runs pf_backward.
+One step (default ``--mode train``) = one training iteration: rebuild the
+scene's adjacency from the current parameters (pf_build_scene), rasterise the
+8 views with a forward state (pf_render_raster), take the L2 loss against
+seeded U(0,1) noise targets in torch, and run the backward (pf_backward via
+torch.autograd) into zeroed gradient buffers.  ``--mode fwd`` times build +
+forward only.  The JSON line also carries forward-only and ray-walk
+throughput and, with ``--serve-seconds``, serving latency of a Poisson
+request stream (batched server vs one call per request) on the same scene.
 Prints ONE JSON line (see ``main``).
 """
 from __future__ import annotations
@@ -37,6 +42,9 @@ def parse():
     ap.add_argument("--views", type=int, default=8)
     ap.add_argument("--width", type=int, default=1600)
     ap.add_argument("--height", type=int, default=1066)
+    ap.add_argument("--mode", choices=["train", "fwd"], default="train")
+    ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--cpu-rays", type=int, default=4, help="oracle sample size for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
@@ -79,22 +87,30 @@ def main():
     sc = W.c3_scene(n=args.cells)
     cams = W.c3_cameras(n_views=args.views, width=args.width, height=args.height)
     log(f"inputs generated in {time.time() - t0:.1f}s")
-    params = pf.to_device_params(sc)
+    params = {k: v.requires_grad_(args.mode == "train") for k, v in pf.to_device_params(sc).items()}
     rays = sum(c.n_rays for c in cams)
     out = torch.empty(4 * rays, dtype=torch.float32, device="cuda")
+    tgt = torch.cat([torch.as_tensor(t, device="cuda").reshape(-1, 3) for t in W.targets(cams)])
     stream = torch.cuda.current_stream()
 
     def step():
         scene = pf.build_scene(params, sigma_scale=sc.sigma_scale, tau=sc.tau, stream=stream)
-        pf.render_raster(scene, cams, stream=stream, out=out)
+        if args.mode == "fwd":
+            pf.render_raster(scene, cams, stream=stream, out=out)
+            return scene
+        for v in params.values():
+            v.grad = None
+        imgs = pf.render_raster_diff(scene, cams)
+        rgb = torch.cat([im.reshape(-1, 4)[:, :3] for im in imgs])
+        loss = ((rgb - tgt) ** 2).mean()
+        loss.backward()
         return scene
 
     for i in range(args.warmup):
         s = step()
         torch.cuda.synchronize()
         if i == 0:
-            info = s.info()
-            log(f"scene: {info}")
+            log(f"scene: {s.info()}")
         s.destroy()
     log("warmup done")
 
@@ -112,14 +128,46 @@ def main():
     _lib.profile_enable(False)
     ms = ev0.elapsed_time(ev1) / args.steps
     value = rays / (ms * 1e-3) / 1e6
-    log(f"step {ms:.2f} ms, kernels: " + ", ".join(f"{k}={v[1] / max(1, v[0]):.3f}ms x{v[0]}" for k, v in prof.items()))
+    kms = {k: v[1] / args.steps for k, v in prof.items()}
+    log(f"step {ms:.2f} ms, kernel ms/step: " + ", ".join(f"{k}={v:.2f}" for k, v in sorted(kms.items(), key=lambda kv: -kv[1])))
 
-    dom = max(prof.items(), key=lambda kv: kv[1][1]) if prof else ("none", (1, 0.0))
-    roof = {"kernel": dom[0], "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": None, "traffic": None,
-            "avg_ms": dom[1][1] / max(1, dom[1][0])}
+    # side measurements on one built scene (not part of the timed step)
+    scene = pf.build_scene({k: v.detach() for k, v in params.items()}, sigma_scale=sc.sigma_scale, tau=sc.tau)
+    box = scene.info()
+    extra = {}
+    for name, fn in (("raster_fwd", lambda: pf.render_raster(scene, cams, out=out)),
+                     ("trace_fwd", lambda: pf.render_trace(scene, cams, out=out))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(2):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        extra[name + "_mrays_s"] = round(rays / (e0.elapsed_time(e1) / 2 * 1e-3) / 1e6, 2)
+    log(f"side: {extra}")
+    serving = None
+    if args.serve_seconds > 0:
+        from paper_2604_24994_amd import serve
+        reqs = W.request_stream(args.serve_rate, args.serve_seconds)
+        serving = {"rate_req_s": args.serve_rate, "seconds": args.serve_seconds}
+        for name, srv in (("batched", serve.Server({0: scene}, hbm_budget_bytes=16 << 30)),
+                          ("plain", serve.PlainServer({0: scene}))):
+            try:
+                st = serve.replay(srv, reqs)
+            finally:
+                srv.close()
+            serving[name] = {k: round(v, 3) for k, v in st.items()}
+            log(f"serving {name}: {serving[name]}")
+
+    dom_name, dom_ms = max(kms.items(), key=lambda kv: kv[1]) if kms else ("none", 0.0)
+    dom_launches = prof[dom_name][0] / args.steps if prof else 1
+    roof = {"kernel": dom_name, "bound": "alu", "achieved": None, "peak": None, "unit": None,
+            "frac": None, "traffic": None, "avg_ms": round(dom_ms / max(1, dom_launches), 4)}
     res = {
-        "metric": "Mrays/s fwd at 1M cells (raster, adjacency rebuilt every step)",
+        "metric": ("Mrays/s fwd+bwd at 1M cells (raster training step incl. adjacency rebuild)"
+                   if args.mode == "train" else "Mrays/s fwd at 1M cells (raster, adjacency rebuilt every step)"),
         "value": round(value, 3),
         "unit": "Mrays/s",
         "n_gpus": 1,
@@ -132,9 +180,12 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.cells} cells, {args.views} pinhole views {args.width}x{args.height}, "
-                               "build + raster forward",
+                               + ("build + raster fwd + L2 loss + bwd" if args.mode == "train" else "build + raster fwd"),
                    "cells": args.cells, "views": args.views, "width": args.width, "height": args.height},
-        "kernels_ms": {k: round(v[1] / max(1, v[0]), 4) for k, v in prof.items()},
+        "kernels_ms_per_step": {k: round(v, 3) for k, v in kms.items()},
+        "scene": {"hidden": box["n_hidden"], "faces": box["n_faces"]},
+        **extra,
+        "serving": serving,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

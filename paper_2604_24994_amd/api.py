@@ -176,3 +176,58 @@ def render_trace(scene: Scene, cams, t_min: float = 1e-6, max_steps: int = 4096,
                                      C.c_void_p(_stream_ptr(stream))))
     imgs = _split(buf, shapes)
     return (imgs, int(trunc.value)) if return_truncated else imgs
+
+
+class ForwardState:
+    """pf_fwd_state handle of a store-mode raster forward."""
+
+    def __init__(self, handle: int, scene: Scene, shapes):
+        self._h = C.c_void_p(handle)
+        self.scene = scene
+        self.shapes = shapes
+
+    @property
+    def handle(self) -> C.c_void_p:
+        if not self._h:
+            raise RuntimeError("forward state was released")
+        return self._h
+
+    def release(self):
+        if self._h:
+            L.load().pf_state_release(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+def render_raster_state(scene: Scene, cams, t_min: float = 1e-6, stream=None, out: Optional[torch.Tensor] = None):
+    """pf_render_raster with a forward state: (flat RGBA buffer, ForwardState)."""
+    arr, nc, shapes = _cams(cams)
+    buf = out if out is not None else _alloc_images(shapes, scene.params["p"].device)
+    opts = _opts(t_min, 0)
+    h = C.c_void_p()
+    L.check(L.load().pf_render_raster(scene.handle, arr, nc, C.byref(opts), C.c_void_p(buf.data_ptr()),
+                                      C.byref(h), C.c_void_p(_stream_ptr(stream))))
+    return buf, ForwardState(h.value, scene, shapes)
+
+
+def backward(scene: Scene, state: ForwardState, d_rgba: torch.Tensor, grads: Dict[str, torch.Tensor],
+             stream=None) -> None:
+    """pf_backward: adds dL/dparams into ``grads`` (dict of float32 device
+    tensors shaped like the parameters; missing keys are skipped)."""
+    d = d_rgba.contiguous()
+    if d.dtype != torch.float32:
+        raise TypeError("d_rgba must be float32")
+    g = L.PfGrads()
+    for f in PARAM_FIELDS:
+        t = grads.get(f)
+        if t is not None:
+            if not (t.is_contiguous() and t.dtype == torch.float32 and t.shape == scene.params[f].shape):
+                raise ValueError(f"gradient buffer {f} must be contiguous float32 shaped like the parameter")
+            setattr(g, f, t.data_ptr())
+    L.check(L.load().pf_backward(scene.handle, state.handle, C.c_void_p(d.data_ptr()), C.byref(g),
+                                 C.c_void_p(_stream_ptr(stream))))

@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "pf_backward.hpp"
 #include "pf_internal.hpp"
 #include "pf_render.hpp"
 
@@ -17,7 +18,19 @@ struct pf_scene {
 
 struct pf_fwd_state {
   const pf_scene* scene = nullptr;
+  pf::BwdState st;
+  std::vector<pf_camera> cams;
 };
+
+namespace {
+void free_state_mem(pf_fwd_state* s) {
+  void* ptrs[] = {s->st.rec.ri, s->st.rec.rf, s->st.rec.rt, s->st.rec.head, s->st.rec.counter, s->st.cams_dev};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  s->st.rec = pf::RecBuf{};
+  s->st.cams_dev = nullptr;
+}
+}  // namespace
 
 namespace pf {
 
@@ -157,19 +170,71 @@ pf_status pf_render_raster(pf_scene* scene, const pf_camera* cams, int32_t ncam,
   if (state) *state = nullptr;
   pf_status st = check_render(scene, cams, ncam, rgba, "pf_render_raster");
   if (st != PF_OK) return st;
-  if (state) {
-    pf::set_error("pf_render_raster: forward state is not available in this build");
-    return PF_ERR_UNSUPPORTED;
-  }
   const float t_min = (opts && opts->t_min > 0) ? opts->t_min : 1e-6f;
   hipStream_t s = (hipStream_t)stream;
-  int64_t off = 0;
-  for (int c = 0; c < ncam; ++c) {
-    st = pf::raster_view(scene->s, cams[c], t_min, rgba + off, s);
-    if (st != PF_OK) return st;
-    off += 4ll * cams[c].width * cams[c].height;
+  if (!state) return pf::raster_views(scene->s, cams, ncam, t_min, rgba, s);
+  if (ncam >= 4096) return invalid("pf_render_raster: at most 4095 cameras per call with a forward state");
+  pf_fwd_state* fs = new (std::nothrow) pf_fwd_state();
+  if (!fs) {
+    pf::set_error("pf_render_raster: host allocation failed");
+    return PF_ERR_OOM;
   }
-  return PF_OK;
+  fs->scene = scene;
+  fs->cams.assign(cams, cams + ncam);
+  int64_t npix = 0;
+  for (int c = 0; c < ncam; ++c) npix += (int64_t)cams[c].width * cams[c].height;
+  fs->st.npix = npix;
+  auto fail = [&](pf_status e) {
+    free_state_mem(fs);
+    delete fs;
+    return e;
+  };
+  hipError_t e = hipMalloc((void**)&fs->st.cams_dev, sizeof(pf_camera) * ncam);
+  if (e == hipSuccess) e = hipMemcpyAsync(fs->st.cams_dev, cams, sizeof(pf_camera) * ncam, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMalloc((void**)&fs->st.rec.head, sizeof(int32_t) * npix);
+  if (e == hipSuccess) e = hipMalloc((void**)&fs->st.rec.counter, sizeof(unsigned long long));
+  if (e != hipSuccess) {
+    pf::set_error(std::string("pf_render_raster: ") + hipGetErrorString(e));
+    return fail(e == hipErrorOutOfMemory ? PF_ERR_OOM : PF_ERR_HIP);
+  }
+  // record pool sized from the last forward of this scene; a pass that runs
+  // out of room is repeated once with the exact size
+  int64_t cap = (int64_t)(scene->s.rec_per_pixel * (double)npix) + 1024;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    fs->st.rec.cap = cap;
+    e = hipMalloc((void**)&fs->st.rec.ri, sizeof(int4) * cap);
+    if (e == hipSuccess) e = hipMalloc((void**)&fs->st.rec.rf, sizeof(float4) * cap);
+    if (e == hipSuccess) e = hipMalloc((void**)&fs->st.rec.rt, sizeof(float) * cap);
+    if (e == hipSuccess) e = hipMemsetAsync(fs->st.rec.counter, 0, sizeof(unsigned long long), s);
+    if (e != hipSuccess) {
+      pf::set_error(std::string("pf_render_raster: record pool: ") + hipGetErrorString(e));
+      return fail(e == hipErrorOutOfMemory ? PF_ERR_OOM : PF_ERR_HIP);
+    }
+    st = pf::raster_views(scene->s, cams, ncam, t_min, rgba, s, &fs->st.rec);
+    if (st != PF_OK) return fail(st);
+    unsigned long long used = 0;
+    e = hipMemcpyAsync(&used, fs->st.rec.counter, sizeof(used), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      pf::set_error(std::string("pf_render_raster: ") + hipGetErrorString(e));
+      return fail(PF_ERR_HIP);
+    }
+    scene->s.rec_per_pixel = 1.05 * (double)used / (double)npix;
+    if ((int64_t)used <= cap) {
+      fs->st.nrec = (int64_t)used;
+      *state = fs;
+      return PF_OK;
+    }
+    (void)hipFree(fs->st.rec.ri);
+    (void)hipFree(fs->st.rec.rf);
+    (void)hipFree(fs->st.rec.rt);
+    fs->st.rec.ri = nullptr;
+    fs->st.rec.rf = nullptr;
+    fs->st.rec.rt = nullptr;
+    cap = (int64_t)used + 1024;
+  }
+  pf::set_error("pf_render_raster: record pool sizing failed");
+  return fail(PF_ERR_HIP);
 }
 
 pf_status pf_render_trace(pf_scene* scene, const pf_camera* cams, int32_t ncam, const pf_render_opts* opts,
@@ -215,13 +280,16 @@ pf_status pf_render_trace(pf_scene* scene, const pf_camera* cams, int32_t ncam, 
 
 pf_status pf_backward(pf_scene* scene, const pf_fwd_state* state, const float* d_rgba, const pf_grads* grads,
                       void* stream) {
-  (void)stream;
   if (!scene || !state || !d_rgba || !grads) return invalid("pf_backward: NULL argument");
-  pf::set_error("pf_backward: not available in this build");
-  return PF_ERR_UNSUPPORTED;
+  if (state->scene != scene) return invalid("pf_backward: the state belongs to another scene");
+  return pf::backward_impl(scene->s, state->st, d_rgba, *grads, (hipStream_t)stream);
 }
 
-void pf_state_release(pf_fwd_state* state) { delete state; }
+void pf_state_release(pf_fwd_state* state) {
+  if (!state) return;
+  free_state_mem(state);
+  delete state;
+}
 
 pf_status pf_profile_enable(int32_t on) {
   pf::g_prof_on.store(on != 0);

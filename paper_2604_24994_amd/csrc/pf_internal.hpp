@@ -41,9 +41,24 @@ struct Scene {
   int32_t* col = nullptr;          // [E] neighbour, or -1-f for box face f
   float4* plane = nullptr;         // [E] (m, h): (x - p_i).m <= h
   int64_t n_faces = 0, n_hidden = 0, n_overflow = 0, n_big = 0;
+  double rec_per_pixel = 12.0;     // record-pool sizing hint for store mode
 };
 
-struct ViewOut;  // forward-state record sets (render)
+// Contribution records written by the store-mode forward: one per (pixel,
+// cell) with alpha > 0, chained per pixel back to front through `prev`.
+//   ri = (cell, pixel within its view, prev record or -1,
+//         view << 20 | (bind0 + 2) << 10 | (bind1 + 2))
+//   rf = (alpha, c.r, c.g, c.b); after the per-pixel pass (dL/dalpha, dL/dc)
+//   rt = transmittance in front of the contribution
+// bind: -1 sphere, -2 ray start, f >= 0 raster face index of the cell.
+struct RecBuf {
+  int4* ri = nullptr;
+  float4* rf = nullptr;
+  float* rt = nullptr;
+  int32_t* head = nullptr;            // [pixels of all views] last record or -1
+  unsigned long long* counter = nullptr;
+  int64_t cap = 0;
+};
 
 // Thread-local error text.
 void set_error(const std::string& msg);

@@ -19,6 +19,7 @@
 #include "pf_render.hpp"
 #include "pf_shade.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -114,6 +115,15 @@ struct ViewArgs {
   int tiles_x, tiles_y;
 };
 
+// One camera of a batched raster call: its tiles are numbered from
+// tile_base and its pixels from pix_base across the whole batch.
+struct ViewDev {
+  ViewArgs v;
+  long long tile_base;
+  long long pix_base;
+  int view_id;   // camera index within the call
+};
+
 __device__ inline bool cell_rect(const ViewArgs& v, const float4 g, float rho, int& x0, int& x1, int& y0, int& y1) {
   if (!(rho >= 0.0f)) return false;
   const float* m = v.cam.c2w;
@@ -124,34 +134,39 @@ __device__ inline bool cell_rect(const ViewArgs& v, const float4 g, float rho, i
   return ball_rect(v.cam, X, Y, Z, (double)rho * (1.0 + 1e-5) + 1e-7, v.tiles_x, v.tiles_y, x0, x1, y0, y1);
 }
 
-__global__ void k_view_count(ViewArgs v, const float4* __restrict__ geo, const float* __restrict__ cull,
-                             const float* __restrict__ power, int64_t n, uint32_t* __restrict__ cnt,
-                             uint32_t* __restrict__ key) {
+// blockIdx.y = view; one thread per (view, cell).
+__global__ void k_view_count(const ViewDev* __restrict__ views, const float4* __restrict__ geo,
+                             const float* __restrict__ cull, const float* __restrict__ power, int64_t n,
+                             uint32_t* __restrict__ cnt, uint32_t* __restrict__ key) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const ViewArgs& v = views[blockIdx.y].v;
+  const int64_t o = (int64_t)blockIdx.y * n + i;
   const float4 g = geo[i];
   int x0, x1, y0, y1;
   uint32_t c = 0;
   if (cell_rect(v, g, cull[i], x0, x1, y0, y1)) c = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
-  cnt[i] = c;
+  cnt[o] = c;
   const float* m = v.cam.c2w;
   const double ex = (double)m[3] - g.x, ey = (double)m[7] - g.y, ez = (double)m[11] - g.z;
-  key[i] = order_key((float)(ex * ex + ey * ey + ez * ez - (double)power[i]));
+  key[o] = order_key((float)(ex * ex + ey * ey + ez * ez - (double)power[i]));
 }
 
-__global__ void k_view_emit(ViewArgs v, const float4* __restrict__ geo, const float* __restrict__ cull,
-                            int64_t n, const uint32_t* __restrict__ off, const uint32_t* __restrict__ key,
-                            uint32_t* __restrict__ ptile, unsigned long long* __restrict__ pval,
-                            uint32_t* __restrict__ tile_cnt) {
+__global__ void k_view_emit(const ViewDev* __restrict__ views, const float4* __restrict__ geo,
+                            const float* __restrict__ cull, int64_t n, const uint32_t* __restrict__ off,
+                            const uint32_t* __restrict__ key, uint32_t* __restrict__ ptile,
+                            unsigned long long* __restrict__ pval, uint32_t* __restrict__ tile_cnt) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const ViewDev& vd = views[blockIdx.y];
+  const int64_t oi = (int64_t)blockIdx.y * n + i;
   int x0, x1, y0, y1;
-  if (!cell_rect(v, geo[i], cull[i], x0, x1, y0, y1)) return;
-  uint32_t o = off[i];
-  const unsigned long long val = ((unsigned long long)key[i] << 32) | (uint32_t)i;
+  if (!cell_rect(vd.v, geo[i], cull[i], x0, x1, y0, y1)) return;
+  uint32_t o = off[oi];
+  const unsigned long long val = ((unsigned long long)key[oi] << 32) | (uint32_t)i;
   for (int ty = y0; ty <= y1; ++ty)
     for (int tx = x0; tx <= x1; ++tx) {
-      const uint32_t t = (uint32_t)(ty * v.tiles_x + tx);
+      const uint32_t t = (uint32_t)(vd.tile_base + ty * vd.v.tiles_x + tx);
       ptile[o] = t;
       pval[o] = val;
       atomicAdd(&tile_cnt[t], 1u);
@@ -249,28 +264,83 @@ __device__ inline void contribute(const SceneDev& S, const RayD& R, int ci, bool
   }
 }
 
-__device__ inline void tile_pixel(int tiles_x, int& px, int& py) {
-  const int tile = blockIdx.x;
+__device__ inline void tile_pixel(int tiles_x, int& px, int& py, int tile = -1) {
+  if (tile < 0) tile = blockIdx.x;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   px = tx * TILE + (w & 1) * 8 + (lane & 7);
   py = ty * TILE + (w >> 1) * 8 + (lane >> 3);
 }
 
-__global__ void __launch_bounds__(256) k_raster(ViewArgs v, SceneDev S, const unsigned long long* __restrict__ list,
+template <bool STORE>
+__global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ views, int nview, SceneDev S,
+                                                const unsigned long long* __restrict__ list,
                                                 const uint32_t* __restrict__ tile_off, float t_min,
-                                                float* __restrict__ rgba) {
+                                                float* __restrict__ rgba_all, RecBuf rec) {
+  // view of this tile: the last one whose tiles start at or before it
+  int lo = 0, hi = nview - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (views[mid].tile_base <= (long long)blockIdx.x) lo = mid; else hi = mid - 1;
+  }
+  const ViewDev& vd = views[lo];
+  const int view = vd.view_id;
+  const ViewArgs& v = vd.v;
+  const int64_t pix_base = vd.pix_base;
+  float* rgba = rgba_all + 4 * pix_base;
   int px, py;
-  tile_pixel(v.tiles_x, px, py);
+  tile_pixel(v.tiles_x, px, py, (int)(blockIdx.x - vd.tile_base));
   const bool inside = px < v.cam.width && py < v.cam.height;
   const RayD R = make_ray(v.cam, px + 0.5, py + 0.5);
   bool live = inside && R.valid;
   float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
+  int head = -1;
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int pix = py * v.cam.width + px;
   const uint32_t e0 = tile_off[blockIdx.x], e1 = tile_off[blockIdx.x + 1];
   for (uint32_t e = e0; e < e1; ++e) {
     if (!__any(live)) break;
     const int ci = __builtin_amdgcn_readfirstlane((int)(uint32_t)list[e]);
-    contribute(S, R, ci, live, T, cr, cg, cb);
+    if constexpr (!STORE) {
+      contribute(S, R, ci, live, T, cr, cg, cb);
+    } else {
+      const float4 g = S.geo[ci];
+      const float rho = S.cull[ci];
+      const Local L = make_local(R, g.x, g.y, g.z);
+      const bool hit = live && (rho >= 0.0f) && (L.qq < (double)rho * (double)rho);
+      if (!__any(hit)) continue;
+      const float* tx = S.tex + (int64_t)ci * (KD * TEXW);
+      Piece P;
+      P.alpha = 0.0f;
+      float r = 0.0f, gg = 0.0f, b = 0.0f;
+      if (hit) {
+        const int r0 = S.row[ci];
+        P = piece_geometry(R, L, g.w, S.plane + r0, S.nrast[ci], S.nrm[ci], tx, S.tau);
+        if (P.alpha > 0.0f) radiance(tx, S.rgb + 3 * (int64_t)ci, P.ux, P.uy, R.fx, R.fy, R.fz, S.tau, r, gg, b);
+      }
+      const bool contrib = hit && P.alpha > 0.0f;
+      const uint64_t m = __ballot(contrib);
+      if (m) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(rec.counter, (unsigned long long)__popcll(m));
+        base = __shfl(base, 0, 64);
+        if (contrib) {
+          const long long slot = (long long)base + __popcll(m & lt);
+          if (slot < rec.cap) {
+            rec.ri[slot] = make_int4(ci, pix, head, (view << 20) | ((P.bind0 + 2) << 10) | (P.bind1 + 2));
+            rec.rf[slot] = make_float4(P.alpha, r, gg, b);
+            rec.rt[slot] = T;
+            head = (int)slot;
+          }
+          const float wgt = T * P.alpha;
+          cr += wgt * r;
+          cg += wgt * gg;
+          cb += wgt * b;
+          T *= (1.0f - P.alpha);
+        }
+      }
+    }
     live = live && (T >= t_min);
   }
   if (inside) {
@@ -279,6 +349,7 @@ __global__ void __launch_bounds__(256) k_raster(ViewArgs v, SceneDev S, const un
     o[1] = cg;
     o[2] = cb;
     o[3] = 1.0f - T;
+    if constexpr (STORE) rec.head[pix_base + pix] = head;
   }
 }
 
@@ -463,50 +534,79 @@ bool camera_ok(const pf_camera& c, std::string* why) {
   return true;
 }
 
-pf_status raster_view(const Scene& sc, const pf_camera& cam, float t_min, float* rgba, hipStream_t s) {
+pf_status raster_views(const Scene& sc, const pf_camera* cams, int ncam, float t_min, float* rgba, hipStream_t s,
+                       const RecBuf* rec) {
   const int64_t n = sc.n;
-  ViewArgs v;
-  v.cam = cam;
-  v.tiles_x = (cam.width + TILE - 1) / TILE;
-  v.tiles_y = (cam.height + TILE - 1) / TILE;
-  const int64_t ntiles = (int64_t)v.tiles_x * v.tiles_y;
-  const unsigned g = (unsigned)((n + 255) / 256);
-  Buf<uint32_t> cnt(s), key(s), off(s), tcnt(s), toff(s), fill(s);
-  PF_HIP_TRY(cnt.alloc(n + 1));
-  PF_HIP_TRY(key.alloc(n));
-  PF_HIP_TRY(off.alloc(n + 1));
-  PF_HIP_TRY(tcnt.alloc(ntiles + 1));
-  PF_HIP_TRY(toff.alloc(ntiles + 1));
-  PF_HIP_TRY(fill.alloc(ntiles));
-  k_view_count<<<g, 256, 0, s>>>(v, sc.geo, sc.cull, sc.prm.power, n, cnt.p, key.p);
-  PF_HIP_TRY(hipGetLastError());
-  PF_HIP_TRY(hipMemsetAsync(cnt.p + n, 0, sizeof(uint32_t), s));
-  PF_HIP_TRY(exclusive_scan_u32(cnt.p, off.p, n + 1, nullptr, s));
-  uint32_t np = 0;
-  PF_HIP_TRY(hipMemcpyAsync(&np, off.p + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  PF_HIP_TRY(hipStreamSynchronize(s));
-  Buf<uint32_t> ptile(s);
-  Buf<unsigned long long> pval(s), sorted(s);
-  PF_HIP_TRY(ptile.alloc(np));
-  PF_HIP_TRY(pval.alloc(np));
-  PF_HIP_TRY(sorted.alloc(np));
-  PF_HIP_TRY(hipMemsetAsync(tcnt.p, 0, sizeof(uint32_t) * (ntiles + 1), s));
-  PF_HIP_TRY(hipMemsetAsync(fill.p, 0, sizeof(uint32_t) * ntiles, s));
-  k_view_emit<<<g, 256, 0, s>>>(v, sc.geo, sc.cull, n, off.p, key.p, ptile.p, pval.p, tcnt.p);
-  PF_HIP_TRY(hipGetLastError());
-  PF_HIP_TRY(exclusive_scan_u32(tcnt.p, toff.p, ntiles + 1, nullptr, s));
-  if (np) {
-    k_tile_scatter<<<(unsigned)((np + 255) / 256), 256, 0, s>>>(ptile.p, pval.p, np, toff.p, fill.p, sorted.p);
+  // views are processed in groups so that the per-(view, cell) scan fits 32 bits
+  const int group = (int)std::max<int64_t>(1, std::min<int64_t>(ncam, ((int64_t)1 << 28) / n));
+  int64_t pix_done = 0;
+  for (int c0 = 0; c0 < ncam; c0 += group) {
+    const int nv = std::min(group, ncam - c0);
+    std::vector<ViewDev> hv(nv);
+    int64_t ntiles = 0;
+    for (int v = 0; v < nv; ++v) {
+      const pf_camera& cam = cams[c0 + v];
+      hv[v].v.cam = cam;
+      hv[v].v.tiles_x = (cam.width + TILE - 1) / TILE;
+      hv[v].v.tiles_y = (cam.height + TILE - 1) / TILE;
+      hv[v].tile_base = ntiles;
+      hv[v].pix_base = pix_done;
+      hv[v].view_id = c0 + v;
+      ntiles += (int64_t)hv[v].v.tiles_x * hv[v].v.tiles_y;
+      pix_done += (int64_t)cam.width * cam.height;
+    }
+    const int64_t nvc = (int64_t)nv * n;
+    Buf<ViewDev> views(s);
+    Buf<uint32_t> cnt(s), key(s), off(s), tcnt(s), toff(s), fill(s);
+    PF_HIP_TRY(views.alloc(nv));
+    PF_HIP_TRY(hipMemcpyAsync(views.p, hv.data(), sizeof(ViewDev) * nv, hipMemcpyHostToDevice, s));
+    PF_HIP_TRY(cnt.alloc(nvc + 1));
+    PF_HIP_TRY(key.alloc(nvc));
+    PF_HIP_TRY(off.alloc(nvc + 1));
+    PF_HIP_TRY(tcnt.alloc(ntiles + 1));
+    PF_HIP_TRY(toff.alloc(ntiles + 1));
+    PF_HIP_TRY(fill.alloc(ntiles));
+    const dim3 g((unsigned)((n + 255) / 256), (unsigned)nv);
+    k_view_count<<<g, 256, 0, s>>>(views.p, sc.geo, sc.cull, sc.prm.power, n, cnt.p, key.p);
     PF_HIP_TRY(hipGetLastError());
-    ProfScope ps("k_tile_sort", s);
-    k_tile_sort<<<(unsigned)ntiles, SORT_THREADS, 0, s>>>(sorted.p, toff.p);
+    PF_HIP_TRY(hipMemsetAsync(cnt.p + nvc, 0, sizeof(uint32_t), s));
+    PF_HIP_TRY(exclusive_scan_u32(cnt.p, off.p, nvc + 1, nullptr, s));
+    uint32_t np = 0;
+    PF_HIP_TRY(hipMemcpyAsync(&np, off.p + nvc, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    PF_HIP_TRY(hipStreamSynchronize(s));
+    Buf<uint32_t> ptile(s);
+    Buf<unsigned long long> pval(s), sorted(s);
+    PF_HIP_TRY(ptile.alloc(np));
+    PF_HIP_TRY(pval.alloc(np));
+    PF_HIP_TRY(sorted.alloc(np));
+    PF_HIP_TRY(hipMemsetAsync(tcnt.p, 0, sizeof(uint32_t) * (ntiles + 1), s));
+    PF_HIP_TRY(hipMemsetAsync(fill.p, 0, sizeof(uint32_t) * ntiles, s));
+    {
+      ProfScope ps("k_view_emit", s);
+      k_view_emit<<<g, 256, 0, s>>>(views.p, sc.geo, sc.cull, n, off.p, key.p, ptile.p, pval.p, tcnt.p);
+    }
+    PF_HIP_TRY(hipGetLastError());
+    PF_HIP_TRY(exclusive_scan_u32(tcnt.p, toff.p, ntiles + 1, nullptr, s));
+    if (np) {
+      k_tile_scatter<<<(unsigned)((np + 255) / 256), 256, 0, s>>>(ptile.p, pval.p, np, toff.p, fill.p, sorted.p);
+      PF_HIP_TRY(hipGetLastError());
+      ProfScope ps("k_tile_sort", s);
+      k_tile_sort<<<(unsigned)ntiles, SORT_THREADS, 0, s>>>(sorted.p, toff.p);
+      PF_HIP_TRY(hipGetLastError());
+    }
+    {
+      ProfScope ps(rec ? "k_raster_store" : "k_raster", s);
+      if (rec) {
+        RecBuf rb = *rec;
+        k_raster<true><<<(unsigned)ntiles, 256, 0, s>>>(views.p, nv, scene_dev(sc), sorted.p, toff.p, t_min, rgba,
+                                                        rb);
+      } else {
+        k_raster<false><<<(unsigned)ntiles, 256, 0, s>>>(views.p, nv, scene_dev(sc), sorted.p, toff.p, t_min, rgba,
+                                                         RecBuf{});
+      }
+    }
     PF_HIP_TRY(hipGetLastError());
   }
-  {
-    ProfScope ps("k_raster", s);
-    k_raster<<<(unsigned)ntiles, 256, 0, s>>>(v, scene_dev(sc), sorted.p, toff.p, t_min, rgba);
-  }
-  PF_HIP_TRY(hipGetLastError());
   return PF_OK;
 }
 

@@ -8,7 +8,10 @@
 namespace pf {
 
 bool camera_ok(const pf_camera& c, std::string* why);
-pf_status raster_view(const Scene& sc, const pf_camera& cam, float t_min, float* rgba, hipStream_t s);
+// All cameras of a call in one batch; images back to back in rgba.
+// rec: store-mode records (null: plain forward).
+pf_status raster_views(const Scene& sc, const pf_camera* cams, int ncam, float t_min, float* rgba, hipStream_t s,
+                       const RecBuf* rec = nullptr);
 pf_status trace_view(const Scene& sc, const pf_camera& cam, float t_min, int max_steps, float* rgba,
                      unsigned long long* trunc_dev, hipStream_t s);
 

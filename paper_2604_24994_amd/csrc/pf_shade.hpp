@@ -72,7 +72,8 @@ struct Local {
   float qx, qy, qz;
   float beta;
   double qq;
-  double b;   // float64 beta
+  double b;          // float64 beta
+  double dqx, dqy, dqz;  // float64 q
 };
 
 __device__ inline Local make_local(const RayD& R, float px, float py, float pz) {
@@ -83,6 +84,9 @@ __device__ inline Local make_local(const RayD& R, float px, float py, float pz) 
   L.qx = (float)qx;
   L.qy = (float)qy;
   L.qz = (float)qz;
+  L.dqx = qx;
+  L.dqy = qy;
+  L.dqz = qz;
   L.qq = qx * qx + qy * qy + qz * qz;
   L.b = b;
   L.beta = (float)b;
