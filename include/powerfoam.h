@@ -174,6 +174,10 @@ pf_status pf_backward(pf_scene* scene, const pf_fwd_state* state, const float* d
 
 void pf_state_release(pf_fwd_state* state);
 
+/* Number of contribution records (pixel-cell pairs with alpha > 0) and of
+   pixels in a forward state (host outputs). */
+pf_status pf_state_info(const pf_fwd_state* state, int64_t* n_records, int64_t* n_pixels);
+
 /* Kernel timing for measurement.  While enabled (on != 0), every kernel the
    library launches is bracketed by HIP events on its stream; pf_profile_read
    waits for those events and returns, per kernel name, the launch count and

@@ -12,7 +12,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "OOM", 3: "HIP", 4: "UNSUPPORTED", 5: 
 
 EXPORTS = ("pf_build_scene", "pf_scene_info_get", "pf_scene_adjacency", "pf_scene_destroy",
            "pf_render_raster", "pf_render_trace", "pf_backward", "pf_state_release", "pf_last_error",
-           "pf_profile_enable", "pf_profile_read")
+           "pf_profile_enable", "pf_profile_read", "pf_state_info")
 
 
 class PfParams(C.Structure):
@@ -77,6 +77,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.pf_backward.argtypes = [vp, vp, vp, C.POINTER(PfGrads), vp]
     lib.pf_state_release.argtypes = [vp]
     lib.pf_state_release.restype = None
+    lib.pf_state_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
     lib.pf_profile_enable.argtypes = [i32]
     lib.pf_profile_read.argtypes = [C.POINTER(PfProfileEntry), i32, C.POINTER(i32)]
     lib.pf_last_error.argtypes = []

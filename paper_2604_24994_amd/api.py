@@ -192,6 +192,11 @@ class ForwardState:
             raise RuntimeError("forward state was released")
         return self._h
 
+    def info(self) -> dict:
+        nr, npx = C.c_int64(0), C.c_int64(0)
+        L.check(L.load().pf_state_info(self.handle, C.byref(nr), C.byref(npx)))
+        return {"records": int(nr.value), "pixels": int(npx.value)}
+
     def release(self):
         if self._h:
             L.load().pf_state_release(self._h)

@@ -9,6 +9,10 @@ import torch
 from .api import PARAM_FIELDS, Scene, backward, render_raster_state
 
 
+# record count of the most recent differentiable forward (for measurement)
+LAST_FORWARD = {"records": 0}
+
+
 class _RasterFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, scene: Scene, cams, t_min: float, *params):
@@ -16,6 +20,7 @@ class _RasterFn(torch.autograd.Function):
             if t.data_ptr() != scene.params[f].data_ptr():
                 raise ValueError(f"parameter {f} is not the tensor the scene was built from")
         buf, state = render_raster_state(scene, cams, t_min=t_min)
+        LAST_FORWARD["records"] = state.info()["records"]
         ctx.scene = scene
         ctx.state = state
         return buf

@@ -291,6 +291,13 @@ void pf_state_release(pf_fwd_state* state) {
   delete state;
 }
 
+pf_status pf_state_info(const pf_fwd_state* state, int64_t* n_records, int64_t* n_pixels) {
+  if (!state || !n_records || !n_pixels) return invalid("pf_state_info: NULL argument");
+  *n_records = state->st.nrec;
+  *n_pixels = state->st.npix;
+  return PF_OK;
+}
+
 pf_status pf_profile_enable(int32_t on) {
   pf::g_prof_on.store(on != 0);
   return PF_OK;
