@@ -1,4 +1,5 @@
 // C ABI entry points: argument checks, error text, handle lifetime.
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -16,6 +17,12 @@ struct pf_scene {
   pf::Scene s;
 };
 
+namespace {
+// process-wide record-pool sizing hints (records / segment slots per pixel)
+std::atomic<double> g_rec_hint{16.0};
+std::atomic<double> g_seg_hint{4.0};
+}  // namespace
+
 struct pf_fwd_state {
   const pf_scene* scene = nullptr;
   pf::BwdState st;
@@ -24,7 +31,8 @@ struct pf_fwd_state {
 
 namespace {
 void free_state_mem(pf_fwd_state* s) {
-  void* ptrs[] = {s->st.rec.ri, s->st.rec.rf, s->st.rec.rt, s->st.rec.head, s->st.rec.counter, s->st.cams_dev};
+  void* ptrs[] = {s->st.rec.ri,      s->st.rec.rf,  s->st.rec.rt,   s->st.rec.head,
+                  s->st.rec.counter, s->st.rec.seg, s->st.cams_dev};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   s->st.rec = pf::RecBuf{};
@@ -192,46 +200,66 @@ pf_status pf_render_raster(pf_scene* scene, const pf_camera* cams, int32_t ncam,
   hipError_t e = hipMalloc((void**)&fs->st.cams_dev, sizeof(pf_camera) * ncam);
   if (e == hipSuccess) e = hipMemcpyAsync(fs->st.cams_dev, cams, sizeof(pf_camera) * ncam, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMalloc((void**)&fs->st.rec.head, sizeof(int32_t) * npix);
-  if (e == hipSuccess) e = hipMalloc((void**)&fs->st.rec.counter, sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMalloc((void**)&fs->st.rec.counter, 3 * sizeof(unsigned long long));
   if (e != hipSuccess) {
     pf::set_error(std::string("pf_render_raster: ") + hipGetErrorString(e));
     return fail(e == hipErrorOutOfMemory ? PF_ERR_OOM : PF_ERR_HIP);
   }
-  // record pool sized from the last forward of this scene; a pass that runs
-  // out of room is repeated once with the exact size
-  int64_t cap = (int64_t)(scene->s.rec_per_pixel * (double)npix) + 1024;
+  // record pool and segment list sized from the last store-mode forward of
+  // this scene (else of any scene in the process); a pass that runs out of
+  // room is repeated once with the exact sizes
+  const bool seen = scene->s.rec_per_pixel > 0.0;
+  const double rpp = seen ? scene->s.rec_per_pixel : g_rec_hint.load();
+  const double spp = seen ? scene->s.seg_per_pixel : g_seg_hint.load();
+  int64_t cap = (int64_t)(rpp * (double)npix) + 4096;
+  int64_t seg_cap = (int64_t)(spp * (double)npix) + 4096;
   for (int attempt = 0; attempt < 2; ++attempt) {
     fs->st.rec.cap = cap;
+    fs->st.rec.seg_cap = seg_cap;
     e = hipMalloc((void**)&fs->st.rec.ri, sizeof(int4) * cap);
     if (e == hipSuccess) e = hipMalloc((void**)&fs->st.rec.rf, sizeof(float4) * cap);
     if (e == hipSuccess) e = hipMalloc((void**)&fs->st.rec.rt, sizeof(float) * cap);
-    if (e == hipSuccess) e = hipMemsetAsync(fs->st.rec.counter, 0, sizeof(unsigned long long), s);
+    if (e == hipSuccess) e = hipMalloc((void**)&fs->st.rec.seg, sizeof(int4) * seg_cap);
+    if (e == hipSuccess) e = hipMemsetAsync(fs->st.rec.counter, 0, 3 * sizeof(unsigned long long), s);
     if (e != hipSuccess) {
       pf::set_error(std::string("pf_render_raster: record pool: ") + hipGetErrorString(e));
       return fail(e == hipErrorOutOfMemory ? PF_ERR_OOM : PF_ERR_HIP);
     }
     st = pf::raster_views(scene->s, cams, ncam, t_min, rgba, s, &fs->st.rec);
     if (st != PF_OK) return fail(st);
-    unsigned long long used = 0;
-    e = hipMemcpyAsync(&used, fs->st.rec.counter, sizeof(used), hipMemcpyDeviceToHost, s);
+    unsigned long long used[3] = {0, 0, 0};
+    e = hipMemcpyAsync(used, fs->st.rec.counter, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && (int64_t)used[0] <= cap && (int64_t)used[1] <= seg_cap) {
+      st = pf::seg_record_total(fs->st.rec.seg, (int64_t)used[1], fs->st.rec.counter + 2, s);
+      if (st != PF_OK) return fail(st);
+      e = hipMemcpyAsync(used + 2, fs->st.rec.counter + 2, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
       pf::set_error(std::string("pf_render_raster: ") + hipGetErrorString(e));
       return fail(PF_ERR_HIP);
     }
-    scene->s.rec_per_pixel = 1.05 * (double)used / (double)npix;
-    if ((int64_t)used <= cap) {
-      fs->st.nrec = (int64_t)used;
+    if (used[0] > (unsigned long long)INT32_MAX)
+      return fail(invalid("pf_render_raster: more than 2^31 - 1 contributions in one call; render fewer views"));
+    scene->s.rec_per_pixel = 1.05 * (double)used[0] / (double)npix;
+    scene->s.seg_per_pixel = 1.05 * (double)used[1] / (double)npix;
+    g_rec_hint.store(scene->s.rec_per_pixel);
+    g_seg_hint.store(scene->s.seg_per_pixel);
+    if ((int64_t)used[0] <= cap && (int64_t)used[1] <= seg_cap) {
+      fs->st.nrec = (int64_t)used[2];
+      fs->st.nseg = (int64_t)used[1];
       *state = fs;
       return PF_OK;
     }
-    (void)hipFree(fs->st.rec.ri);
-    (void)hipFree(fs->st.rec.rf);
-    (void)hipFree(fs->st.rec.rt);
+    void* pool[] = {fs->st.rec.ri, fs->st.rec.rf, fs->st.rec.rt, fs->st.rec.seg};
+    for (void* q : pool) (void)hipFree(q);
     fs->st.rec.ri = nullptr;
     fs->st.rec.rf = nullptr;
     fs->st.rec.rt = nullptr;
-    cap = (int64_t)used + 1024;
+    fs->st.rec.seg = nullptr;
+    cap = std::max(cap, (int64_t)used[0] + 4096);
+    seg_cap = std::max(seg_cap, (int64_t)used[1] + 4096);
   }
   pf::set_error("pf_render_raster: record pool sizing failed");
   return fail(PF_ERR_HIP);

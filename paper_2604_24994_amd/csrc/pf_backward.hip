@@ -7,17 +7,21 @@
 //                   Cb_{k} = a_k c_k + (1 - a_k) Cb_{k+1},  Ab likewise,
 //                 dL/da_k = T_k (gC.(c_k - Cb_{k+1}) + gA (1 - Ab_{k+1})),
 //                 dL/dc_k = T_k a_k gC                      (Sec. 3.1 sum)
-//   k_rec_hist /  counting sort of the records by cell
-//   k_rec_scatter
-//   k_bwd_cell    one workgroup per chunk of a cell's records: re-derives the
-//                 piece (bounded interval from its binding sphere / face /
-//                 ray start, dipole split with displacement, radiance) and
-//                 applies the chain rule by hand (reverse order of the
-//                 forward); per detail site the 51 texture gradients are
-//                 summed over the wave and added into LDS, neighbour
-//                 gradients through binding faces are gathered per face in
-//                 LDS, and everything is flushed with one global atomic per
-//                 (chunk, parameter).
+//   k_seg_hist /  records grouped by cell through the forward's segment list
+//   k_seg_scatter (one atomic per segment of <= 64 contiguous records)
+//   k_bwd_cell    one wave per chunk of a cell's records, 64 records at a
+//                 time.  Lane = record: re-derives the piece (bounded
+//                 interval from its binding sphere / face / ray start,
+//                 dipole split with displacement, radiance) and applies the
+//                 chain rule by hand, in reverse order of the forward; the
+//                 per-record sums (cell parameters, detail-site positions and
+//                 displacements) are reduced over the wave with DPP.  Lane =
+//                 (detail site k, axis m): the 6 Spherical-Voronoi gradients
+//                 of (k, m) accumulate in registers over the chunk, reading
+//                 each record's direction, dL/dc and per-site softmax terms
+//                 from LDS.  Neighbour gradients through binding faces gather
+//                 per face in LDS.  Everything is flushed with one global
+//                 atomic per (chunk, parameter).
 #include "pf_backward.hpp"
 #include "pf_shade.hpp"
 
@@ -26,11 +30,12 @@
 namespace pf {
 namespace {
 
-constexpr int BWD_THREADS = 256;
-constexpr int CHUNK = 4096;         // records per workgroup
-constexpr int FMAX_B = 256;         // raster faces held in LDS
-constexpr int ACC_CELL = 12;        // p(3) w r n(3) lambda rgb(3)
-constexpr int ACC = ACC_CELL + KD * TEXW;
+constexpr int BWD_THREADS = 64;     // one wave per workgroup
+constexpr int CHUNK = 2048;         // records per workgroup
+constexpr int FMAX_B = 128;         // faces gathered in LDS; faces beyond add to global directly
+constexpr int NCELL = 12;           // p(3) w r n(3) lambda rgb(3)
+constexpr int NSUM = NCELL + 3 * KD;  // + detail-site s(2), d per site
+constexpr int KPAD = 65;            // row pitch of the per-site LDS table (bank spread)
 
 __global__ void k_suffix(const int32_t* __restrict__ head, int64_t npix, const float* __restrict__ d_rgba,
                          const int4* __restrict__ ri, float4* __restrict__ rf, const float* __restrict__ rt) {
@@ -56,17 +61,22 @@ __global__ void k_suffix(const int32_t* __restrict__ head, int64_t npix, const f
   }
 }
 
-__global__ void k_rec_hist(const int4* __restrict__ ri, int64_t nrec, uint32_t* __restrict__ cnt) {
+__global__ void k_seg_hist(const int4* __restrict__ seg, int64_t nseg, uint32_t* __restrict__ cnt) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nrec) atomicAdd(&cnt[ri[i].x], 1u);
+  if (i < nseg) {
+    const int4 g = seg[i];
+    if (g.z > 0) atomicAdd(&cnt[g.x], (uint32_t)g.z);
+  }
 }
 
-__global__ void k_rec_scatter(const int4* __restrict__ ri, int64_t nrec, const uint32_t* __restrict__ off,
+__global__ void k_seg_scatter(const int4* __restrict__ seg, int64_t nseg, const uint32_t* __restrict__ off,
                               uint32_t* __restrict__ fill, int32_t* __restrict__ order) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nrec) return;
-  const int c = ri[i].x;
-  order[off[c] + atomicAdd(&fill[c], 1u)] = (int32_t)i;
+  if (i >= nseg) return;
+  const int4 g = seg[i];
+  if (g.z <= 0) return;   // unused slot of a segment block
+  const uint32_t at = off[g.x] + atomicAdd(&fill[g.x], (uint32_t)g.z);
+  for (int j = 0; j < g.z; ++j) order[at + j] = g.y + j;
 }
 
 __global__ void k_chunk_count(const uint32_t* __restrict__ cnt, int64_t n, uint32_t* __restrict__ nch) {
@@ -86,39 +96,24 @@ __global__ void k_chunk_fill(const uint32_t* __restrict__ cnt, const uint32_t* _
   }
 }
 
-__device__ inline float wave_sum(float x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+// Sum of x over the wave, valid in lane 63: DPP butterflies within rows of
+// 16 lanes, then the row broadcasts of lane 15 and lane 31.
+__device__ inline float wave_total(float x) {
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xf, 0xf, false));  // quad [1,0,3,2]
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xf, 0xf, false));  // quad [2,3,0,1]
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x141, 0xf, 0xf, false)); // row half mirror
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x140, 0xf, 0xf, false)); // row mirror
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x142, 0xa, 0xf, false)); // row bcast 15
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x143, 0xc, 0xf, false)); // row bcast 31
   return x;
 }
 
-// Adds the wave-wide sum of v into the LDS accumulator (one LDS atomic per
-// wave; the workgroup's waves share the accumulators).
-__device__ inline void acc_add(float* acc, int idx, float v) {
-  const float s = wave_sum(v);
-  if ((threadIdx.x & 63) == 0 && s != 0.0f) atomicAdd(&acc[idx], s);
+// acc[i] += sum over the wave of (valid ? v : 0); acc is the wave's own LDS.
+__device__ inline void sum_to(float* acc, int i, bool valid, float v) {
+  const float t = wave_total(valid ? v : 0.0f);
+  if ((threadIdx.x & 63) == 63) acc[i] += t;
 }
 
-struct BwdArgs {
-  const pf_camera* cams;
-  const int4* ri;
-  const float4* rf;
-  const int32_t* order;
-  const int4* chunks;
-  const float* p;
-  const float* power;
-  const float* radius;
-  const float* normal;
-  const float* lam;
-  const float* rgb;
-  const float* tex;
-  const int32_t* row;
-  const int32_t* nrast;
-  const int32_t* col;
-  const float4* plane;
-  float sigma_scale, tau;
-  pf_grads g;
-};
 
 __device__ inline float softplus_b(float x) { return x > 20.0f ? x : log1pf(expf(x)); }
 
@@ -165,33 +160,35 @@ __device__ inline void dlogit_du(double ux, double uy, double sx, double sy, dou
   gy = (-uy * e - sy * un) * inv;
 }
 
-__global__ void __launch_bounds__(BWD_THREADS) k_bwd_cell(BwdArgs A) {
-  __shared__ float tex_s[KD * TEXW];
-  __shared__ float4 fpl[FMAX_B];
-  __shared__ float acc[ACC];
-  __shared__ float facc[FMAX_B][4];
+__global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) k_bwd_cell(
+    const pf_camera* __restrict__ cams, const int4* __restrict__ ri, const float4* __restrict__ rf,
+    const int32_t* __restrict__ order, const int4* __restrict__ chunks, const float* __restrict__ prm_p,
+    const float* __restrict__ radius, const float* __restrict__ normal, const float* __restrict__ lamv,
+    const float* __restrict__ tex, const int32_t* __restrict__ row, const int32_t* __restrict__ nrast,
+    const int32_t* __restrict__ col, const float4* __restrict__ plane, float sigma_scale, float tau_, pf_grads G) {
+  __shared__ float4 st_dir[64];          // per record: ray direction (float), 0
+  __shared__ float4 st_gc[64];           // per record: dL/dc, 0
+  __shared__ float2 st_k[KD][KPAD];      // per record and site: softmax shift, dL/dw_k
+  __shared__ float acc[NSUM];
+  __shared__ float4 facc[FMAX_B];
 
-  const int4 ch = A.chunks[blockIdx.x];
+  const int4 ch = chunks[blockIdx.x];
   const int ci = ch.x;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int r0 = A.row[ci];
-  const int nf = min(A.nrast[ci], FMAX_B);
-  for (int t = tid; t < KD * TEXW; t += BWD_THREADS) tex_s[t] = A.tex[(int64_t)ci * KD * TEXW + t];
-  for (int t = tid; t < nf; t += BWD_THREADS) fpl[t] = A.plane[r0 + t];
-  for (int t = tid; t < ACC; t += BWD_THREADS) acc[t] = 0.0f;
-  for (int t = tid; t < FMAX_B * 4; t += BWD_THREADS) (&facc[0][0])[t] = 0.0f;
-  __syncthreads();
+  const int lane = threadIdx.x;
+  const int r0 = row[ci];
+  const int nf = nrast[ci];
+  const int nfl = min(nf, FMAX_B);
+  const float* __restrict__ txc = tex + (int64_t)ci * KD * TEXW;
+  for (int t = lane; t < NSUM; t += BWD_THREADS) acc[t] = 0.0f;
+  for (int t = lane; t < nfl; t += BWD_THREADS) facc[t] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 
   // cell constants, computed exactly as the build's per-cell record
-  const float px = A.p[3 * ci], py = A.p[3 * ci + 1], pz = A.p[3 * ci + 2];
-  const float rad = A.radius[ci];
-  const float nrx = A.normal[3 * ci], nry = A.normal[3 * ci + 1], nrz = A.normal[3 * ci + 2];
-  const float ninv = 1.0f / sqrtf(nrx * nrx + nry * nry + nrz * nrz);
-  const float nx = nrx * ninv, ny = nry * ninv, nz = nrz * ninv;
-  const float lam = A.lam[ci];
-  const float sigma = A.sigma_scale * softplus_b(lam);
-  const float* rgbp = A.rgb + 3 * (int64_t)ci;
-  const float tau = A.tau;
+  const float px = prm_p[3 * ci], py = prm_p[3 * ci + 1], pz = prm_p[3 * ci + 2];
+  const float rad = radius[ci];
+  const float nrx = normal[3 * ci], nry = normal[3 * ci + 1], nrz = normal[3 * ci + 2];
+  const float lam = lamv[ci];
+  const float sigma = sigma_scale * softplus_b(lam);
+  const float tau = tau_;
   // float64 face frame (for the displacement chain)
   const double dninv = 1.0 / sqrt((double)nrx * nrx + (double)nry * nry + (double)nrz * nrz);
   const double dnx = nrx * dninv, dny = nry * dninv, dnz = nrz * dninv;
@@ -208,22 +205,38 @@ __global__ void __launch_bounds__(BWD_THREADS) k_bwd_cell(BwdArgs A) {
     d2z = -dny;
   }
 
-  for (int base = ch.y + wv * 64; base < ch.z; base += BWD_THREADS) {
+  // (site, axis) owned by this lane in the transposed phase
+  const int km = lane >> 3, mm = lane & 7;
+  const float* tkm = txc + km * TEXW;
+  const float ax = tkm[3 + 3 * mm], ay = tkm[4 + 3 * mm], az = tkm[5 + 3 * mm];
+  const float ccr = tkm[3 + 3 * MA + 3 * mm], ccg = tkm[4 + 3 * MA + 3 * mm], ccb = tkm[5 + 3 * MA + 3 * mm];
+  float gax = 0.0f, gay = 0.0f, gaz = 0.0f, gcr_a = 0.0f, gcg_a = 0.0f, gcb_a = 0.0f;
+
+  for (int base = ch.y; base < ch.z; base += 64) {
+    // the texture is re-read per record batch (scalar loads) rather than
+    // held in registers across the loop
+    const float* __restrict__ tx = txc;
+    asm volatile("" : "+s"(tx));
     const int idx = base + lane;
     const bool valid = idx < ch.z;
+    const int nvalid = min(64, ch.z - base);
     int4 rec = make_int4(0, 0, -1, 0);
     float4 gf = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if (valid) {
-      const int ridx = A.order[idx];
-      rec = A.ri[ridx];
-      gf = A.rf[ridx];
+      const int ridx = order[idx];
+      rec = ri[ridx];
+      gf = rf[ridx];
     }
     const int view = rec.w >> 20;
     const int b0 = ((rec.w >> 10) & 1023) - 2, b1 = (rec.w & 1023) - 2;
-    const pf_camera& cam = A.cams[valid ? view : 0];
+    const pf_camera& cam = cams[valid ? view : 0];
     const int pxl = rec.y % cam.width, pyl = rec.y / cam.width;
     const RayD R = make_ray(cam, pxl + 0.5, pyl + 0.5);
     const float fx = R.fx, fy = R.fy, fz = R.fz;
+    const float g_alpha = gf.x;
+    const float gcr = gf.y, gcg = gf.z, gcb = gf.w;
+    st_dir[lane] = make_float4(fx, fy, fz, 0.0f);
+    st_gc[lane] = make_float4(gcr, gcg, gcb, 0.0f);
 
     // ---------------- forward recompute.  Interval ends in float32 as in
     // piece_geometry; the face frame, displacement and texture point in
@@ -232,16 +245,14 @@ __global__ void __launch_bounds__(BWD_THREADS) k_bwd_cell(BwdArgs A) {
     const Local L = make_local(R, px, py, pz);
     const double Dd = (double)rad * (double)rad - L.qq;
     const float sq = sqrtf((float)fmax(Dd, 1e-30));
-    auto plane_s = [&](int f, float& a_out) {
-      const float4 pl = fpl[f];
-      const float a = fx * pl.x + fy * pl.y + fz * pl.z;
-      const float bb = pl.w - (L.qx * pl.x + L.qy * pl.y + L.qz * pl.z);
-      a_out = a;
-      return bb * frcp(a);
-    };
-    float a0 = 1.0f, a1 = 1.0f;
-    const float s0 = (b0 == -1) ? -sq : (b0 == -2) ? L.beta : plane_s(max(b0, 0), a0);
-    const float s1 = (b1 == -1) ? sq : plane_s(max(b1, 0), a1);
+    const float4 pl0 = (b0 >= 0 && b0 < nf) ? plane[r0 + b0] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const float4 pl1 = (b1 >= 0 && b1 < nf) ? plane[r0 + b1] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const float a0 = fx * pl0.x + fy * pl0.y + fz * pl0.z;
+    const float a1 = fx * pl1.x + fy * pl1.y + fz * pl1.z;
+    const float s0 = (b0 == -1) ? -sq
+                     : (b0 == -2) ? L.beta
+                                  : (pl0.w - (L.qx * pl0.x + L.qy * pl0.y + L.qz * pl0.z)) * frcp(a0);
+    const float s1 = (b1 == -1) ? sq : (pl1.w - (L.qx * pl1.x + L.qy * pl1.y + L.qz * pl1.z)) * frcp(a1);
     const double ddx = R.dx, ddy = R.dy, ddz = R.dz;
     const double qdx = L.dqx, qdy = L.dqy, qdz = L.dqz;
     const double den = ddx * dnx + ddy * dny + ddz * dnz;
@@ -252,7 +263,7 @@ __global__ void __launch_bounds__(BWD_THREADS) k_bwd_cell(BwdArgs A) {
     const double dt2 = ddx * d2x + ddy * d2y + ddz * d2z;
     const bool nzden = den != 0.0;
     double idn = 0.0, sbar = 0.0, sxx = 0.0, delta = 0.0;
-    double wd[KD];
+    float wd[KD];   // displacement weights at ubar (float64 while summed)
     double ubx = 0.0, uby = 0.0;
     double j0 = s0, j1 = s1;
     int sel0 = 0, sel1 = 0;   // 1: the end is the displaced face
@@ -262,9 +273,15 @@ __global__ void __launch_bounds__(BWD_THREADS) k_bwd_cell(BwdArgs A) {
       sbar = -qn * idn;
       ubx = qt1 + sbar * dt1;
       uby = qt2 + sbar * dt2;
-      sv_weights_d(tex_s, ubx, uby, (double)tau, wd);
+      {
+        double w64[KD];
+        sv_weights_d(tx, ubx, uby, (double)tau, w64);
 #pragma unroll
-      for (int k = 0; k < KD; ++k) delta += wd[k] * (double)tex_s[k * TEXW + 2];
+        for (int k = 0; k < KD; ++k) {
+          delta += w64[k] * (double)tx[k * TEXW + 2];
+          wd[k] = (float)w64[k];
+        }
+      }
       sxx = (delta - qn) * idn;
       if (den > 0.0) {
         sel1 = sxx < (double)s1;
@@ -276,7 +293,7 @@ __global__ void __launch_bounds__(BWD_THREADS) k_bwd_cell(BwdArgs A) {
       S = sxx;
     } else {
 #pragma unroll
-      for (int k = 0; k < KD; ++k) wd[k] = 0.0;
+      for (int k = 0; k < KD; ++k) wd[k] = 0.0f;
       S = 0.5 * ((double)s0 + (double)s1);
       if (!(qn < 0.0)) j1 = j0;
     }
@@ -284,14 +301,12 @@ __global__ void __launch_bounds__(BWD_THREADS) k_bwd_cell(BwdArgs A) {
     uy = qt2 + S * dt2;
     const float ell = (float)fmax(j1 - j0, 0.0);
     const float alpha = 1.0f - __expf(-sigma * ell);
-    const float g_alpha = valid ? gf.x : 0.0f;
-    const float gcr = valid ? gf.y : 0.0f, gcg = valid ? gf.z : 0.0f, gcb = valid ? gf.w : 0.0f;
 
     // ---------------- opacity
     const float om = 1.0f - alpha;
     const float g_ell = (ell > 0.0f) ? g_alpha * sigma * om : 0.0f;
     const float g_sigma = g_alpha * ell * om;
-    const float g_lam = g_sigma * A.sigma_scale / (1.0f + __expf(-lam));
+    const float g_lam = g_sigma * sigma_scale / (1.0f + __expf(-lam));
     float g_s0 = 0.0f, g_s1 = 0.0f;
     double g_sx = 0.0;
     if (nzden || qn < 0.0) {
@@ -299,14 +314,20 @@ __global__ void __launch_bounds__(BWD_THREADS) k_bwd_cell(BwdArgs A) {
       if (sel0) g_sx -= g_ell; else g_s0 -= g_ell;
     }
 
-    // ---------------- radiance: pass A (weights at u, their softmax backward)
-    double wr[KD];
-    float gwr[KD];
-    sv_weights_d(tex_s, ux, uy, (double)tau, wr);
+    // ---------------- radiance: weights at u, the sites' Spherical-Voronoi
+    // colours sv_k(d) and the softmax backward of the weights
+    float wr[KD];
+    {
+      double w64[KD];
+      sv_weights_d(tx, ux, uy, (double)tau, w64);
+#pragma unroll
+      for (int k = 0; k < KD; ++k) wr[k] = (float)w64[k];
+    }
     double sum_wg = 0.0;
+    float gwr[KD];
 #pragma unroll
     for (int k = 0; k < KD; ++k) {
-      const float* t = tex_s + k * TEXW;
+      const float* t = tx + k * TEXW;
       float lg[MA], mx = -INFINITY;
 #pragma unroll
       for (int m = 0; m < MA; ++m) {
@@ -323,23 +344,25 @@ __global__ void __launch_bounds__(BWD_THREADS) k_bwd_cell(BwdArgs A) {
         sb += e * t[5 + 3 * MA + 3 * m];
       }
       const float inv = frcp(sum);
-      gwr[k] = gcr * sr * inv + gcg * sg * inv + gcb * sb * inv;   // dL/dw'_k = gC . sv_k
-      sum_wg += wr[k] * (double)gwr[k];
+      gwr[k] = (gcr * sr + gcg * sg + gcb * sb) * inv;   // dL/dw_k = gC . sv_k
+      sum_wg += (double)wr[k] * (double)gwr[k];
+      // w_k softmax_m(a_km.d) = exp(a_km.d - shift_k)
+      const float wi = wr[k] * inv;
+      st_k[k][lane] = make_float2(wi > 0.0f ? mx - __logf(wi) : INFINITY, gwr[k]);
     }
-    float gsx_[KD], gsy_[KD];
     double gux = 0.0, guy = 0.0;
 #pragma unroll
     for (int k = 0; k < KD; ++k) {
-      const double ge = -(double)tau * wr[k] * ((double)gwr[k] - sum_wg);   // z_k = -tau(|u - s_k| - |u|)
+      const double ge = -(double)tau * (double)wr[k] * ((double)gwr[k] - sum_wg);   // z_k = -tau(|u - s_k| - |u|)
       double lx, ly;
-      dlogit_du(ux, uy, tex_s[k * TEXW], tex_s[k * TEXW + 1], lx, ly);
+      dlogit_du(ux, uy, tx[k * TEXW], tx[k * TEXW + 1], lx, ly);
       gux += ge * lx;
       guy += ge * ly;
-      const double ex = ux - tex_s[k * TEXW], ey = uy - tex_s[k * TEXW + 1];
+      const double ex = ux - tx[k * TEXW], ey = uy - tx[k * TEXW + 1];
       const double dist = sqrt(ex * ex + ey * ey);
       const double id = dist > 0.0 ? 1.0 / dist : 0.0;
-      gsx_[k] = (float)(-ge * ex * id);
-      gsy_[k] = (float)(-ge * ey * id);
+      sum_to(acc, NCELL + 3 * k, valid, (float)(-ge * ex * id));
+      sum_to(acc, NCELL + 3 * k + 1, valid, (float)(-ge * ey * id));
     }
     // u = (qt1 + S dt1, qt2 + S dt2)
     double g_qt1 = gux, g_qt2 = guy, g_dt1 = gux * S, g_dt2 = guy * S;
@@ -349,9 +372,6 @@ __global__ void __launch_bounds__(BWD_THREADS) k_bwd_cell(BwdArgs A) {
 
     // ---------------- displaced face sx = (delta - qn)/den
     double g_qn = 0.0, g_den = 0.0;
-    float gdk[KD];
-#pragma unroll
-    for (int k = 0; k < KD; ++k) gdk[k] = 0.0f;
     if (nzden) {
       const double g_delta = g_sx * idn;
       g_qn -= g_sx * idn;
@@ -360,23 +380,23 @@ __global__ void __launch_bounds__(BWD_THREADS) k_bwd_cell(BwdArgs A) {
       double gw[KD];
 #pragma unroll
       for (int k = 0; k < KD; ++k) {
-        gdk[k] = (float)(g_delta * wd[k]);
-        gw[k] = g_delta * (double)tex_s[k * TEXW + 2];
-        sum_w += wd[k] * gw[k];
+        sum_to(acc, NCELL + 3 * k + 2, valid, (float)(g_delta * (double)wd[k]));
+        gw[k] = g_delta * (double)tx[k * TEXW + 2];
+        sum_w += (double)wd[k] * gw[k];
       }
       double gubx = 0.0, guby = 0.0;
 #pragma unroll
       for (int k = 0; k < KD; ++k) {
-        const double ge = -(double)tau * wd[k] * (gw[k] - sum_w);
+        const double ge = -(double)tau * (double)wd[k] * (gw[k] - sum_w);
         double lx, ly;
-        dlogit_du(ubx, uby, tex_s[k * TEXW], tex_s[k * TEXW + 1], lx, ly);
+        dlogit_du(ubx, uby, tx[k * TEXW], tx[k * TEXW + 1], lx, ly);
         gubx += ge * lx;
         guby += ge * ly;
-        const double ex = ubx - tex_s[k * TEXW], ey = uby - tex_s[k * TEXW + 1];
+        const double ex = ubx - tx[k * TEXW], ey = uby - tx[k * TEXW + 1];
         const double dist = sqrt(ex * ex + ey * ey);
         const double id = dist > 0.0 ? 1.0 / dist : 0.0;
-        gsx_[k] -= (float)(ge * ex * id);
-        gsy_[k] -= (float)(ge * ey * id);
+        sum_to(acc, NCELL + 3 * k, valid, (float)(-ge * ex * id));
+        sum_to(acc, NCELL + 3 * k + 1, valid, (float)(-ge * ey * id));
       }
       // ubar = (qt1 + sbar dt1, qt2 + sbar dt2), sbar = -qn/den
       g_qt1 += gubx;
@@ -386,48 +406,6 @@ __global__ void __launch_bounds__(BWD_THREADS) k_bwd_cell(BwdArgs A) {
       const double g_sbar = gubx * dt1 + guby * dt2;
       g_qn -= g_sbar * idn;
       g_den += g_sbar * qn * idn * idn;
-    }
-
-    // ---------------- texture gradients, pass B: one wave sum per entry
-#pragma unroll
-    for (int k = 0; k < KD; ++k) {
-      const float* t = tex_s + k * TEXW;
-      float* ak = acc + ACC_CELL + k * TEXW;
-      acc_add(ak, 0, gsx_[k]);
-      acc_add(ak, 1, gsy_[k]);
-      acc_add(ak, 2, gdk[k]);
-      float lg[MA], mx = -INFINITY;
-#pragma unroll
-      for (int m = 0; m < MA; ++m) {
-        lg[m] = t[3 + 3 * m] * fx + t[4 + 3 * m] * fy + t[5 + 3 * m] * fz;
-        mx = fmaxf(mx, lg[m]);
-      }
-      float v[MA], sum = 0.0f;
-#pragma unroll
-      for (int m = 0; m < MA; ++m) {
-        v[m] = __expf(lg[m] - mx);
-        sum += v[m];
-      }
-      const float inv = frcp(sum);
-      const float wk = (float)wr[k];
-      const float gsr = wk * gcr, gsg = wk * gcg, gsb = wk * gcb;   // dL/dsv_k
-      float gv[MA], sgv = 0.0f;
-#pragma unroll
-      for (int m = 0; m < MA; ++m) {
-        v[m] *= inv;
-        gv[m] = gsr * t[3 + 3 * MA + 3 * m] + gsg * t[4 + 3 * MA + 3 * m] + gsb * t[5 + 3 * MA + 3 * m];
-        sgv += v[m] * gv[m];
-      }
-#pragma unroll
-      for (int m = 0; m < MA; ++m) {
-        const float gl = v[m] * (gv[m] - sgv);
-        acc_add(ak, 3 + 3 * m, gl * fx);
-        acc_add(ak, 4 + 3 * m, gl * fy);
-        acc_add(ak, 5 + 3 * m, gl * fz);
-        acc_add(ak, 3 + 3 * MA + 3 * m, gsr * v[m]);
-        acc_add(ak, 4 + 3 * MA + 3 * m, gsg * v[m]);
-        acc_add(ak, 5 + 3 * MA + 3 * m, gsb * v[m]);
-      }
     }
 
     // ---------------- frame: q.nhat, d.nhat, q.t1, d.t1, q.t2, d.t2 (float64)
@@ -454,7 +432,7 @@ __global__ void __launch_bounds__(BWD_THREADS) k_bwd_cell(BwdArgs A) {
     // ---------------- ends of the bounded interval
     float g_beta = 0.0f, g_r = 0.0f, g_wi = 0.0f;
     float gpx = 0.0f, gpy = 0.0f, gpz = 0.0f;   // explicit p_i terms (planes)
-    auto end_grad = [&](int b, float s, float a, float ge, bool upper) {
+    auto end_grad = [&](int b, const float4& pl, float s, float a, float ge, bool upper) {
       if (ge == 0.0f) return;
       if (b == -1) {                       // s = +-sqrt(r^2 - |q|^2)
         const float inv = 1.0f / sq;
@@ -465,8 +443,7 @@ __global__ void __launch_bounds__(BWD_THREADS) k_bwd_cell(BwdArgs A) {
         g_r += sgn * ge * rad * inv;
       } else if (b == -2) {                // s = beta (ray start)
         g_beta += ge;
-      } else {                             // s = (h - q.m)/(d.m), neighbour face
-        const float4 pl = fpl[b];
+      } else if (b < nf) {                 // s = (h - q.m)/(d.m), neighbour face
         const float ia = 1.0f / a;
         gqx -= ge * pl.x * ia;
         gqy -= ge * pl.y * ia;
@@ -479,15 +456,27 @@ __global__ void __launch_bounds__(BWD_THREADS) k_bwd_cell(BwdArgs A) {
         gpy -= gmy;
         gpz -= gmz;
         g_wi += 0.5f * gh;
-        atomicAdd(&facc[b][0], gmx);
-        atomicAdd(&facc[b][1], gmy);
-        atomicAdd(&facc[b][2], gmz);
-        atomicAdd(&facc[b][3], -0.5f * gh);
+        if (b < FMAX_B) {
+          atomicAdd(&facc[b].x, gmx);
+          atomicAdd(&facc[b].y, gmy);
+          atomicAdd(&facc[b].z, gmz);
+          atomicAdd(&facc[b].w, -0.5f * gh);
+        } else {
+          const int j = col[r0 + b];
+          if (j >= 0) {
+            if (G.p) {
+              atomicAdd(G.p + 3 * (int64_t)j, gmx);
+              atomicAdd(G.p + 3 * (int64_t)j + 1, gmy);
+              atomicAdd(G.p + 3 * (int64_t)j + 2, gmz);
+            }
+            if (G.power) atomicAdd(G.power + j, -0.5f * gh);
+          }
+        }
       }
     };
     if (valid) {
-      end_grad(b0, s0, a0, g_s0, false);
-      end_grad(b1, s1, a1, g_s1, true);
+      end_grad(b0, pl0, s0, a0, g_s0, false);
+      end_grad(b1, pl1, s1, a1, g_s1, true);
     }
     // q = oc - beta d, beta = oc.d, oc = o - p_i
     const float gqd = gqx * fx + gqy * fy + gqz * fz;
@@ -495,43 +484,73 @@ __global__ void __launch_bounds__(BWD_THREADS) k_bwd_cell(BwdArgs A) {
     gpy += -(gqy - gqd * fy) - g_beta * fy;
     gpz += -(gqz - gqd * fz) - g_beta * fz;
 
-    acc_add(acc, 0, gpx);
-    acc_add(acc, 1, gpy);
-    acc_add(acc, 2, gpz);
-    acc_add(acc, 3, g_wi);
-    acc_add(acc, 4, g_r);
-    acc_add(acc, 5, gnx);
-    acc_add(acc, 6, gny);
-    acc_add(acc, 7, gnz);
-    acc_add(acc, 8, g_lam);
-    acc_add(acc, 9, gcr);
-    acc_add(acc, 10, gcg);
-    acc_add(acc, 11, gcb);
+    // ---------------- per-record sums over the wave (lanes past the chunk
+    // add zero)
+    {
+      const float cellv[NCELL] = {gpx, gpy, gpz, g_wi, g_r, gnx, gny, gnz, g_lam, gcr, gcg, gcb};
+#pragma unroll
+      for (int i = 0; i < NCELL; ++i) sum_to(acc, i, valid, cellv[i]);
+    }
+
+    // ---------------- Spherical-Voronoi gradients, lane = (site k, axis m):
+    //   v = softmax_m(a_km . d),  dL/dc_km += w_k v gC,
+    //   dL/da_km += w_k v (gC.c_km - gC.sv_k) d
+    __builtin_amdgcn_wave_barrier();
+    for (int r = 0; r < nvalid; ++r) {
+      const float4 dd = st_dir[r];
+      const float4 gc = st_gc[r];
+      const float2 kk = st_k[km][r];
+      const float lg = ax * dd.x + ay * dd.y + az * dd.z;
+      const float vw = __expf(lg - kk.x);
+      const float gcm = gc.x * ccr + gc.y * ccg + gc.z * ccb;
+      const float gl = vw * (gcm - kk.y);
+      gax += gl * dd.x;
+      gay += gl * dd.y;
+      gaz += gl * dd.z;
+      gcr_a += vw * gc.x;
+      gcg_a += vw * gc.y;
+      gcb_a += vw * gc.z;
+    }
+    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
 
   // flush
-  for (int t = tid; t < ACC; t += BWD_THREADS) {
+  for (int t = lane; t < NSUM; t += BWD_THREADS) {
     const float v = acc[t];
     if (v == 0.0f) continue;
     float* dst = nullptr;
-    if (t < 3) dst = A.g.p ? A.g.p + 3 * (int64_t)ci + t : nullptr;
-    else if (t == 3) dst = A.g.power ? A.g.power + ci : nullptr;
-    else if (t == 4) dst = A.g.radius ? A.g.radius + ci : nullptr;
-    else if (t < 8) dst = A.g.normal ? A.g.normal + 3 * (int64_t)ci + (t - 5) : nullptr;
-    else if (t == 8) dst = A.g.occ_logit ? A.g.occ_logit + ci : nullptr;
-    else if (t < 12) dst = A.g.rgb ? A.g.rgb + 3 * (int64_t)ci + (t - 9) : nullptr;
-    else dst = A.g.tex ? A.g.tex + (int64_t)ci * KD * TEXW + (t - ACC_CELL) : nullptr;
+    if (t < 3) dst = G.p ? G.p + 3 * (int64_t)ci + t : nullptr;
+    else if (t == 3) dst = G.power ? G.power + ci : nullptr;
+    else if (t == 4) dst = G.radius ? G.radius + ci : nullptr;
+    else if (t < 8) dst = G.normal ? G.normal + 3 * (int64_t)ci + (t - 5) : nullptr;
+    else if (t == 8) dst = G.occ_logit ? G.occ_logit + ci : nullptr;
+    else if (t < NCELL) dst = G.rgb ? G.rgb + 3 * (int64_t)ci + (t - 9) : nullptr;
+    else {
+      const int k = (t - NCELL) / 3, c = (t - NCELL) % 3;
+      dst = G.tex ? G.tex + (int64_t)ci * KD * TEXW + k * TEXW + c : nullptr;
+    }
     if (dst) atomicAdd(dst, v);
   }
-  for (int f = tid; f < nf; f += BWD_THREADS) {
-    const int j = A.col[r0 + f];
-    if (j < 0) continue;
-    if (A.g.p) {
-      for (int c = 0; c < 3; ++c)
-        if (facc[f][c] != 0.0f) atomicAdd(A.g.p + 3 * (int64_t)j + c, facc[f][c]);
+  if (G.tex) {
+    float* gt = G.tex + (int64_t)ci * KD * TEXW + km * TEXW;
+    const float va[3] = {gax, gay, gaz}, vc[3] = {gcr_a, gcg_a, gcb_a};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (va[c] != 0.0f) atomicAdd(gt + 3 + 3 * mm + c, va[c]);
+      if (vc[c] != 0.0f) atomicAdd(gt + 3 + 3 * MA + 3 * mm + c, vc[c]);
     }
-    if (A.g.power && facc[f][3] != 0.0f) atomicAdd(A.g.power + j, facc[f][3]);
+  }
+  for (int f = lane; f < nfl; f += BWD_THREADS) {
+    const int j = col[r0 + f];
+    if (j < 0) continue;
+    const float4 v = facc[f];
+    if (G.p) {
+      if (v.x != 0.0f) atomicAdd(G.p + 3 * (int64_t)j, v.x);
+      if (v.y != 0.0f) atomicAdd(G.p + 3 * (int64_t)j + 1, v.y);
+      if (v.z != 0.0f) atomicAdd(G.p + 3 * (int64_t)j + 2, v.z);
+    }
+    if (G.power && v.w != 0.0f) atomicAdd(G.power + j, v.w);
   }
 }
 
@@ -567,11 +586,17 @@ pf_status backward_impl(const Scene& sc, const BwdState& st, const float* d_rgba
   PF_HIP_TRY(order.alloc(nrec));
   PF_HIP_TRY(hipMemsetAsync(cnt.p, 0, sizeof(uint32_t) * (n + 1), s));
   PF_HIP_TRY(hipMemsetAsync(fill.p, 0, sizeof(uint32_t) * n, s));
-  const unsigned gr = (unsigned)((nrec + 255) / 256), gc = (unsigned)((n + 255) / 256);
-  k_rec_hist<<<gr, 256, 0, s>>>(st.rec.ri, nrec, cnt.p);
+  const unsigned gsg = (unsigned)((st.nseg + 255) / 256), gc = (unsigned)((n + 255) / 256);
+  if (st.nseg) {
+    ProfScope ps("k_seg_hist", s);
+    k_seg_hist<<<gsg, 256, 0, s>>>(st.rec.seg, st.nseg, cnt.p);
+  }
   PF_HIP_TRY(hipGetLastError());
   PF_HIP_TRY(exclusive_scan_u32(cnt.p, off.p, n + 1, nullptr, s));
-  k_rec_scatter<<<gr, 256, 0, s>>>(st.rec.ri, nrec, off.p, fill.p, order.p);
+  if (st.nseg) {
+    ProfScope ps("k_seg_scatter", s);
+    k_seg_scatter<<<gsg, 256, 0, s>>>(st.rec.seg, st.nseg, off.p, fill.p, order.p);
+  }
   PF_HIP_TRY(hipGetLastError());
   k_chunk_count<<<gc, 256, 0, s>>>(cnt.p, n, nch.p);
   PF_HIP_TRY(hipGetLastError());
@@ -584,29 +609,11 @@ pf_status backward_impl(const Scene& sc, const BwdState& st, const float* d_rgba
   PF_HIP_TRY(chunks.alloc(nchunks));
   k_chunk_fill<<<gc, 256, 0, s>>>(cnt.p, off.p, choff.p, n, chunks.p);
   PF_HIP_TRY(hipGetLastError());
-  BwdArgs A;
-  A.cams = st.cams_dev;
-  A.ri = st.rec.ri;
-  A.rf = st.rec.rf;
-  A.order = order.p;
-  A.chunks = chunks.p;
-  A.p = sc.prm.p;
-  A.power = sc.prm.power;
-  A.radius = sc.prm.radius;
-  A.normal = sc.prm.normal;
-  A.lam = sc.prm.occ_logit;
-  A.rgb = sc.prm.rgb;
-  A.tex = sc.prm.tex;
-  A.row = sc.row;
-  A.nrast = sc.nrast;
-  A.col = sc.col;
-  A.plane = sc.plane;
-  A.sigma_scale = sc.prm.sigma_scale;
-  A.tau = sc.prm.tau;
-  A.g = g;
   if (nchunks) {
     ProfScope ps("k_bwd_cell", s);
-    k_bwd_cell<<<nchunks, BWD_THREADS, 0, s>>>(A);
+    k_bwd_cell<<<nchunks, BWD_THREADS, 0, s>>>(st.cams_dev, st.rec.ri, st.rec.rf, order.p, chunks.p, sc.prm.p,
+                                                sc.prm.radius, sc.prm.normal, sc.prm.occ_logit, sc.prm.tex, sc.row,
+                                                sc.nrast, sc.col, sc.plane, sc.prm.sigma_scale, sc.prm.tau, g);
   }
   PF_HIP_TRY(hipGetLastError());
   return PF_OK;

@@ -8,6 +8,7 @@ namespace pf {
 struct BwdState {
   RecBuf rec;                 // contribution records of all views
   int64_t nrec = 0;           // records written
+  int64_t nseg = 0;           // segments written
   int64_t npix = 0;           // pixels of all views
   pf_camera* cams_dev = nullptr;
 };

@@ -41,7 +41,8 @@ struct Scene {
   int32_t* col = nullptr;          // [E] neighbour, or -1-f for box face f
   float4* plane = nullptr;         // [E] (m, h): (x - p_i).m <= h
   int64_t n_faces = 0, n_hidden = 0, n_overflow = 0, n_big = 0;
-  double rec_per_pixel = 12.0;     // record-pool sizing hint for store mode
+  double rec_per_pixel = 0.0;      // record-pool sizing hint for store mode (0: none yet)
+  double seg_per_pixel = 0.0;      // segment-list sizing hint for store mode
 };
 
 // Contribution records written by the store-mode forward: one per (pixel,
@@ -51,13 +52,19 @@ struct Scene {
 //   rf = (alpha, c.r, c.g, c.b); after the per-pixel pass (dL/dalpha, dL/dc)
 //   rt = transmittance in front of the contribution
 // bind: -1 sphere, -2 ray start, f >= 0 raster face index of the cell.
+// Every wave-wide append of one cell's records is also listed as a segment
+// (cell, first record, count, 0): the records of a segment are contiguous
+// and belong to one cell, which lets the backward group records by cell with
+// one atomic per segment.
 struct RecBuf {
   int4* ri = nullptr;
   float4* rf = nullptr;
   float* rt = nullptr;
   int32_t* head = nullptr;            // [pixels of all views] last record or -1
-  unsigned long long* counter = nullptr;
-  int64_t cap = 0;
+  unsigned long long* counter = nullptr;   // [2]: records, segments appended
+  int4* seg = nullptr;
+  int64_t cap = 0;                    // record capacity
+  int64_t seg_cap = 0;                // segment capacity
 };
 
 // Thread-local error text.

@@ -264,6 +264,15 @@ __device__ inline void contribute(const SceneDev& S, const RayD& R, int ci, bool
   }
 }
 
+constexpr int RBLK = 256;   // record slots reserved per wave at a time
+constexpr int SBLK = 32;    // segment slots reserved per wave at a time
+
+__device__ inline unsigned long long bcast64(unsigned long long x) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)x);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(x >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
 __device__ inline void tile_pixel(int tiles_x, int& px, int& py, int tile = -1) {
   if (tile < 0) tile = blockIdx.x;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
@@ -276,7 +285,11 @@ template <bool STORE>
 __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ views, int nview, SceneDev S,
                                                 const unsigned long long* __restrict__ list,
                                                 const uint32_t* __restrict__ tile_off, float t_min,
-                                                float* __restrict__ rgba_all, RecBuf rec) {
+                                                float* __restrict__ rgba_all, int4* __restrict__ rec_ri,
+                                                float4* __restrict__ rec_rf, float* __restrict__ rec_rt,
+                                                int32_t* __restrict__ rec_head,
+                                                unsigned long long* __restrict__ rec_counter,
+                                                int4* __restrict__ rec_seg, int64_t rec_cap, int64_t seg_cap) {
   // view of this tile: the last one whose tiles start at or before it
   int lo = 0, hi = nview - 1;
   while (lo < hi) {
@@ -299,6 +312,8 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int pix = py * v.cam.width + px;
   const uint32_t e0 = tile_off[blockIdx.x], e1 = tile_off[blockIdx.x + 1];
+  long long rblk = 0, sblk = 0;   // the wave's current record / segment block
+  int rleft = 0, sleft = 0;
   for (uint32_t e = e0; e < e1; ++e) {
     if (!__any(live)) break;
     const int ci = __builtin_amdgcn_readfirstlane((int)(uint32_t)list[e]);
@@ -322,15 +337,33 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
       const bool contrib = hit && P.alpha > 0.0f;
       const uint64_t m = __ballot(contrib);
       if (m) {
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(rec.counter, (unsigned long long)__popcll(m));
-        base = __shfl(base, 0, 64);
+        // slots come from the wave's own blocks; a new block is reserved
+        // with one global atomic when the current one cannot take the append
+        const int cnt = __popcll(m);
+        if (cnt > rleft) {
+          unsigned long long b = 0;
+          if (lane == 0) b = atomicAdd(&rec_counter[0], (unsigned long long)RBLK);
+          rblk = (long long)bcast64(b);
+          rleft = RBLK;
+        }
+        if (sleft == 0) {
+          unsigned long long b = 0;
+          if (lane == 0) b = atomicAdd(&rec_counter[1], (unsigned long long)SBLK);
+          sblk = (long long)bcast64(b);
+          sleft = SBLK;
+        }
+        const long long base = rblk, sg = sblk;
+        rblk += cnt;
+        rleft -= cnt;
+        sblk += 1;
+        sleft -= 1;
+        if (lane == 0 && sg < seg_cap && base + cnt <= rec_cap) rec_seg[sg] = make_int4(ci, (int)base, cnt, 0);
         if (contrib) {
-          const long long slot = (long long)base + __popcll(m & lt);
-          if (slot < rec.cap) {
-            rec.ri[slot] = make_int4(ci, pix, head, (view << 20) | ((P.bind0 + 2) << 10) | (P.bind1 + 2));
-            rec.rf[slot] = make_float4(P.alpha, r, gg, b);
-            rec.rt[slot] = T;
+          const long long slot = base + __popcll(m & lt);
+          if (slot < rec_cap) {
+            rec_ri[slot] = make_int4(ci, pix, head, (view << 20) | ((P.bind0 + 2) << 10) | (P.bind1 + 2));
+            rec_rf[slot] = make_float4(P.alpha, r, gg, b);
+            rec_rt[slot] = T;
             head = (int)slot;
           }
           const float wgt = T * P.alpha;
@@ -349,8 +382,27 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
     o[1] = cg;
     o[2] = cb;
     o[3] = 1.0f - T;
-    if constexpr (STORE) rec.head[pix_base + pix] = head;
+    if constexpr (STORE) rec_head[pix_base + pix] = head;
   }
+  if constexpr (STORE) {
+    // unused slots of the last segment block are marked empty (count 0)
+    for (int j = lane; j < sleft; j += 64)
+      if (sblk + j < seg_cap) rec_seg[sblk + j] = make_int4(0, 0, 0, 0);
+  }
+}
+
+// Total records listed by the segments (the block reservation leaves unused
+// record slots, so the reserved count is an upper bound).
+__global__ void __launch_bounds__(256) k_seg_total(const int4* __restrict__ seg, int64_t nseg,
+                                                   unsigned long long* __restrict__ total) {
+  __shared__ unsigned long long part[4];
+  unsigned long long acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nseg; i += (int64_t)gridDim.x * blockDim.x)
+    acc += (unsigned long long)seg[i].z;
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(total, part[0] + part[1] + part[2] + part[3]);
 }
 
 // argmin over cells with a non-empty power cell of pow(o, p_i) in float64;
@@ -597,14 +649,25 @@ pf_status raster_views(const Scene& sc, const pf_camera* cams, int ncam, float t
     {
       ProfScope ps(rec ? "k_raster_store" : "k_raster", s);
       if (rec) {
-        RecBuf rb = *rec;
+        const RecBuf& rb = *rec;
         k_raster<true><<<(unsigned)ntiles, 256, 0, s>>>(views.p, nv, scene_dev(sc), sorted.p, toff.p, t_min, rgba,
-                                                        rb);
+                                                        rb.ri, rb.rf, rb.rt, rb.head, rb.counter, rb.seg, rb.cap,
+                                                        rb.seg_cap);
       } else {
         k_raster<false><<<(unsigned)ntiles, 256, 0, s>>>(views.p, nv, scene_dev(sc), sorted.p, toff.p, t_min, rgba,
-                                                         RecBuf{});
+                                                         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0);
       }
     }
+    PF_HIP_TRY(hipGetLastError());
+  }
+  return PF_OK;
+}
+
+pf_status seg_record_total(const int4* seg, int64_t nseg, unsigned long long* total_dev, hipStream_t s) {
+  PF_HIP_TRY(hipMemsetAsync(total_dev, 0, sizeof(unsigned long long), s));
+  if (nseg > 0) {
+    const unsigned nb = (unsigned)std::min<int64_t>(1024, (nseg + 255) / 256);
+    k_seg_total<<<nb, 256, 0, s>>>(seg, nseg, total_dev);
     PF_HIP_TRY(hipGetLastError());
   }
   return PF_OK;

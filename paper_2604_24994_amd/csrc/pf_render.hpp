@@ -12,6 +12,8 @@ bool camera_ok(const pf_camera& c, std::string* why);
 // rec: store-mode records (null: plain forward).
 pf_status raster_views(const Scene& sc, const pf_camera* cams, int ncam, float t_min, float* rgba, hipStream_t s,
                        const RecBuf* rec = nullptr);
+// Sum of the segments' record counts into *total_dev (device).
+pf_status seg_record_total(const int4* seg, int64_t nseg, unsigned long long* total_dev, hipStream_t s);
 pf_status trace_view(const Scene& sc, const pf_camera& cam, float t_min, int max_steps, float* rgba,
                      unsigned long long* trunc_dev, hipStream_t s);
 
