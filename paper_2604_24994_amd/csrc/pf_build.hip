@@ -177,6 +177,9 @@ struct Shared {
   unsigned char used[PM];
   unsigned short remap[PM];
   unsigned long long omask[SPL];  // removed-vertex masks of the current clip
+  double key[64];                 // per-lane ordering keys
+  double cpl[64][5];              // flagged candidates in processing order: m, |m|^2, h
+  int corig[64];
 };
 
 enum ClipResult { NOCUT = 0, CUT = 1, EMPTY = 2, OVER_V = 3, OVER_P = 4, OVER_W = 5, OVER_S = 6 };
@@ -450,47 +453,57 @@ __device__ int compact_planes(Shared<SPL, PM>& S, EOT* eo, Poly<SPL>& P, int npl
   return base;
 }
 
-// Sorts the 64 lanes' candidate slots by squared distance (bitonic network
-// over lanes) and loads the candidates in that order.
-__device__ inline Cand sorted_cands(const float4* __restrict__ sp, const int32_t* __restrict__ sidx, int64_t j,
-                                   bool valid, double px, double py, double pz, double wi) {
-  const int lane = threadIdx.x;
-  double key = INFINITY;
-  if (valid) {
-    const float4 s = sp[j];
-    const double dx = (double)s.x - px, dy = (double)s.y - py, dz = (double)s.z - pz;
-    key = dx * dx + dy * dy + dz * dz;
-  }
-  int64_t jj = j;
-  for (int kk = 2; kk <= 64; kk <<= 1) {
-    for (int st = kk >> 1; st > 0; st >>= 1) {
-      const double ok = __shfl_xor(key, st, 64);
-      const int64_t oj = __shfl_xor(jj, st, 64);
-      const bool up = (lane & kk) == 0;
-      const bool lower = (lane & st) == 0;
-      const bool take = lower ? (up ? (ok < key) : (ok > key)) : (up ? (ok > key) : (ok < key));
-      if (take) { key = ok; jj = oj; }
-    }
-  }
-  return load_cand(sp, sidx, jj, key != INFINITY, px, py, pz, wi);
+// Whether the plane (m, h) cuts off a vertex of the current polytope (the
+// vertex list after the last clip is in S.tpos).
+template <int SPL, int PM>
+__device__ inline bool cuts_vertices(const Shared<SPL, PM>& S, int ntri, double mx, double my, double mz,
+                                     double h) {
+  for (int t = 0; t < ntri; ++t)
+    if (mx * S.tpos[t][0] + my * S.tpos[t][1] + mz * S.tpos[t][2] > h) return true;
+  return false;
 }
 
-// Processes the candidates of this wave's lanes in lane order.  Returns
-// false when the cell became empty or overflowed (state in status).
+// Number of flagged lanes whose key orders before this lane's (ties by
+// lane); keys of the wave in S.key.
+template <int SPL, int PM>
+__device__ inline int lane_rank(const Shared<SPL, PM>& S, double key) {
+  const int lane = threadIdx.x;
+  int rank = 0;
+  for (int t = 0; t < 64; ++t) {
+    const double kt = S.key[t];
+    rank += (kt < key || (kt == key && t < lane)) ? 1 : 0;
+  }
+  return rank;
+}
+
+// Processes one batch of candidates (one per lane).  The polytope only
+// shrinks, so a candidate whose plane misses every current vertex can never
+// cut later and is dropped at once; the others are clipped nearest first.
+// Returns false when the cell became empty or overflowed (state in status).
 template <int SPL, int PM, typename EOT>
-__device__ bool process_cands(Shared<SPL, PM>& S, EOT* eo, Poly<SPL>& P, int& nplanes, int& status, const Cand& c,
+__device__ bool process_batch(Shared<SPL, PM>& S, EOT* eo, Poly<SPL>& P, int& nplanes, int& status, const Cand& c,
                               int self_orig, int& work) {
-  uint64_t mask = __ballot(c.ok && may_cut(P, c.mx, c.my, c.mz, c.mm, c.h));
-  while (mask) {
+  const int lane = threadIdx.x;
+  const bool f = c.ok && (c.mm == 0.0 || (may_cut(P, c.mx, c.my, c.mz, c.mm, c.h) &&
+                                          cuts_vertices(S, P.ntri, c.mx, c.my, c.mz, c.h)));
+  const uint64_t fm = __ballot(f);
+  if (fm == 0ull) return true;
+  const int nflag = __popcll(fm);
+  S.key[lane] = f ? c.mm : INFINITY;
+  __syncthreads();
+  if (f) {
+    const int r = lane_rank(S, c.mm);
+    S.cpl[r][0] = c.mx; S.cpl[r][1] = c.my; S.cpl[r][2] = c.mz; S.cpl[r][3] = c.mm; S.cpl[r][4] = c.h;
+    S.corig[r] = c.orig;
+  }
+  __syncthreads();
+  for (int r = 0; r < nflag; ++r) {
     if (++work > WORK_LIMIT) {
       status = OVER_W;
       return false;
     }
-    const int t = __ffsll((long long)mask) - 1;
-    mask &= mask - 1;
-    const double mx = __shfl(c.mx, t, 64), my = __shfl(c.my, t, 64), mz = __shfl(c.mz, t, 64);
-    const double mm = __shfl(c.mm, t, 64), h = __shfl(c.h, t, 64);
-    const int orig = __shfl(c.orig, t, 64);
+    const double mx = S.cpl[r][0], my = S.cpl[r][1], mz = S.cpl[r][2], mm = S.cpl[r][3], h = S.cpl[r][4];
+    const int orig = S.corig[r];
     if (mm == 0.0) {
       // coincident sites: the one with the smaller weight (or, on a tie,
       // the larger index) owns nothing
@@ -508,7 +521,7 @@ __device__ bool process_cands(Shared<SPL, PM>& S, EOT* eo, Poly<SPL>& P, int& np
         return false;
       }
     }
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
       S.pl[nplanes][0] = mx; S.pl[nplanes][1] = my; S.pl[nplanes][2] = mz; S.pl[nplanes][3] = h;
       S.nb[nplanes] = orig;
     }
@@ -577,6 +590,9 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
     P.y[0] = sy > 0 ? bh[2] : -bh[3];
     P.z[0] = sz > 0 ? bh[4] : -bh[5];
   }
+  if (lane < 8) {
+    S.tpos[lane][0] = P.x[0]; S.tpos[lane][1] = P.y[0]; S.tpos[lane][2] = P.z[0];
+  }
   __syncthreads();
   if (lane < 8) reg_edges<PM>(eo, P.id[0], lane);
   __syncthreads();
@@ -598,8 +614,8 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
       d2 = dx * dx + dy * dy + dz * dz;
     }
     dmax = fmax(sqrt(wave_max_d(d2)), 1e-6);
-    const Cand c = sorted_cands(sp, sidx, j, ok, px, py, pz, wi);
-    process_cands(S, eo, P, nplanes, status, c, self, work);
+    const Cand c = load_cand(sp, sidx, j, ok, px, py, pz, wi);
+    process_batch(S, eo, P, nplanes, status, c, self, work);
   }
 
   // phase 2: the other sites in rings of doubling radius [dmin, dmax) around
@@ -629,10 +645,10 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
         const Cand c0 = load_cand(sp, sidx, j, ok, px, py, pz, wi);
         const bool beyond = ok && c0.mm >= dmax * dmax;
         if (__ballot(beyond && may_cut(P, c0.mx, c0.my, c0.mz, c0.mm, c0.h)) != 0ull) skipped = true;
-        const bool inring = ok && !beyond && c0.mm >= dmin * dmin;
-        if (__ballot(inring) == 0ull) continue;
-        const Cand c = sorted_cands(sp, sidx, j, inring, px, py, pz, wi);
-        if (!process_cands(S, eo, P, nplanes, status, c, self, work)) break;
+        Cand c = c0;
+        c.ok = ok && !beyond && c0.mm >= dmin * dmin;
+        if (__ballot(c.ok) == 0ull) continue;
+        if (!process_batch(S, eo, P, nplanes, status, c, self, work)) break;
         continue;
       }
       // children are nodes of level L-1
@@ -665,42 +681,30 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
         if (keep) dkey = dx * dx + dy * dy + dz * dz;
       }
       if (__ballot(valid && skipped) != 0ull) skipped = true;
-      // order the surviving children by box distance, nearest last on the stack
-      int dlane = lane;
-      for (int kk = 2; kk <= 64; kk <<= 1) {
-        for (int st = kk >> 1; st > 0; st >>= 1) {
-          const double ok = __shfl_xor(dkey, st, 64);
-          const int ol = __shfl_xor(dlane, st, 64);
-          const bool up = (lane & kk) == 0;
-          const bool lower = (lane & st) == 0;
-          const bool take = lower ? (up ? (ok < dkey) : (ok > dkey)) : (up ? (ok > dkey) : (ok < dkey));
-          if (take) { dkey = ok; dlane = ol; }
+      // exact per-vertex test, one child box per lane: can any site in the
+      // box beat p_i at a vertex of the current polytope?
+      bool cut = false;
+      if (keep) {
+        for (int t = 0; t < P.ntri && !cut; ++t) {
+          const double vx = S.tpos[t][0], vy = S.tpos[t][1], vz = S.tpos[t][2];
+          const double dx = fmax(0.0, fmax(lx - vx, vx - hx));
+          const double dy = fmax(0.0, fmax(ly - vy, vy - hy));
+          const double dz = fmax(0.0, fmax(lz - vz, vz - hz));
+          cut = dx * dx + dy * dy + dz * dz - W < vx * vx + vy * vy + vz * vz - wi;
         }
       }
-      const int nkeep = __popcll(__ballot(keep));
-      for (int r = nkeep - 1; r >= 0; --r) {
-        const int t = __shfl(dlane, r, 64);
-        const double blx = __shfl(lx, t, 64), bly = __shfl(ly, t, 64), blz = __shfl(lz, t, 64);
-        const double bhx = __shfl(hx, t, 64), bhy = __shfl(hy, t, 64), bhz = __shfl(hz, t, 64);
-        const double bw = __shfl(W, t, 64);
-        // exact per-vertex test: can any site in the box beat p_i at a vertex?
-        bool cut = false;
-#pragma unroll
-        for (int s = 0; s < SPL; ++s) {
-          if (lane + 64 * s >= P.ntri) continue;
-          const double vx = P.x[s], vy = P.y[s], vz = P.z[s];
-          const double dx = fmax(0.0, fmax(blx - vx, vx - bhx));
-          const double dy = fmax(0.0, fmax(bly - vy, vy - bhy));
-          const double dz = fmax(0.0, fmax(blz - vz, vz - bhz));
-          const double pw_box = dx * dx + dy * dy + dz * dz - bw;
-          const double pw_me = vx * vx + vy * vy + vz * vz - wi;
-          cut |= pw_box < pw_me;
+      const uint64_t cm = __ballot(cut);
+      if (cm != 0ull) {
+        const int nc = __popcll(cm);
+        if (top + nc > STACK) {
+          status = OVER_S;
+          break;
         }
-        if (__ballot(cut) != 0ull) {
-          if (top >= STACK) { status = OVER_S; break; }
-          if (lane == 0) S.stack[top] = ((L - 1) << 24) | (int)(idx * 64 + t);
-          ++top;
-        }
+        // nearest child on top of the stack
+        S.key[lane] = cut ? dkey : INFINITY;
+        __syncthreads();
+        if (cut) S.stack[top + nc - 1 - lane_rank(S, dkey)] = ((L - 1) << 24) | (int)(idx * 64 + lane);
+        top += nc;
       }
       __syncthreads();
     }

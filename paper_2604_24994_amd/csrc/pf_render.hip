@@ -10,7 +10,9 @@
 //                 memory fallback for long lists)
 //   k_raster      one 256-thread workgroup per 16x16 tile, one lane per
 //                 pixel, each wave an 8x8 quadrant walking the tile's list
-//                 front to back with wave-uniform cell loads
+//                 front to back; the list and the cells' records are staged
+//                 in LDS 256 entries at a time by the whole workgroup, so a
+//                 cell that misses the quadrant costs no memory latency
 // Trace, per view (Sec. 3.2, ray tracing; appendix C):
 //   k_start_*     argmin power distance from the camera centre
 //   k_trace       one lane per ray; per step the piece of the current cell
@@ -239,31 +241,7 @@ struct SceneDev {
   float tau;
 };
 
-// One contribution of cell ci to the lane's pixel; returns false when the
-// lane's ray misses the cell's cull ball.
-__device__ inline void contribute(const SceneDev& S, const RayD& R, int ci, bool live, float& T, float& cr,
-                                  float& cg, float& cb) {
-  const float4 g = S.geo[ci];
-  const float rho = S.cull[ci];
-  const Local L = make_local(R, g.x, g.y, g.z);
-  const bool hit = live && (rho >= 0.0f) && (L.qq < (double)rho * (double)rho);
-  if (!__any(hit)) return;
-  const float* tx = S.tex + (int64_t)ci * (KD * TEXW);
-  if (hit) {
-    const int r0 = S.row[ci];
-    const Piece P = piece_geometry(R, L, g.w, S.plane + r0, S.nrast[ci], S.nrm[ci], tx, S.tau);
-    if (P.alpha > 0.0f) {
-      float r, gg, b;
-      radiance(tx, S.rgb + 3 * (int64_t)ci, P.ux, P.uy, R.fx, R.fy, R.fz, S.tau, r, gg, b);
-      const float wgt = T * P.alpha;
-      cr += wgt * r;
-      cg += wgt * gg;
-      cb += wgt * b;
-      T *= (1.0f - P.alpha);
-    }
-  }
-}
-
+constexpr int RB = 256;     // tile-list entries staged in LDS per batch
 constexpr int RBLK = 256;   // record slots reserved per wave at a time
 constexpr int SBLK = 32;    // segment slots reserved per wave at a time
 
@@ -290,6 +268,16 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
                                                 int32_t* __restrict__ rec_head,
                                                 unsigned long long* __restrict__ rec_counter,
                                                 int4* __restrict__ rec_seg, int64_t rec_cap, int64_t seg_cap) {
+  // the tile's sorted cells are staged RB at a time: list entry and the cell
+  // record fields every lane needs, loaded by the whole workgroup at once
+  __shared__ int s_ci[RB];
+  __shared__ float4 s_geo[RB];
+  __shared__ float4 s_nrm[RB];
+  __shared__ float s_rho[RB];
+  __shared__ int s_row[RB];
+  __shared__ int s_nr[RB];
+  __shared__ int s_more[4];
+
   // view of this tile: the last one whose tiles start at or before it
   int lo = 0, hi = nview - 1;
   while (lo < hi) {
@@ -308,20 +296,32 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
   bool live = inside && R.valid;
   float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
   int head = -1;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int pix = py * v.cam.width + px;
   const uint32_t e0 = tile_off[blockIdx.x], e1 = tile_off[blockIdx.x + 1];
   long long rblk = 0, sblk = 0;   // the wave's current record / segment block
   int rleft = 0, sleft = 0;
-  for (uint32_t e = e0; e < e1; ++e) {
-    if (!__any(live)) break;
-    const int ci = __builtin_amdgcn_readfirstlane((int)(uint32_t)list[e]);
-    if constexpr (!STORE) {
-      contribute(S, R, ci, live, T, cr, cg, cb);
-    } else {
-      const float4 g = S.geo[ci];
-      const float rho = S.cull[ci];
+  for (uint32_t b0 = e0; b0 < e1; b0 += RB) {
+    {
+      const uint32_t e = b0 + threadIdx.x;
+      if (e < e1) {
+        const int c = (int)(uint32_t)list[e];
+        s_ci[threadIdx.x] = c;
+        s_geo[threadIdx.x] = S.geo[c];
+        s_nrm[threadIdx.x] = S.nrm[c];
+        s_rho[threadIdx.x] = S.cull[c];
+        s_row[threadIdx.x] = S.row[c];
+        s_nr[threadIdx.x] = S.nrast[c];
+      }
+    }
+    __syncthreads();
+    const int nb = (int)min((uint32_t)RB, e1 - b0);
+    for (int q = 0; q < nb; ++q) {
+      if (!__any(live)) break;
+      const int ci = __builtin_amdgcn_readfirstlane(s_ci[q]);
+      const float4 g = s_geo[q];
+      const float rho = s_rho[q];
       const Local L = make_local(R, g.x, g.y, g.z);
       const bool hit = live && (rho >= 0.0f) && (L.qq < (double)rho * (double)rho);
       if (!__any(hit)) continue;
@@ -330,51 +330,61 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
       P.alpha = 0.0f;
       float r = 0.0f, gg = 0.0f, b = 0.0f;
       if (hit) {
-        const int r0 = S.row[ci];
-        P = piece_geometry(R, L, g.w, S.plane + r0, S.nrast[ci], S.nrm[ci], tx, S.tau);
+        P = piece_geometry(R, L, g.w, S.plane + __builtin_amdgcn_readfirstlane(s_row[q]),
+                           __builtin_amdgcn_readfirstlane(s_nr[q]), s_nrm[q], tx, S.tau);
         if (P.alpha > 0.0f) radiance(tx, S.rgb + 3 * (int64_t)ci, P.ux, P.uy, R.fx, R.fy, R.fz, S.tau, r, gg, b);
       }
       const bool contrib = hit && P.alpha > 0.0f;
-      const uint64_t m = __ballot(contrib);
-      if (m) {
-        // slots come from the wave's own blocks; a new block is reserved
-        // with one global atomic when the current one cannot take the append
-        const int cnt = __popcll(m);
-        if (cnt > rleft) {
-          unsigned long long b = 0;
-          if (lane == 0) b = atomicAdd(&rec_counter[0], (unsigned long long)RBLK);
-          rblk = (long long)bcast64(b);
-          rleft = RBLK;
-        }
-        if (sleft == 0) {
-          unsigned long long b = 0;
-          if (lane == 0) b = atomicAdd(&rec_counter[1], (unsigned long long)SBLK);
-          sblk = (long long)bcast64(b);
-          sleft = SBLK;
-        }
-        const long long base = rblk, sg = sblk;
-        rblk += cnt;
-        rleft -= cnt;
-        sblk += 1;
-        sleft -= 1;
-        if (lane == 0 && sg < seg_cap && base + cnt <= rec_cap) rec_seg[sg] = make_int4(ci, (int)base, cnt, 0);
-        if (contrib) {
-          const long long slot = base + __popcll(m & lt);
-          if (slot < rec_cap) {
-            rec_ri[slot] = make_int4(ci, pix, head, (view << 20) | ((P.bind0 + 2) << 10) | (P.bind1 + 2));
-            rec_rf[slot] = make_float4(P.alpha, r, gg, b);
-            rec_rt[slot] = T;
-            head = (int)slot;
+      if constexpr (STORE) {
+        const uint64_t m = __ballot(contrib);
+        if (m) {
+          // slots come from the wave's own blocks; a new block is reserved
+          // with one global atomic when the current one cannot take the append
+          const int cnt = __popcll(m);
+          if (cnt > rleft) {
+            unsigned long long bk = 0;
+            if (lane == 0) bk = atomicAdd(&rec_counter[0], (unsigned long long)RBLK);
+            rblk = (long long)bcast64(bk);
+            rleft = RBLK;
           }
-          const float wgt = T * P.alpha;
-          cr += wgt * r;
-          cg += wgt * gg;
-          cb += wgt * b;
-          T *= (1.0f - P.alpha);
+          if (sleft == 0) {
+            unsigned long long bk = 0;
+            if (lane == 0) bk = atomicAdd(&rec_counter[1], (unsigned long long)SBLK);
+            sblk = (long long)bcast64(bk);
+            sleft = SBLK;
+          }
+          const long long base = rblk, sg = sblk;
+          rblk += cnt;
+          rleft -= cnt;
+          sblk += 1;
+          sleft -= 1;
+          if (lane == 0 && sg < seg_cap && base + cnt <= rec_cap) rec_seg[sg] = make_int4(ci, (int)base, cnt, 0);
+          if (contrib) {
+            const long long slot = base + __popcll(m & lt);
+            if (slot < rec_cap) {
+              rec_ri[slot] = make_int4(ci, pix, head, (view << 20) | ((P.bind0 + 2) << 10) | (P.bind1 + 2));
+              rec_rf[slot] = make_float4(P.alpha, r, gg, b);
+              rec_rt[slot] = T;
+              head = (int)slot;
+            }
+          }
         }
       }
+      if (contrib) {
+        const float wgt = T * P.alpha;
+        cr += wgt * r;
+        cg += wgt * gg;
+        cb += wgt * b;
+        T *= (1.0f - P.alpha);
+      }
+      live = live && (T >= t_min);
     }
-    live = live && (T >= t_min);
+    const bool wl = __any(live);
+    if (lane == 0) s_more[wave] = wl ? 1 : 0;
+    __syncthreads();
+    const bool more = (s_more[0] | s_more[1] | s_more[2] | s_more[3]) != 0;
+    __syncthreads();
+    if (!more) break;
   }
   if (inside) {
     float* o = rgba + 4 * ((int64_t)py * v.cam.width + px);
