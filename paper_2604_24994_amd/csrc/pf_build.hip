@@ -60,9 +60,38 @@ __device__ inline float wave_max(float x) {
   for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
   return x;
 }
+// Wave-wide reductions of a double with DPP moves (all 64 lanes active):
+// butterflies within rows of 16 lanes, then the row broadcasts of lanes 15
+// and 31 leave the result in lane 63, which is read back to every lane.
+template <int CTRL, int ROW_MASK>
+__device__ inline double dpp_d(double x, double old) {
+  const long long xb = __double_as_longlong(x), ob = __double_as_longlong(old);
+  const int lo = __builtin_amdgcn_update_dpp((int)ob, (int)xb, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(ob >> 32), (int)(xb >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline double lane63_d(double x) {
+  const long long xb = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)xb, 63), hi = __builtin_amdgcn_readlane((int)(xb >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 __device__ inline double wave_max_d(double x) {
-  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
-  return x;
+  x = fmax(x, dpp_d<0xB1, 0xf>(x, -INFINITY));    // quad perm [1,0,3,2]
+  x = fmax(x, dpp_d<0x4E, 0xf>(x, -INFINITY));    // quad perm [2,3,0,1]
+  x = fmax(x, dpp_d<0x141, 0xf>(x, -INFINITY));   // row half mirror
+  x = fmax(x, dpp_d<0x140, 0xf>(x, -INFINITY));   // row mirror
+  x = fmax(x, dpp_d<0x142, 0xa>(x, -INFINITY));   // row bcast 15
+  x = fmax(x, dpp_d<0x143, 0xc>(x, -INFINITY));   // row bcast 31
+  return lane63_d(x);
+}
+__device__ inline double wave_sum_d(double x) {
+  x += dpp_d<0xB1, 0xf>(x, 0.0);
+  x += dpp_d<0x4E, 0xf>(x, 0.0);
+  x += dpp_d<0x141, 0xf>(x, 0.0);
+  x += dpp_d<0x140, 0xf>(x, 0.0);
+  x += dpp_d<0x142, 0xa>(x, 0.0);
+  x += dpp_d<0x143, 0xc>(x, 0.0);
+  return lane63_d(x);
 }
 
 // Per-block partial bounds of the spheres and weights:
@@ -201,10 +230,6 @@ __device__ inline void unpack(int id, int& a, int& b, int& c) {
   c = (id >> 16) & 255;
 }
 
-__device__ inline double wave_sum_d(double x) {
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
-}
 
 template <int PM, typename EOT>
 __device__ inline void reg_edges(EOT* eo, int id, int slot) {
@@ -307,12 +332,15 @@ __device__ ClipResult clip(Shared<SPL, PM>& S, EOT* eo, Poly<SPL>& P, int kp, do
       my_new += e[3 * s + q] ? 1 : 0;
     }
   }
-  int incl = my_new;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int v = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += v;
+  // exclusive prefix sum and total of my_new (< 2^NB) from one ballot per bit
+  constexpr int NB = SPL <= 2 ? 3 : SPL <= 5 ? 4 : 5;
+  int excl = 0, total_new = 0;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const uint64_t bm = __ballot((my_new >> b) & 1);
+    excl += __popcll(bm & lt) << b;
+    total_new += __popcll(bm) << b;
   }
-  const int total_new = __shfl(incl, 63, 64);
   const int nkeep = P.ntri - nout;
   if (nkeep + total_new > NT) return OVER_V;
 
@@ -328,7 +356,7 @@ __device__ ClipResult clip(Shared<SPL, PM>& S, EOT* eo, Poly<SPL>& P, int kp, do
     }
     kbase += __popcll(kb);
   }
-  int pos = nkeep + incl - my_new;
+  int pos = nkeep + excl;
 #pragma unroll
   for (int q = 0; q < 3 * SPL; ++q) {
     if (e[q]) {
@@ -466,10 +494,12 @@ __device__ inline bool cuts_vertices(const Shared<SPL, PM>& S, int ntri, double 
 // Number of flagged lanes whose key orders before this lane's (ties by
 // lane); keys of the wave in S.key.
 template <int SPL, int PM>
-__device__ inline int lane_rank(const Shared<SPL, PM>& S, double key) {
+__device__ inline int lane_rank(const Shared<SPL, PM>& S, uint64_t flagged, double key) {
   const int lane = threadIdx.x;
   int rank = 0;
-  for (int t = 0; t < 64; ++t) {
+  while (flagged) {
+    const int t = __ffsll((long long)flagged) - 1;
+    flagged &= flagged - 1;
     const double kt = S.key[t];
     rank += (kt < key || (kt == key && t < lane)) ? 1 : 0;
   }
@@ -492,7 +522,7 @@ __device__ bool process_batch(Shared<SPL, PM>& S, EOT* eo, Poly<SPL>& P, int& np
   S.key[lane] = f ? c.mm : INFINITY;
   __syncthreads();
   if (f) {
-    const int r = lane_rank(S, c.mm);
+    const int r = lane_rank(S, fm, c.mm);
     S.cpl[r][0] = c.mx; S.cpl[r][1] = c.my; S.cpl[r][2] = c.mz; S.cpl[r][3] = c.mm; S.cpl[r][4] = c.h;
     S.corig[r] = c.orig;
   }
@@ -618,11 +648,12 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
     process_batch(S, eo, P, nplanes, status, c, self, work);
   }
 
-  // phase 2: the other sites in rings of doubling radius [dmin, dmax) around
-  // p_i, so that candidates come roughly nearest first across the whole tree
-  // (this keeps the transient polytope small).  Each ring walks the tree
-  // depth first, nearest child first, pruning by the current polytope; a
-  // ring that left no prunable work beyond dmax ends the search.
+  // phase 2: the sites within the own leaf's radius dmax first (nearest
+  // first across the whole tree, which keeps the transient polytope small),
+  // then every remaining site in one more traversal.  Each traversal walks
+  // the tree depth first, nearest child first, pruning by the current
+  // polytope; a first traversal that left no prunable work beyond dmax ends
+  // the search.
   double dmin = 0.0;
   while (status == CUT) {
     bool skipped = false;
@@ -703,14 +734,16 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
         // nearest child on top of the stack
         S.key[lane] = cut ? dkey : INFINITY;
         __syncthreads();
-        if (cut) S.stack[top + nc - 1 - lane_rank(S, dkey)] = ((L - 1) << 24) | (int)(idx * 64 + lane);
+        if (cut) S.stack[top + nc - 1 - lane_rank(S, cm, dkey)] = ((L - 1) << 24) | (int)(idx * 64 + lane);
         top += nc;
       }
       __syncthreads();
     }
     if (!skipped) break;
+    // after the first ring the polytope is close to final; the rest of the
+    // tree is checked in one unrestricted traversal (no per-ring restarts)
     dmin = dmax;
-    dmax *= 2.0;
+    dmax = INFINITY;
   }
 
   // --- outputs
@@ -935,34 +968,42 @@ pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipSt
   k_gather_sites<<<g256, 256, 0, s>>>(prm.p, prm.power, order.p, n, sp.p, sidx.p);
   PF_HIP_TRY(hipGetLastError());
 
-  // implicit 64-ary tree
-  Levels lv{};
-  lv.cnt[0] = n;
-  long long total_nodes = 0;
-  int L = 0;
-  do {
-    ++L;
-    if (L > MAXLVL) {
-      set_error("pf_build_scene: too many sites for the build tree");
-      return PF_ERR_UNSUPPORTED;
+  // implicit 64-ary tree over n sorted sites: per node the box of its sites
+  // and their largest weight
+  auto build_tree = [&](const float4* sites, int64_t count, Levels& lvl, DevBuf<float4>& lo_b,
+                        DevBuf<float4>& hi_b) -> pf_status {
+    lvl = Levels{};
+    lvl.cnt[0] = count;
+    long long total_nodes = 0;
+    int L = 0;
+    do {
+      ++L;
+      if (L > MAXLVL) {
+        set_error("pf_build_scene: too many sites for the build tree");
+        return PF_ERR_UNSUPPORTED;
+      }
+      lvl.cnt[L] = (lvl.cnt[L - 1] + 63) / 64;
+      lvl.off[L] = total_nodes;
+      total_nodes += lvl.cnt[L];
+    } while (lvl.cnt[L] > 1);
+    lvl.n = L;
+    PF_HIP_TRY(lo_b.alloc(total_nodes));
+    PF_HIP_TRY(hi_b.alloc(total_nodes));
+    for (int l = 1; l <= lvl.n; ++l) {
+      const bool from_sites = l == 1;
+      k_tree_level<<<(unsigned)lvl.cnt[l], 64, 0, s>>>(from_sites ? sites : nullptr,
+                                                       from_sites ? nullptr : lo_b.p + lvl.off[l - 1],
+                                                       from_sites ? nullptr : hi_b.p + lvl.off[l - 1],
+                                                       lvl.cnt[l - 1], lo_b.p + lvl.off[l], hi_b.p + lvl.off[l]);
+      PF_HIP_TRY(hipGetLastError());
     }
-    lv.cnt[L] = (lv.cnt[L - 1] + 63) / 64;
-    lv.off[L] = total_nodes;
-    total_nodes += lv.cnt[L];
-  } while (lv.cnt[L] > 1);
-  lv.n = L;
-  // off[] is indexed by level; shift so that lv.off[L-1] addresses level L-1
-  // for L-1 >= 1 (level 0 = sites is never read through the node arrays).
+    return PF_OK;
+  };
+  Levels lv{};
   DevBuf<float4> nlo(s), nhi(s);
-  PF_HIP_TRY(nlo.alloc(total_nodes));
-  PF_HIP_TRY(nhi.alloc(total_nodes));
-  for (int l = 1; l <= lv.n; ++l) {
-    const bool from_sites = l == 1;
-    k_tree_level<<<(unsigned)lv.cnt[l], 64, 0, s>>>(from_sites ? sp.p : nullptr,
-                                                    from_sites ? nullptr : nlo.p + lv.off[l - 1],
-                                                    from_sites ? nullptr : nhi.p + lv.off[l - 1],
-                                                    lv.cnt[l - 1], nlo.p + lv.off[l], nhi.p + lv.off[l]);
-    PF_HIP_TRY(hipGetLastError());
+  {
+    const pf_status st = build_tree(sp.p, n, lv, nlo, nhi);
+    if (st != PF_OK) return st;
   }
 
   // per-cell clipping
