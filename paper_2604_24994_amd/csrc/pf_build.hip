@@ -31,7 +31,7 @@ namespace {
 
 constexpr int PM_BIG = 256;       // plane capacity of the high-degree pass
 constexpr int SPL_BIG = 8;        // vertex slots per lane of the high-degree pass
-constexpr int STACK = 512;
+constexpr int STACK = 256;       // traversal stack (tree depth x 63 + 64 entries suffice up to ~8M sites)
 constexpr int MAXLVL = 8;
 // Upper bound on candidate clips plus node visits per cell; a cell that
 // reaches it is reported as over capacity instead of running on.
@@ -206,8 +206,8 @@ struct Shared {
   unsigned char used[PM];
   unsigned short remap[PM];
   unsigned long long omask[SPL];  // removed-vertex masks of the current clip
-  double key[64];                 // per-lane ordering keys
-  double cpl[64][5];              // flagged candidates in processing order: m, |m|^2, h
+  float key[64];                  // per-lane ordering keys
+  double cpl[64][4];              // flagged candidates in processing order: m, h
   int corig[64];
 };
 
@@ -494,13 +494,13 @@ __device__ inline bool cuts_vertices(const Shared<SPL, PM>& S, int ntri, double 
 // Number of flagged lanes whose key orders before this lane's (ties by
 // lane); keys of the wave in S.key.
 template <int SPL, int PM>
-__device__ inline int lane_rank(const Shared<SPL, PM>& S, uint64_t flagged, double key) {
+__device__ inline int lane_rank(const Shared<SPL, PM>& S, uint64_t flagged, float key) {
   const int lane = threadIdx.x;
   int rank = 0;
   while (flagged) {
     const int t = __ffsll((long long)flagged) - 1;
     flagged &= flagged - 1;
-    const double kt = S.key[t];
+    const float kt = S.key[t];
     rank += (kt < key || (kt == key && t < lane)) ? 1 : 0;
   }
   return rank;
@@ -519,11 +519,11 @@ __device__ bool process_batch(Shared<SPL, PM>& S, EOT* eo, Poly<SPL>& P, int& np
   const uint64_t fm = __ballot(f);
   if (fm == 0ull) return true;
   const int nflag = __popcll(fm);
-  S.key[lane] = f ? c.mm : INFINITY;
+  S.key[lane] = f ? (float)c.mm : INFINITY;
   __syncthreads();
   if (f) {
-    const int r = lane_rank(S, fm, c.mm);
-    S.cpl[r][0] = c.mx; S.cpl[r][1] = c.my; S.cpl[r][2] = c.mz; S.cpl[r][3] = c.mm; S.cpl[r][4] = c.h;
+    const int r = lane_rank(S, fm, (float)c.mm);
+    S.cpl[r][0] = c.mx; S.cpl[r][1] = c.my; S.cpl[r][2] = c.mz; S.cpl[r][3] = c.h;
     S.corig[r] = c.orig;
   }
   __syncthreads();
@@ -532,7 +532,8 @@ __device__ bool process_batch(Shared<SPL, PM>& S, EOT* eo, Poly<SPL>& P, int& np
       status = OVER_W;
       return false;
     }
-    const double mx = S.cpl[r][0], my = S.cpl[r][1], mz = S.cpl[r][2], mm = S.cpl[r][3], h = S.cpl[r][4];
+    const double mx = S.cpl[r][0], my = S.cpl[r][1], mz = S.cpl[r][2], h = S.cpl[r][3];
+    const double mm = mx * mx + my * my + mz * mz;
     const int orig = S.corig[r];
     if (mm == 0.0) {
       // coincident sites: the one with the smaller weight (or, on a tie,
@@ -732,9 +733,9 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
           break;
         }
         // nearest child on top of the stack
-        S.key[lane] = cut ? dkey : INFINITY;
+        S.key[lane] = cut ? (float)dkey : INFINITY;
         __syncthreads();
-        if (cut) S.stack[top + nc - 1 - lane_rank(S, cm, dkey)] = ((L - 1) << 24) | (int)(idx * 64 + lane);
+        if (cut) S.stack[top + nc - 1 - lane_rank(S, cm, (float)dkey)] = ((L - 1) << 24) | (int)(idx * 64 + lane);
         top += nc;
       }
       __syncthreads();

@@ -14,7 +14,7 @@ constexpr int KD = 8;              // detail sites per face (built variant)
 constexpr int MA = 8;              // Spherical-Voronoi axes per detail site
 constexpr int TEXW = 3 + 6 * MA;   // floats per (cell, detail site)
 constexpr int TILE = 16;           // raster tile edge in pixels
-constexpr int FACE_CAP = 96;       // faces per cell incl. domain-box faces
+constexpr int FACE_CAP = 64;       // planes / faces per cell in the main build pass (larger cells take a second pass)
 constexpr int LEAF = 64;           // sites per leaf of the build tree
 
 // Per-cell flags written by the build.
