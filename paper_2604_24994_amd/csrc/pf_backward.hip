@@ -117,47 +117,45 @@ __device__ inline void sum_to(float* acc, int i, bool valid, float v) {
 
 __device__ inline float softplus_b(float x) { return x > 20.0f ? x : log1pf(expf(x)); }
 
-// Soft-Voronoi weights in float64 with the shifted logits of sv_weights.
-__device__ inline void sv_weights_d(const float* __restrict__ tx, double ux, double uy, double tau, double* w) {
-  const double un = sqrt(ux * ux + uy * uy);
-  double mx = -INFINITY;
-#pragma unroll
-  for (int k = 0; k < KD; ++k) {
-    const double sx = tx[k * TEXW + 0], sy = tx[k * TEXW + 1];
-    const double ex = ux - sx, ey = uy - sy;
-    const double dist = sqrt(ex * ex + ey * ey);
-    const double num = sx * sx + sy * sy - 2.0 * (ux * sx + uy * sy);
-    const double den = dist + un;
-    w[k] = den > 0.0 ? -tau * num / den : 0.0;
-    mx = fmax(mx, w[k]);
-  }
-  double sum = 0.0;
-#pragma unroll
-  for (int k = 0; k < KD; ++k) {
-    w[k] = exp(w[k] - mx);
-    sum += w[k];
-  }
-#pragma unroll
-  for (int k = 0; k < KD; ++k) w[k] /= sum;
+// 1/x in float64: hardware reciprocal refined by two Newton steps (x != 0).
+__device__ inline double rcp_d(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
 }
 
-// d/du of the shifted logit |u - s| - |u| (the softmax is shift invariant):
-// (u - s)/|u - s| - u/|u|, written without cancellation as
-// (-u (|u - s| - |u|) - s |u|) / (|u - s| |u|).
-__device__ inline void dlogit_du(double ux, double uy, double sx, double sy, double& gx, double& gy) {
+// Softmax backward of the soft-Voronoi weights at texture point u (float64).
+// With z_k = -tau (|u - s_k| - |u|) and ge_k = dL/dz_k, accumulates dL/du
+// into (gux, guy) and the wave's sum of dL/ds_k into acc.  d/du of the shifted
+// logit, (u - s)/|u - s| - u/|u|, is evaluated as
+// (-u (|u - s| - |u|) - s |u|) / (|u - s| |u|), which stays accurate when u
+// is far from the sites (grazing rays).
+__device__ inline void sv_backward(const float* __restrict__ tx, double ux, double uy, const double* ge, double& gux,
+                                   double& guy, float* acc, bool valid) {
   const double un = sqrt(ux * ux + uy * uy);
-  const double ex = ux - sx, ey = uy - sy;
-  const double dist = sqrt(ex * ex + ey * ey);
-  if (un == 0.0 || dist == 0.0) {
-    const double id = dist > 0.0 ? 1.0 / dist : 0.0;
-    gx = ex * id;
-    gy = ey * id;
-    return;
+  const double iun = un > 0.0 ? rcp_d(un) : 0.0;
+#pragma unroll
+  for (int k = 0; k < KD; ++k) {
+    const double sx = tx[k * TEXW], sy = tx[k * TEXW + 1];
+    const double ex = ux - sx, ey = uy - sy;
+    const double dist = sqrt(ex * ex + ey * ey);
+    const double rd = dist > 0.0 ? rcp_d(dist) : 0.0;
+    double lx, ly;
+    if (un > 0.0 && dist > 0.0) {
+      const double e = (sx * sx + sy * sy - 2.0 * (ux * sx + uy * sy)) * rcp_d(dist + un);   // |u - s| - |u|
+      const double f = rd * iun;
+      lx = (-ux * e - sx * un) * f;
+      ly = (-uy * e - sy * un) * f;
+    } else {
+      lx = ex * rd;
+      ly = ey * rd;
+    }
+    gux += ge[k] * lx;
+    guy += ge[k] * ly;
+    sum_to(acc, NCELL + 3 * k, valid, (float)(-ge[k] * ex * rd));
+    sum_to(acc, NCELL + 3 * k + 1, valid, (float)(-ge[k] * ey * rd));
   }
-  const double e = (sx * sx + sy * sy - 2.0 * (ux * sx + uy * sy)) / (dist + un);   // |u - s| - |u|
-  const double inv = 1.0 / (dist * un);
-  gx = (-ux * e - sx * un) * inv;
-  gy = (-uy * e - sy * un) * inv;
 }
 
 __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) k_bwd_cell(
@@ -194,8 +192,9 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
   const double dnx = nrx * dninv, dny = nry * dninv, dnz = nrz * dninv;
   const double dsg = copysign(1.0, dnz);
   double d1x, d1y, d1z, d2x, d2y, d2z;
+  const double oa = -1.0 / (dsg + dnz);   // Duff et al. frame constant
   {
-    const double a = -1.0 / (dsg + dnz);
+    const double a = oa;
     const double b = dnx * dny * a;
     d1x = 1.0 + dsg * dnx * dnx * a;
     d1y = dsg * b;
@@ -263,25 +262,19 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     const double dt2 = ddx * d2x + ddy * d2y + ddz * d2z;
     const bool nzden = den != 0.0;
     double idn = 0.0, sbar = 0.0, sxx = 0.0, delta = 0.0;
-    float wd[KD];   // displacement weights at ubar (float64 while summed)
+    float wd[KD];   // displacement weights at ubar
     double ubx = 0.0, uby = 0.0;
     double j0 = s0, j1 = s1;
     int sel0 = 0, sel1 = 0;   // 1: the end is the displaced face
     double ux, uy, S;
     if (nzden) {
-      idn = 1.0 / den;
+      idn = rcp_d(den);
       sbar = -qn * idn;
       ubx = qt1 + sbar * dt1;
       uby = qt2 + sbar * dt2;
-      {
-        double w64[KD];
-        sv_weights_d(tx, ubx, uby, (double)tau, w64);
+      sv_weights(tx, (float)ubx, (float)uby, tau, wd);
 #pragma unroll
-        for (int k = 0; k < KD; ++k) {
-          delta += w64[k] * (double)tx[k * TEXW + 2];
-          wd[k] = (float)w64[k];
-        }
-      }
+      for (int k = 0; k < KD; ++k) delta += (double)wd[k] * (double)tx[k * TEXW + 2];
       sxx = (delta - qn) * idn;
       if (den > 0.0) {
         sel1 = sxx < (double)s1;
@@ -317,12 +310,7 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     // ---------------- radiance: weights at u, the sites' Spherical-Voronoi
     // colours sv_k(d) and the softmax backward of the weights
     float wr[KD];
-    {
-      double w64[KD];
-      sv_weights_d(tx, ux, uy, (double)tau, w64);
-#pragma unroll
-      for (int k = 0; k < KD; ++k) wr[k] = (float)w64[k];
-    }
+    sv_weights(tx, (float)ux, (float)uy, tau, wr);
     double sum_wg = 0.0;
     float gwr[KD];
 #pragma unroll
@@ -351,18 +339,11 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
       st_k[k][lane] = make_float2(wi > 0.0f ? mx - __logf(wi) : INFINITY, gwr[k]);
     }
     double gux = 0.0, guy = 0.0;
+    {
+      double ge[KD];
 #pragma unroll
-    for (int k = 0; k < KD; ++k) {
-      const double ge = -(double)tau * (double)wr[k] * ((double)gwr[k] - sum_wg);   // z_k = -tau(|u - s_k| - |u|)
-      double lx, ly;
-      dlogit_du(ux, uy, tx[k * TEXW], tx[k * TEXW + 1], lx, ly);
-      gux += ge * lx;
-      guy += ge * ly;
-      const double ex = ux - tx[k * TEXW], ey = uy - tx[k * TEXW + 1];
-      const double dist = sqrt(ex * ex + ey * ey);
-      const double id = dist > 0.0 ? 1.0 / dist : 0.0;
-      sum_to(acc, NCELL + 3 * k, valid, (float)(-ge * ex * id));
-      sum_to(acc, NCELL + 3 * k + 1, valid, (float)(-ge * ey * id));
+      for (int k = 0; k < KD; ++k) ge[k] = -(double)tau * (double)wr[k] * ((double)gwr[k] - sum_wg);
+      sv_backward(tx, ux, uy, ge, gux, guy, acc, valid);
     }
     // u = (qt1 + S dt1, qt2 + S dt2)
     double g_qt1 = gux, g_qt2 = guy, g_dt1 = gux * S, g_dt2 = guy * S;
@@ -385,18 +366,11 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
         sum_w += (double)wd[k] * gw[k];
       }
       double gubx = 0.0, guby = 0.0;
+      {
+        double ge[KD];
 #pragma unroll
-      for (int k = 0; k < KD; ++k) {
-        const double ge = -(double)tau * (double)wd[k] * (gw[k] - sum_w);
-        double lx, ly;
-        dlogit_du(ubx, uby, tx[k * TEXW], tx[k * TEXW + 1], lx, ly);
-        gubx += ge * lx;
-        guby += ge * ly;
-        const double ex = ubx - tx[k * TEXW], ey = uby - tx[k * TEXW + 1];
-        const double dist = sqrt(ex * ex + ey * ey);
-        const double id = dist > 0.0 ? 1.0 / dist : 0.0;
-        sum_to(acc, NCELL + 3 * k, valid, (float)(-ge * ex * id));
-        sum_to(acc, NCELL + 3 * k + 1, valid, (float)(-ge * ey * id));
+        for (int k = 0; k < KD; ++k) ge[k] = -(double)tau * (double)wd[k] * (gw[k] - sum_w);
+        sv_backward(tx, ubx, uby, ge, gubx, guby, acc, valid);
       }
       // ubar = (qt1 + sbar dt1, qt2 + sbar dt2), sbar = -qn/den
       g_qt1 += gubx;
@@ -417,7 +391,6 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     const double g2x = g_qt2 * qdx + g_dt2 * ddx, g2y = g_qt2 * qdy + g_dt2 * ddy, g2z = g_qt2 * qdz + g_dt2 * ddz;
     // orthonormal basis of Duff et al. (JCGT 2017), differentiated
     const double sg = dsg;
-    const double oa = -1.0 / (sg + dnz);
     const double oa2 = oa * oa;
     double gnxd = gnx_h + g1x * (2.0 * sg * dnx * oa) + g1y * sg * dny * oa - g1z * sg + g2x * dny * oa;
     double gnyd = gny_h + g1y * sg * dnx * oa + g2x * dnx * oa + g2y * 2.0 * dny * oa - g2z;
