@@ -111,6 +111,7 @@ typedef struct {
   int64_t n_faces;           /* total directed faces in the adjacency         */
   int64_t n_hidden;          /* cells whose bounded cell is empty             */
   int64_t n_overflow;        /* cells whose build exceeded a capacity (0)     */
+  int64_t n_high_degree;     /* cells that took the high-degree build pass    */
   float box_min[3], box_max[3];
 } pf_scene_info;
 

@@ -29,10 +29,13 @@
 namespace pf {
 namespace {
 
-constexpr int PM_BIG = 256;       // plane capacity of the high-degree pass
-constexpr int SPL_BIG = 8;        // vertex slots per lane of the high-degree pass
+constexpr int PM_MID = 128;       // plane capacity of the second pass (edge table in LDS)
+constexpr int SPL_MID = 4;        // vertex slots per lane of the second pass
+constexpr int PM_BIG = 256;       // plane capacity of the third pass (edge table in HBM)
+constexpr int SPL_BIG = 8;        // vertex slots per lane of the third pass
 constexpr int STACK = 256;       // traversal stack (tree depth x 63 + 64 entries suffice up to ~8M sites)
 constexpr int MAXLVL = 8;
+constexpr int RING_K = 16;        // rank of the leaf mate that sets the first ring radius
 // Upper bound on candidate clips plus node visits per cell; a cell that
 // reaches it is reported as over capacity instead of running on.
 constexpr int WORK_LIMIT = 1 << 22;
@@ -508,7 +511,8 @@ __device__ inline int lane_rank(const Shared<SPL, PM>& S, uint64_t flagged, floa
 
 // Processes one batch of candidates (one per lane).  The polytope only
 // shrinks, so a candidate whose plane misses every current vertex can never
-// cut later and is dropped at once; the others are clipped nearest first.
+// cut later and is dropped at once; the others are clipped in order of
+// their bisector's offset from p_i (most constraining first).
 // Returns false when the cell became empty or overflowed (state in status).
 template <int SPL, int PM, typename EOT>
 __device__ bool process_batch(Shared<SPL, PM>& S, EOT* eo, Poly<SPL>& P, int& nplanes, int& status, const Cand& c,
@@ -519,10 +523,13 @@ __device__ bool process_batch(Shared<SPL, PM>& S, EOT* eo, Poly<SPL>& P, int& np
   const uint64_t fm = __ballot(f);
   if (fm == 0ull) return true;
   const int nflag = __popcll(fm);
-  S.key[lane] = f ? (float)c.mm : INFINITY;
+  // most constraining first: order by the plane's offset from p_i, h/|m|
+  // (coincident sites first)
+  const float okey = c.mm > 0.0 ? (float)(c.h / sqrt(c.mm)) : -INFINITY;
+  S.key[lane] = f ? okey : INFINITY;
   __syncthreads();
   if (f) {
-    const int r = lane_rank(S, fm, (float)c.mm);
+    const int r = lane_rank(S, fm, okey);
     S.cpl[r][0] = c.mx; S.cpl[r][1] = c.my; S.cpl[r][2] = c.mz; S.cpl[r][3] = c.h;
     S.corig[r] = c.orig;
   }
@@ -568,10 +575,13 @@ __device__ bool process_batch(Shared<SPL, PM>& S, EOT* eo, Poly<SPL>& P, int& np
   return true;
 }
 
-// BIG = false: all cells, sorted position k = blockIdx.x, faces at stride
-// FACE_CAP by original index, edge table in LDS.  BIG = true: the cells
-// listed in klist, faces at stride PM by list slot, edge table in HBM.
-template <int SPL, int PM, bool BIG>
+// MODE 0: all cells, sorted position k = blockIdx.x, faces at stride
+// FACE_CAP by original index, edge table in LDS.  MODE 1: the cells listed
+// in klist (sorted positions), faces at stride PM_BIG in slot blockIdx.x
+// (recorded in bigslot), edge table in LDS.  MODE 2: listed cells that
+// already own a slot, edge table in an HBM workspace (for PM*PM too large
+// for LDS).
+template <int SPL, int PM, int MODE>
 __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, const int32_t* __restrict__ sidx,
                                              int64_t n, const float4* __restrict__ nlo,
                                              const float4* __restrict__ nhi, Levels lv, float3 bmin,
@@ -580,14 +590,16 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
                                              int32_t* __restrict__ faces, int32_t* __restrict__ bigslot,
                                              int32_t* __restrict__ counts, int32_t* __restrict__ nrast,
                                              float* __restrict__ cull, int32_t* __restrict__ flags) {
-  using EOT = typename std::conditional<BIG, unsigned short, unsigned char>::type;
+  constexpr bool LISTED = MODE >= 1, EO_HBM = MODE == 2;
+  using EOT = typename std::conditional<(64 * SPL > 256), unsigned short, unsigned char>::type;
+  static_assert(EO_HBM ? std::is_same<EOT, unsigned short>::value : true, "HBM edge table holds 16-bit slots");
   __shared__ Shared<SPL, PM> S;
-  __shared__ unsigned char eo_lds[BIG ? 1 : PM * PM];
+  __shared__ EOT eo_lds[EO_HBM ? 1 : PM * PM];
   EOT* eo;
-  if constexpr (BIG) eo = eo_g + (int64_t)blockIdx.x * PM * PM;
+  if constexpr (EO_HBM) eo = (EOT*)(eo_g + (int64_t)blockIdx.x * PM * PM);
   else eo = eo_lds;
   const int lane = threadIdx.x;
-  const int64_t k = BIG ? (int64_t)klist[blockIdx.x] : (int64_t)blockIdx.x;
+  const int64_t k = LISTED ? (int64_t)klist[blockIdx.x] : (int64_t)blockIdx.x;
   const float4 me = sp[k];
   const int32_t self = sidx[k];
   const double px = me.x, py = me.y, pz = me.z, wi = me.w;
@@ -632,29 +644,37 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
   int status = CUT;
   int work = 0;
 
-  // phase 1: own leaf, nearest first
+  // phase 1: the own leaf (Morton neighbours)
   const int64_t leaf = k / LEAF;
   double dmax;
   {
     const int64_t j = leaf * LEAF + lane;
     const bool ok = j < n && j != k;
-    double d2 = 0.0;
+    double d2 = INFINITY;
     if (ok) {
       const float4 q = sp[j];
       const double dx = (double)q.x - px, dy = (double)q.y - py, dz = (double)q.z - pz;
       d2 = dx * dx + dy * dy + dz * dz;
     }
-    dmax = fmax(sqrt(wave_max_d(d2)), 1e-6);
+    // first ring radius: the RING_K-th nearest leaf mate, at most r_i (a
+    // Morton leaf can straddle a jump of the curve and span the scene)
+    const uint64_t okm = __ballot(ok);
+    S.key[lane] = ok ? (float)d2 : INFINITY;
+    __syncthreads();
+    const int target = min(RING_K, __popcll(okm) - 1);
+    const uint64_t sel = __ballot(ok && lane_rank(S, okm, (float)d2) == target);
+    __syncthreads();
+    const double dk = sel ? __shfl(d2, __ffsll((long long)sel) - 1, 64) : 0.0;
+    dmax = fmax(fmin(sqrt(dk), ri), 1e-6);
     const Cand c = load_cand(sp, sidx, j, ok, px, py, pz, wi);
     process_batch(S, eo, P, nplanes, status, c, self, work);
   }
 
-  // phase 2: the sites within the own leaf's radius dmax first (nearest
-  // first across the whole tree, which keeps the transient polytope small),
-  // then every remaining site in one more traversal.  Each traversal walks
-  // the tree depth first, nearest child first, pruning by the current
-  // polytope; a first traversal that left no prunable work beyond dmax ends
-  // the search.
+  // phase 2: the other sites in rings [dmin, dmax) of doubling radius, which
+  // brings near sites first across the whole tree and keeps the transient
+  // polytope small.  Each ring walks the tree depth first, most constraining
+  // child first, pruning by the current polytope; a ring that left no
+  // prunable work beyond dmax ends the search.
   double dmin = 0.0;
   while (status == CUT) {
     bool skipped = false;
@@ -710,7 +730,8 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
           skipped = true;   // wait for a later ring
           keep = false;
         }
-        if (keep) dkey = dx * dx + dy * dy + dz * dz;
+        // lower bound of the bisector offset h/|m| of any site in the box
+        if (keep) dkey = (D * D + wi - W) / (2.0 * fmax(D, 1e-12));
       }
       if (__ballot(valid && skipped) != 0ull) skipped = true;
       // exact per-vertex test, one child box per lane: can any site in the
@@ -732,7 +753,7 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
           status = OVER_S;
           break;
         }
-        // nearest child on top of the stack
+        // most constraining child (smallest offset bound) on top of the stack
         S.key[lane] = cut ? (float)dkey : INFINITY;
         __syncthreads();
         if (cut) S.stack[top + nc - 1 - lane_rank(S, cm, (float)dkey)] = ((L - 1) << 24) | (int)(idx * 64 + lane);
@@ -741,15 +762,23 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
       __syncthreads();
     }
     if (!skipped) break;
-    // after the first ring the polytope is close to final; the rest of the
-    // tree is checked in one unrestricted traversal (no per-ring restarts)
+    // rings double until they lie beyond every vertex of the polytope; the
+    // remaining sites can then only cut through their weight, and one
+    // unrestricted traversal certifies the cell
     dmin = dmax;
-    dmax = INFINITY;
+    dmax = (dmin * dmin >= P.r2) ? INFINITY : 2.0 * dmax;
   }
 
   // --- outputs
-  int32_t* out = BIG ? faces + (int64_t)blockIdx.x * PM : faces + (int64_t)self * FACE_CAP;
-  if (BIG && lane == 0) bigslot[self] = (int32_t)blockIdx.x;
+  int32_t* out;
+  if constexpr (MODE == 0) {
+    out = faces + (int64_t)self * FACE_CAP;
+  } else if constexpr (MODE == 1) {
+    out = faces + (int64_t)blockIdx.x * PM_BIG;
+    if (lane == 0) bigslot[self] = (int32_t)blockIdx.x;
+  } else {
+    out = faces + (int64_t)bigslot[self] * PM_BIG;
+  }
   if (status == EMPTY || is_over(status)) {
     if (lane == 0) {
       counts[self] = 0;
@@ -1023,31 +1052,52 @@ pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipSt
   PF_HIP_TRY(hipMemsetAsync(bigslot.p, 0xFF, sizeof(int32_t) * n, s));
   {
     ProfScope ps_clip("k_clip", s);
-    k_clip<2, FACE_CAP, false><<<(unsigned)n, 64, 0, s>>>(sp.p, sidx.p, n, nlo.p, nhi.p, lv, bmin, bmax, prm.radius,
+    k_clip<2, FACE_CAP, 0><<<(unsigned)n, 64, 0, s>>>(sp.p, sidx.p, n, nlo.p, nhi.p, lv, bmin, bmax, prm.radius,
                                                          nullptr, nullptr, faces_tmp.p, nullptr, counts.p,
                                                          sc->nrast, sc->cull, sc->flags);
   }
   PF_HIP_TRY(hipGetLastError());
-  // second pass with larger capacity for the cells of very high degree
+  // second pass (twice the capacity, edge table still in LDS) for the cells
+  // that overflowed, third pass (4x, edge table in HBM) for what is left
   PF_HIP_TRY(spos.alloc(n));
   PF_HIP_TRY(klist.alloc(n));
   PF_HIP_TRY(nbig_d.alloc(1));
-  PF_HIP_TRY(hipMemsetAsync(nbig_d.p, 0, sizeof(unsigned int), s));
   k_inverse<<<g256, 256, 0, s>>>(sidx.p, n, spos.p);
   PF_HIP_TRY(hipGetLastError());
-  k_list_overflow<<<g256, 256, 0, s>>>(sc->flags, spos.p, n, klist.p, nbig_d.p);
-  PF_HIP_TRY(hipGetLastError());
+  auto list_overflow = [&](unsigned int& count) -> pf_status {
+    PF_HIP_TRY(hipMemsetAsync(nbig_d.p, 0, sizeof(unsigned int), s));
+    k_list_overflow<<<g256, 256, 0, s>>>(sc->flags, spos.p, n, klist.p, nbig_d.p);
+    PF_HIP_TRY(hipGetLastError());
+    PF_HIP_TRY(hipMemcpyAsync(&count, nbig_d.p, sizeof(count), hipMemcpyDeviceToHost, s));
+    PF_HIP_TRY(hipStreamSynchronize(s));
+    return PF_OK;
+  };
   unsigned int nbig = 0;
-  PF_HIP_TRY(hipMemcpyAsync(&nbig, nbig_d.p, sizeof(nbig), hipMemcpyDeviceToHost, s));
-  PF_HIP_TRY(hipStreamSynchronize(s));
+  {
+    const pf_status st = list_overflow(nbig);
+    if (st != PF_OK) return st;
+  }
   sc->n_big = nbig;
   if (nbig) {
     PF_HIP_TRY(faces_big.alloc((size_t)nbig * PM_BIG));
-    PF_HIP_TRY(eo_big.alloc((size_t)nbig * PM_BIG * PM_BIG));
-    k_clip<SPL_BIG, PM_BIG, true><<<nbig, 64, 0, s>>>(sp.p, sidx.p, n, nlo.p, nhi.p, lv, bmin, bmax, prm.radius,
-                                                      klist.p, eo_big.p, faces_big.p, bigslot.p, counts.p,
-                                                      sc->nrast, sc->cull, sc->flags);
+    {
+      ProfScope ps_big("k_clip_mid", s);
+      k_clip<SPL_MID, PM_MID, 1><<<nbig, 64, 0, s>>>(sp.p, sidx.p, n, nlo.p, nhi.p, lv, bmin, bmax, prm.radius,
+                                                    klist.p, nullptr, faces_big.p, bigslot.p, counts.p, sc->nrast,
+                                                    sc->cull, sc->flags);
+    }
     PF_HIP_TRY(hipGetLastError());
+    unsigned int nbig3 = 0;
+    const pf_status st = list_overflow(nbig3);
+    if (st != PF_OK) return st;
+    if (nbig3) {
+      PF_HIP_TRY(eo_big.alloc((size_t)nbig3 * PM_BIG * PM_BIG));
+      ProfScope ps_big("k_clip_big", s);
+      k_clip<SPL_BIG, PM_BIG, 2><<<nbig3, 64, 0, s>>>(sp.p, sidx.p, n, nlo.p, nhi.p, lv, bmin, bmax, prm.radius,
+                                                     klist.p, eo_big.p, faces_big.p, bigslot.p, counts.p,
+                                                     sc->nrast, sc->cull, sc->flags);
+      PF_HIP_TRY(hipGetLastError());
+    }
   }
 
   DevBuf<unsigned long long> cnt(s);
