@@ -104,6 +104,9 @@ typedef struct {
 typedef struct {
   float t_min;               /* stop a ray once T < t_min (default 1e-6)      */
   int32_t max_steps;         /* ray-walk step cap (default 4096)              */
+  int32_t state_mode;        /* forward state: 0 store the contribution
+                                records (default), 1 keep only the cameras and
+                                replay the forward inside pf_backward         */
 } pf_render_opts;
 
 typedef struct {
@@ -133,6 +136,14 @@ typedef struct {
 pf_status pf_build_scene(const pf_params* params, const pf_build_opts* opts,
                          void* stream, pf_scene** out);
 
+/* Rebuilds the adjacency, cull radii and flags of an existing scene for new
+   parameter values (the sites moved during training), keeping the scene's
+   build options and sizing hints.  params (host) as for pf_build_scene; the
+   scene then references the new arrays.  Must not overlap a render or
+   backward on the scene.  On error the scene keeps its previous state.
+   Errors: as pf_build_scene. */
+pf_status pf_update_scene(pf_scene* scene, const pf_params* params, void* stream);
+
 /* Scene statistics (host struct). */
 pf_status pf_scene_info_get(const pf_scene* scene, pf_scene_info* info);
 
@@ -148,9 +159,11 @@ void pf_scene_destroy(pf_scene* scene);
    distance from the camera centre (ties: lower index), composite front to
    back.  cams (host) [ncam]; opts (host) may be NULL; rgba as in the
    conventions.  If state is non-NULL, *state receives a forward state for
-   pf_backward (stores per-pixel contribution records).  Synchronises the
-   stream once per camera (pair-list sizing).
-   Errors: INVALID (ncam < 1, bad camera), OOM, HIP. */
+   pf_backward: with opts->state_mode 0 it stores the per-pixel contribution
+   records (about 36 B per contribution), with 1 only the cameras (the
+   records are rebuilt inside pf_backward).  Synchronises the stream (pair
+   list and record pool sizing).
+   Errors: INVALID (ncam < 1, bad camera, state_mode not 0/1), OOM, HIP. */
 pf_status pf_render_raster(pf_scene* scene, const pf_camera* cams, int32_t ncam,
                            const pf_render_opts* opts, float* rgba,
                            pf_fwd_state** state, void* stream);
@@ -160,20 +173,34 @@ pf_status pf_render_raster(pf_scene* scene, const pf_camera* cams, int32_t ncam,
    power diagram until the ray leaves the domain box, clip each cell by its
    sphere.  Same image as pf_render_raster up to rounding.  Rays cut by
    max_steps are counted in *truncated (host, may be NULL; the count is read
-   back, which synchronises the stream).
+   back, which synchronises the stream).  state as for pf_render_raster: the
+   walk's contributions are recorded in the same form, so pf_backward gives
+   the gradients of the walk.
    Errors: INVALID (also: camera centre outside the domain box), OOM, HIP. */
 pf_status pf_render_trace(pf_scene* scene, const pf_camera* cams, int32_t ncam,
                           const pf_render_opts* opts, float* rgba,
-                          int64_t* truncated, void* stream);
+                          int64_t* truncated, pf_fwd_state** state, void* stream);
 
 /* Gradients of L with respect to all cell parameters given dL/dRGBA
    (d_rgba, same layout as the forward's rgba), for the forward recorded in
-   state.  Adds into grads (host struct of device pointers).
+   state (Sec. 3.1 sum differentiated through Sec. 3.2-3.6).  Adds into
+   grads (host struct of device pointers).  A recompute-mode state first
+   replays its forward with records (temporary memory as for store mode) and
+   synchronises the stream.  The state stays valid; pf_backward may run
+   again on it.
    Errors: INVALID (NULL state/scene mismatch), OOM, HIP. */
 pf_status pf_backward(pf_scene* scene, const pf_fwd_state* state, const float* d_rgba,
                       const pf_grads* grads, void* stream);
 
 void pf_state_release(pf_fwd_state* state);
+
+/* Device memory estimate (bytes, host output) of a render of cams (what 0),
+   of a render with a store-mode forward state (what 1), or of that plus the
+   backward's workspace (what 2), from the scene's sizing hints (pair and
+   record counts of its last renders; defaults before the first).  An
+   estimate for admission control, not a bound.  Errors: INVALID. */
+pf_status pf_query_workspace(const pf_scene* scene, const pf_camera* cams, int32_t ncam,
+                             int32_t what, int64_t* bytes);
 
 /* Number of contribution records (pixel-cell pairs with alpha > 0) and of
    pixels in a forward state (host outputs). */

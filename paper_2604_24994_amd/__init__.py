@@ -3,9 +3,11 @@
 The compute path is libpowerfoam.so (HIP, gfx950) behind the C ABI in
 include/powerfoam.h; this package is its Python binding.
 """
-from .api import (ForwardState, Scene, backward, build_scene, camera_struct, render_raster, render_raster_state,
-                  render_trace, to_device_params)
-from .autograd import render_raster_diff
+from .api import (RECOMPUTE, STORE, ForwardState, Scene, backward, build_scene, camera_struct, query_workspace,
+                  render_raster, render_raster_state, render_trace, render_trace_state, to_device_params,
+                  update_scene)
+from .autograd import render_raster_diff, render_trace_diff
 
-__all__ = ["ForwardState", "Scene", "backward", "build_scene", "camera_struct", "render_raster",
-           "render_raster_state", "render_raster_diff", "render_trace", "to_device_params"]
+__all__ = ["RECOMPUTE", "STORE", "ForwardState", "Scene", "backward", "build_scene", "camera_struct",
+           "query_workspace", "render_raster", "render_raster_state", "render_raster_diff", "render_trace",
+           "render_trace_state", "render_trace_diff", "to_device_params", "update_scene"]

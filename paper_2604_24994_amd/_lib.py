@@ -12,7 +12,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "OOM", 3: "HIP", 4: "UNSUPPORTED", 5: 
 
 EXPORTS = ("pf_build_scene", "pf_scene_info_get", "pf_scene_adjacency", "pf_scene_destroy",
            "pf_render_raster", "pf_render_trace", "pf_backward", "pf_state_release", "pf_last_error",
-           "pf_profile_enable", "pf_profile_read", "pf_state_info")
+           "pf_profile_enable", "pf_profile_read", "pf_state_info", "pf_update_scene", "pf_query_workspace")
 
 
 class PfParams(C.Structure):
@@ -34,7 +34,7 @@ class PfBuildOpts(C.Structure):
 
 
 class PfRenderOpts(C.Structure):
-    _fields_ = [("t_min", C.c_float), ("max_steps", C.c_int32)]
+    _fields_ = [("t_min", C.c_float), ("max_steps", C.c_int32), ("state_mode", C.c_int32)]
 
 
 class PfSceneInfo(C.Structure):
@@ -74,7 +74,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.pf_render_raster.argtypes = [vp, C.POINTER(PfCamera), i32, C.POINTER(PfRenderOpts), vp,
                                      C.POINTER(vp), vp]
     lib.pf_render_trace.argtypes = [vp, C.POINTER(PfCamera), i32, C.POINTER(PfRenderOpts), vp,
-                                    C.POINTER(i64), vp]
+                                    C.POINTER(i64), C.POINTER(vp), vp]
+    lib.pf_update_scene.argtypes = [vp, C.POINTER(PfParams), vp]
+    lib.pf_query_workspace.argtypes = [vp, C.POINTER(PfCamera), i32, i32, C.POINTER(i64)]
     lib.pf_backward.argtypes = [vp, vp, vp, C.POINTER(PfGrads), vp]
     lib.pf_state_release.argtypes = [vp]
     lib.pf_state_release.restype = None

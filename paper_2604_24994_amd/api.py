@@ -136,8 +136,30 @@ def build_scene(params, sigma_scale: float = 10.0, tau: float = 20.0, box=None, 
     return Scene(h.value, t, {"sigma_scale": sigma_scale, "tau": tau})
 
 
-def _opts(t_min: float, max_steps: int) -> L.PfRenderOpts:
-    return L.PfRenderOpts(t_min=float(t_min), max_steps=int(max_steps))
+def update_scene(scene: Scene, params, stream=None) -> Scene:
+    """pf_update_scene: rebuilds ``scene`` in place for new parameter values
+    (same cell count); the scene then references the new tensors."""
+    t = to_device_params(params)
+    if int(t["p"].shape[0]) != int(scene.params["p"].shape[0]):
+        raise ValueError("update_scene keeps the cell count; build a new scene instead")
+    k = int(t["tex"].shape[1])
+    m = (int(t["tex"].shape[2]) - 3) // 6
+    pp = L.PfParams(n=int(t["p"].shape[0]), k_detail=k, m_axes=m, sigma_scale=float(scene.consts["sigma_scale"]),
+                    tau=float(scene.consts["tau"]))
+    for f in PARAM_FIELDS:
+        setattr(pp, f, t[f].data_ptr())
+    L.check(L.load().pf_update_scene(scene.handle, C.byref(pp), C.c_void_p(_stream_ptr(stream))))
+    scene.params = t
+    return scene
+
+
+STORE, RECOMPUTE = 0, 1
+
+
+def _opts(t_min: float, max_steps: int, state_mode: int = STORE) -> L.PfRenderOpts:
+    if state_mode not in (STORE, RECOMPUTE):
+        raise ValueError("state_mode must be STORE (0) or RECOMPUTE (1)")
+    return L.PfRenderOpts(t_min=float(t_min), max_steps=int(max_steps), state_mode=int(state_mode))
 
 
 def _alloc_images(shapes, device):
@@ -172,14 +194,15 @@ def render_trace(scene: Scene, cams, t_min: float = 1e-6, max_steps: int = 4096,
     opts = _opts(t_min, max_steps)
     trunc = C.c_int64(0)
     L.check(L.load().pf_render_trace(scene.handle, arr, nc, C.byref(opts), C.c_void_p(buf.data_ptr()),
-                                     C.byref(trunc) if return_truncated else None,
+                                     C.byref(trunc) if return_truncated else None, None,
                                      C.c_void_p(_stream_ptr(stream))))
     imgs = _split(buf, shapes)
     return (imgs, int(trunc.value)) if return_truncated else imgs
 
 
 class ForwardState:
-    """pf_fwd_state handle of a store-mode raster forward."""
+    """pf_fwd_state handle of a forward (raster or walk, store or recompute
+    mode)."""
 
     def __init__(self, handle: int, scene: Scene, shapes):
         self._h = C.c_void_p(handle)
@@ -209,15 +232,37 @@ class ForwardState:
             pass
 
 
-def render_raster_state(scene: Scene, cams, t_min: float = 1e-6, stream=None, out: Optional[torch.Tensor] = None):
+def render_raster_state(scene: Scene, cams, t_min: float = 1e-6, stream=None, out: Optional[torch.Tensor] = None,
+                        state_mode: int = STORE):
     """pf_render_raster with a forward state: (flat RGBA buffer, ForwardState)."""
     arr, nc, shapes = _cams(cams)
     buf = out if out is not None else _alloc_images(shapes, scene.params["p"].device)
-    opts = _opts(t_min, 0)
+    opts = _opts(t_min, 0, state_mode)
     h = C.c_void_p()
     L.check(L.load().pf_render_raster(scene.handle, arr, nc, C.byref(opts), C.c_void_p(buf.data_ptr()),
                                       C.byref(h), C.c_void_p(_stream_ptr(stream))))
     return buf, ForwardState(h.value, scene, shapes)
+
+
+def render_trace_state(scene: Scene, cams, t_min: float = 1e-6, max_steps: int = 4096, stream=None,
+                       out: Optional[torch.Tensor] = None, state_mode: int = STORE):
+    """pf_render_trace with a forward state: (flat RGBA buffer, ForwardState)."""
+    arr, nc, shapes = _cams(cams)
+    buf = out if out is not None else _alloc_images(shapes, scene.params["p"].device)
+    opts = _opts(t_min, max_steps, state_mode)
+    h = C.c_void_p()
+    L.check(L.load().pf_render_trace(scene.handle, arr, nc, C.byref(opts), C.c_void_p(buf.data_ptr()), None,
+                                     C.byref(h), C.c_void_p(_stream_ptr(stream))))
+    return buf, ForwardState(h.value, scene, shapes)
+
+
+def query_workspace(scene: Scene, cams, what: int = 0) -> int:
+    """pf_query_workspace: estimated device bytes of a render (0), a render
+    with a store-mode state (1), or that plus the backward (2)."""
+    arr, nc, _ = _cams(cams)
+    b = C.c_int64(0)
+    L.check(L.load().pf_query_workspace(scene.handle, arr, nc, int(what), C.byref(b)))
+    return int(b.value)
 
 
 def backward(scene: Scene, state: ForwardState, d_rgba: torch.Tensor, grads: Dict[str, torch.Tensor],

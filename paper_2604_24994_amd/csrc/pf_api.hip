@@ -15,6 +15,7 @@
 
 struct pf_scene {
   pf::Scene s;
+  pf_build_opts opts;   // kept for pf_update_scene
 };
 
 namespace {
@@ -24,9 +25,13 @@ std::atomic<double> g_seg_hint{4.0};
 }  // namespace
 
 struct pf_fwd_state {
-  const pf_scene* scene = nullptr;
+  pf_scene* scene = nullptr;
   pf::BwdState st;
   std::vector<pf_camera> cams;
+  int kind = 0;          // 0 raster, 1 ray walk
+  int mode = 0;          // 0 records stored, 1 recomputed by pf_backward
+  float t_min = 1e-6f;
+  int max_steps = 4096;
 };
 
 namespace {
@@ -97,22 +102,32 @@ extern "C" {
 
 const char* pf_last_error(void) { return pf::g_error.c_str(); }
 
-pf_status pf_build_scene(const pf_params* params, const pf_build_opts* opts, void* stream, pf_scene** out) {
-  if (!out) return invalid("pf_build_scene: out is NULL");
-  *out = nullptr;
-  if (!params) return invalid("pf_build_scene: params is NULL");
+static pf_status check_params(const pf_params* params, const char* who) {
+  const std::string w(who);
+  if (!params) return invalid(w + ": params is NULL");
   const pf_params& p = *params;
-  if (p.n < 1) return invalid("pf_build_scene: n must be >= 1");
-  if (p.n >= (1ll << 30)) return invalid("pf_build_scene: n must be < 2^30");
+  if (p.n < 1) return invalid(w + ": n must be >= 1");
+  if (p.n >= (1ll << 30)) return invalid(w + ": n must be < 2^30");
   if (!p.p || !p.power || !p.radius || !p.normal || !p.occ_logit || !p.rgb || !p.tex)
-    return invalid("pf_build_scene: a parameter array is NULL");
-  if (p.k_detail < 1 || p.m_axes < 1) return invalid("pf_build_scene: k_detail and m_axes must be >= 1");
+    return invalid(w + ": a parameter array is NULL");
+  if (p.k_detail < 1 || p.m_axes < 1) return invalid(w + ": k_detail and m_axes must be >= 1");
   if (p.k_detail != pf::KD || p.m_axes != pf::MA) {
-    pf::set_error("pf_build_scene: only k_detail = 8 and m_axes = 8 are built");
+    pf::set_error(w + ": only k_detail = 8 and m_axes = 8 are built");
     return PF_ERR_UNSUPPORTED;
   }
   if (!std::isfinite(p.sigma_scale) || !(p.sigma_scale >= 0) || !std::isfinite(p.tau))
-    return invalid("pf_build_scene: sigma_scale and tau must be finite, sigma_scale >= 0");
+    return invalid(w + ": sigma_scale and tau must be finite, sigma_scale >= 0");
+  return PF_OK;
+}
+
+pf_status pf_build_scene(const pf_params* params, const pf_build_opts* opts, void* stream, pf_scene** out) {
+  if (!out) return invalid("pf_build_scene: out is NULL");
+  *out = nullptr;
+  {
+    const pf_status st = check_params(params, "pf_build_scene");
+    if (st != PF_OK) return st;
+  }
+  const pf_params& p = *params;
   pf_build_opts o{};
   o.box_min[0] = 1.0f;
   o.box_max[0] = -1.0f;
@@ -123,6 +138,7 @@ pf_status pf_build_scene(const pf_params* params, const pf_build_opts* opts, voi
     pf::set_error("pf_build_scene: host allocation failed");
     return PF_ERR_OOM;
   }
+  sc->opts = o;
   pf_status st = pf::build_scene_impl(p, o, (hipStream_t)stream, &sc->s);
   if (st != PF_OK) {
     pf::free_scene(&sc->s);
@@ -130,6 +146,26 @@ pf_status pf_build_scene(const pf_params* params, const pf_build_opts* opts, voi
     return st;
   }
   *out = sc;
+  return PF_OK;
+}
+
+pf_status pf_update_scene(pf_scene* scene, const pf_params* params, void* stream) {
+  if (!scene) return invalid("pf_update_scene: scene is NULL");
+  {
+    const pf_status st = check_params(params, "pf_update_scene");
+    if (st != PF_OK) return st;
+  }
+  pf::Scene fresh;
+  const pf_status st = pf::build_scene_impl(*params, scene->opts, (hipStream_t)stream, &fresh);
+  if (st != PF_OK) {
+    pf::free_scene(&fresh);
+    return st;
+  }
+  fresh.rec_per_pixel = scene->s.rec_per_pixel;
+  fresh.seg_per_pixel = scene->s.seg_per_pixel;
+  fresh.pairs_per_cell = scene->s.pairs_per_cell;
+  pf::free_scene(&scene->s);
+  scene->s = fresh;
   return PF_OK;
 }
 
@@ -174,46 +210,75 @@ static pf_status check_render(pf_scene* scene, const pf_camera* cams, int32_t nc
   return PF_OK;
 }
 
-pf_status pf_render_raster(pf_scene* scene, const pf_camera* cams, int32_t ncam, const pf_render_opts* opts,
-                           float* rgba, pf_fwd_state** state, void* stream) {
-  if (state) *state = nullptr;
-  pf_status st = check_render(scene, cams, ncam, rgba, "pf_render_raster");
-  if (st != PF_OK) return st;
-  const float t_min = (opts && opts->t_min > 0) ? opts->t_min : 1e-6f;
-  hipStream_t s = (hipStream_t)stream;
-  if (!state) return pf::raster_views(scene->s, cams, ncam, t_min, rgba, s);
-  if (ncam >= 4096) return invalid("pf_render_raster: at most 4095 cameras per call with a forward state");
+namespace {
+
+// The pass that produces a forward state's records: kind 0 tile raster,
+// kind 1 ray walk (one view after the other).
+pf_status run_pass(pf_scene* scene, const std::vector<pf_camera>& cams, int kind, float t_min, int max_steps,
+                   float* rgba, unsigned long long* trunc_dev, hipStream_t s, const pf::RecBuf* rec) {
+  const int ncam = (int)cams.size();
+  if (kind == 0) return pf::raster_views(scene->s, cams.data(), ncam, t_min, rgba, s, rec);
+  int64_t off = 0;
+  for (int c = 0; c < ncam; ++c) {
+    const pf_status st = pf::trace_view(scene->s, cams[c], t_min, max_steps, rgba + 4 * off, trunc_dev, s, rec, c, off);
+    if (st != PF_OK) return st;
+    off += (int64_t)cams[c].width * cams[c].height;
+  }
+  return PF_OK;
+}
+
+// New state with the cameras on the device (no records yet).
+pf_status new_state(pf_scene* scene, const pf_camera* cams, int32_t ncam, int kind, int mode, float t_min,
+                    int max_steps, hipStream_t s, pf_fwd_state** out, const char* who) {
+  *out = nullptr;
+  if (ncam >= 4096) return invalid(std::string(who) + ": at most 4095 cameras per call with a forward state");
   pf_fwd_state* fs = new (std::nothrow) pf_fwd_state();
   if (!fs) {
-    pf::set_error("pf_render_raster: host allocation failed");
+    pf::set_error(std::string(who) + ": host allocation failed");
     return PF_ERR_OOM;
   }
   fs->scene = scene;
   fs->cams.assign(cams, cams + ncam);
+  fs->kind = kind;
+  fs->mode = mode;
+  fs->t_min = t_min;
+  fs->max_steps = max_steps;
   int64_t npix = 0;
   for (int c = 0; c < ncam; ++c) npix += (int64_t)cams[c].width * cams[c].height;
   fs->st.npix = npix;
-  auto fail = [&](pf_status e) {
-    free_state_mem(fs);
-    delete fs;
-    return e;
-  };
   hipError_t e = hipMalloc((void**)&fs->st.cams_dev, sizeof(pf_camera) * ncam);
   if (e == hipSuccess) e = hipMemcpyAsync(fs->st.cams_dev, cams, sizeof(pf_camera) * ncam, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMalloc((void**)&fs->st.rec.head, sizeof(int32_t) * npix);
+  if (e != hipSuccess) {
+    pf::set_error(std::string(who) + ": " + hipGetErrorString(e));
+    free_state_mem(fs);
+    delete fs;
+    return e == hipErrorOutOfMemory ? PF_ERR_OOM : PF_ERR_HIP;
+  }
+  *out = fs;
+  return PF_OK;
+}
+
+// Runs the state's pass with records.  The record pool and segment list are
+// sized from the last store-mode forward of this scene (else of any scene in
+// the process); a pass that runs out of room is repeated once with the
+// exact sizes.  rgba receives the image; trunc_dev (walk only) is zeroed
+// before each attempt.
+pf_status fill_records(pf_fwd_state* fs, float* rgba, unsigned long long* trunc_dev, hipStream_t s,
+                       const char* who) {
+  pf_scene* scene = fs->scene;
+  const int64_t npix = fs->st.npix;
+  hipError_t e = hipMalloc((void**)&fs->st.rec.head, sizeof(int32_t) * npix);
   if (e == hipSuccess) e = hipMalloc((void**)&fs->st.rec.counter, 3 * sizeof(unsigned long long));
   if (e != hipSuccess) {
-    pf::set_error(std::string("pf_render_raster: ") + hipGetErrorString(e));
-    return fail(e == hipErrorOutOfMemory ? PF_ERR_OOM : PF_ERR_HIP);
+    pf::set_error(std::string(who) + ": " + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? PF_ERR_OOM : PF_ERR_HIP;
   }
-  // record pool and segment list sized from the last store-mode forward of
-  // this scene (else of any scene in the process); a pass that runs out of
-  // room is repeated once with the exact sizes
   const bool seen = scene->s.rec_per_pixel > 0.0;
   const double rpp = seen ? scene->s.rec_per_pixel : g_rec_hint.load();
   const double spp = seen ? scene->s.seg_per_pixel : g_seg_hint.load();
   int64_t cap = (int64_t)(rpp * (double)npix) + 4096;
   int64_t seg_cap = (int64_t)(spp * (double)npix) + 4096;
+  if (fs->kind == 1) seg_cap = std::max(seg_cap, cap);   // one segment per record on the walk
   for (int attempt = 0; attempt < 2; ++attempt) {
     fs->st.rec.cap = cap;
     fs->st.rec.seg_cap = seg_cap;
@@ -222,35 +287,38 @@ pf_status pf_render_raster(pf_scene* scene, const pf_camera* cams, int32_t ncam,
     if (e == hipSuccess) e = hipMalloc((void**)&fs->st.rec.rt, sizeof(float) * cap);
     if (e == hipSuccess) e = hipMalloc((void**)&fs->st.rec.seg, sizeof(int4) * seg_cap);
     if (e == hipSuccess) e = hipMemsetAsync(fs->st.rec.counter, 0, 3 * sizeof(unsigned long long), s);
+    if (e == hipSuccess && fs->kind == 1) e = hipMemsetAsync(fs->st.rec.seg, 0, sizeof(int4) * seg_cap, s);
+    if (e == hipSuccess && trunc_dev) e = hipMemsetAsync(trunc_dev, 0, sizeof(unsigned long long), s);
     if (e != hipSuccess) {
-      pf::set_error(std::string("pf_render_raster: record pool: ") + hipGetErrorString(e));
-      return fail(e == hipErrorOutOfMemory ? PF_ERR_OOM : PF_ERR_HIP);
+      pf::set_error(std::string(who) + ": record pool: " + hipGetErrorString(e));
+      return e == hipErrorOutOfMemory ? PF_ERR_OOM : PF_ERR_HIP;
     }
-    st = pf::raster_views(scene->s, cams, ncam, t_min, rgba, s, &fs->st.rec);
-    if (st != PF_OK) return fail(st);
+    pf_status st = run_pass(scene, fs->cams, fs->kind, fs->t_min, fs->max_steps, rgba, trunc_dev, s, &fs->st.rec);
+    if (st != PF_OK) return st;
     unsigned long long used[3] = {0, 0, 0};
     e = hipMemcpyAsync(used, fs->st.rec.counter, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess && (int64_t)used[0] <= cap && (int64_t)used[1] <= seg_cap) {
       st = pf::seg_record_total(fs->st.rec.seg, (int64_t)used[1], fs->st.rec.counter + 2, s);
-      if (st != PF_OK) return fail(st);
+      if (st != PF_OK) return st;
       e = hipMemcpyAsync(used + 2, fs->st.rec.counter + 2, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
-      pf::set_error(std::string("pf_render_raster: ") + hipGetErrorString(e));
-      return fail(PF_ERR_HIP);
+      pf::set_error(std::string(who) + ": " + hipGetErrorString(e));
+      return PF_ERR_HIP;
     }
     if (used[0] > (unsigned long long)INT32_MAX)
-      return fail(invalid("pf_render_raster: more than 2^31 - 1 contributions in one call; render fewer views"));
-    scene->s.rec_per_pixel = 1.05 * (double)used[0] / (double)npix;
-    scene->s.seg_per_pixel = 1.05 * (double)used[1] / (double)npix;
-    g_rec_hint.store(scene->s.rec_per_pixel);
-    g_seg_hint.store(scene->s.seg_per_pixel);
+      return invalid(std::string(who) + ": more than 2^31 - 1 contributions in one call; render fewer views");
+    if (fs->kind == 0) {
+      scene->s.rec_per_pixel = 1.05 * (double)used[0] / (double)npix;
+      scene->s.seg_per_pixel = 1.05 * (double)used[1] / (double)npix;
+      g_rec_hint.store(scene->s.rec_per_pixel);
+      g_seg_hint.store(scene->s.seg_per_pixel);
+    }
     if ((int64_t)used[0] <= cap && (int64_t)used[1] <= seg_cap) {
       fs->st.nrec = (int64_t)used[2];
       fs->st.nseg = (int64_t)used[1];
-      *state = fs;
       return PF_OK;
     }
     void* pool[] = {fs->st.rec.ri, fs->st.rec.rf, fs->st.rec.rt, fs->st.rec.seg};
@@ -262,12 +330,42 @@ pf_status pf_render_raster(pf_scene* scene, const pf_camera* cams, int32_t ncam,
     cap = std::max(cap, (int64_t)used[0] + 4096);
     seg_cap = std::max(seg_cap, (int64_t)used[1] + 4096);
   }
-  pf::set_error("pf_render_raster: record pool sizing failed");
-  return fail(PF_ERR_HIP);
+  pf::set_error(std::string(who) + ": record pool sizing failed");
+  return PF_ERR_HIP;
+}
+
+}  // namespace
+
+pf_status pf_render_raster(pf_scene* scene, const pf_camera* cams, int32_t ncam, const pf_render_opts* opts,
+                           float* rgba, pf_fwd_state** state, void* stream) {
+  if (state) *state = nullptr;
+  pf_status st = check_render(scene, cams, ncam, rgba, "pf_render_raster");
+  if (st != PF_OK) return st;
+  const float t_min = (opts && opts->t_min > 0) ? opts->t_min : 1e-6f;
+  const int mode = opts ? opts->state_mode : 0;
+  if (mode != 0 && mode != 1) return invalid("pf_render_raster: state_mode must be 0 (store) or 1 (recompute)");
+  hipStream_t s = (hipStream_t)stream;
+  if (!state || mode == 1) {
+    st = pf::raster_views(scene->s, cams, ncam, t_min, rgba, s);
+    if (st != PF_OK || !state) return st;
+    return new_state(scene, cams, ncam, 0, 1, t_min, 0, s, state, "pf_render_raster");
+  }
+  pf_fwd_state* fs = nullptr;
+  st = new_state(scene, cams, ncam, 0, 0, t_min, 0, s, &fs, "pf_render_raster");
+  if (st != PF_OK) return st;
+  st = fill_records(fs, rgba, nullptr, s, "pf_render_raster");
+  if (st != PF_OK) {
+    free_state_mem(fs);
+    delete fs;
+    return st;
+  }
+  *state = fs;
+  return PF_OK;
 }
 
 pf_status pf_render_trace(pf_scene* scene, const pf_camera* cams, int32_t ncam, const pf_render_opts* opts,
-                          float* rgba, int64_t* truncated, void* stream) {
+                          float* rgba, int64_t* truncated, pf_fwd_state** state, void* stream) {
+  if (state) *state = nullptr;
   pf_status st = check_render(scene, cams, ncam, rgba, "pf_render_trace");
   if (st != PF_OK) return st;
   for (int c = 0; c < ncam; ++c) {
@@ -280,6 +378,8 @@ pf_status pf_render_trace(pf_scene* scene, const pf_camera* cams, int32_t ncam, 
   }
   const float t_min = (opts && opts->t_min > 0) ? opts->t_min : 1e-6f;
   const int max_steps = (opts && opts->max_steps > 0) ? opts->max_steps : 4096;
+  const int mode = opts ? opts->state_mode : 0;
+  if (mode != 0 && mode != 1) return invalid("pf_render_trace: state_mode must be 0 (store) or 1 (recompute)");
   hipStream_t s = (hipStream_t)stream;
   unsigned long long* trunc = nullptr;
   PF_HIP_TRY(hipMallocAsync((void**)&trunc, sizeof(unsigned long long), s));
@@ -288,30 +388,96 @@ pf_status pf_render_trace(pf_scene* scene, const pf_camera* cams, int32_t ncam, 
     (void)hipFreeAsync(trunc, s);
     PF_HIP_TRY(e);
   }
-  int64_t off = 0;
-  for (int c = 0; c < ncam && st == PF_OK; ++c) {
-    st = pf::trace_view(scene->s, cams[c], t_min, max_steps, rgba + off, trunc, s);
-    off += 4ll * cams[c].width * cams[c].height;
+  pf_fwd_state* fs = nullptr;
+  const std::vector<pf_camera> cv(cams, cams + ncam);
+  if (!state || mode == 1) {
+    st = run_pass(scene, cv, 1, t_min, max_steps, rgba, trunc, s, nullptr);
+    if (st == PF_OK && state) st = new_state(scene, cams, ncam, 1, 1, t_min, max_steps, s, &fs, "pf_render_trace");
+  } else {
+    st = new_state(scene, cams, ncam, 1, 0, t_min, max_steps, s, &fs, "pf_render_trace");
+    if (st == PF_OK) st = fill_records(fs, rgba, trunc, s, "pf_render_trace");
   }
   if (st == PF_OK && truncated) {
     unsigned long long h = 0;
     e = hipMemcpyAsync(&h, trunc, sizeof(h), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
-      (void)hipFreeAsync(trunc, s);
-      PF_HIP_TRY(e);
+      pf::set_error(std::string("pf_render_trace: ") + hipGetErrorString(e));
+      st = PF_ERR_HIP;
+    } else {
+      *truncated = (int64_t)h;
     }
-    *truncated = (int64_t)h;
   }
   (void)hipFreeAsync(trunc, s);
-  return st;
+  if (st != PF_OK) {
+    if (fs) {
+      free_state_mem(fs);
+      delete fs;
+    }
+    return st;
+  }
+  if (state) *state = fs;
+  return PF_OK;
 }
 
 pf_status pf_backward(pf_scene* scene, const pf_fwd_state* state, const float* d_rgba, const pf_grads* grads,
                       void* stream) {
   if (!scene || !state || !d_rgba || !grads) return invalid("pf_backward: NULL argument");
   if (state->scene != scene) return invalid("pf_backward: the state belongs to another scene");
-  return pf::backward_impl(scene->s, state->st, d_rgba, *grads, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  if (state->mode == 0) return pf::backward_impl(scene->s, state->st, d_rgba, *grads, s);
+  // recompute mode: replay the forward with records into a temporary state
+  pf_fwd_state* tmp = nullptr;
+  pf_status st = new_state(scene, state->cams.data(), (int32_t)state->cams.size(), state->kind, 0, state->t_min,
+                           state->max_steps, s, &tmp, "pf_backward");
+  if (st != PF_OK) return st;
+  float* scratch = nullptr;
+  unsigned long long* trunc = nullptr;
+  hipError_t e = hipMalloc((void**)&scratch, sizeof(float) * 4 * tmp->st.npix);
+  if (e == hipSuccess && state->kind == 1) e = hipMalloc((void**)&trunc, sizeof(unsigned long long));
+  if (e != hipSuccess) {
+    pf::set_error(std::string("pf_backward: ") + hipGetErrorString(e));
+    st = e == hipErrorOutOfMemory ? PF_ERR_OOM : PF_ERR_HIP;
+  }
+  if (st == PF_OK) st = fill_records(tmp, scratch, trunc, s, "pf_backward");
+  if (st == PF_OK) st = pf::backward_impl(scene->s, tmp->st, d_rgba, *grads, s);
+  if (st == PF_OK) {
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      pf::set_error(std::string("pf_backward: ") + hipGetErrorString(e));
+      st = PF_ERR_HIP;
+    }
+  }
+  if (scratch) (void)hipFree(scratch);
+  if (trunc) (void)hipFree(trunc);
+  free_state_mem(tmp);
+  delete tmp;
+  return st;
+}
+
+pf_status pf_query_workspace(const pf_scene* scene, const pf_camera* cams, int32_t ncam, int32_t what,
+                             int64_t* bytes) {
+  if (!scene || !cams || ncam < 1 || !bytes) return invalid("pf_query_workspace: NULL argument or ncam < 1");
+  if (what < 0 || what > 2) return invalid("pf_query_workspace: what must be 0, 1 or 2");
+  const pf::Scene& sc = scene->s;
+  const double n = (double)sc.n;
+  double npix = 0.0, ntiles = 0.0;
+  for (int c = 0; c < ncam; ++c) {
+    npix += (double)cams[c].width * cams[c].height;
+    ntiles += (double)((cams[c].width + pf::TILE - 1) / pf::TILE) * ((cams[c].height + pf::TILE - 1) / pf::TILE);
+  }
+  double ppc = 0.0;
+  __atomic_load(&sc.pairs_per_cell, &ppc, __ATOMIC_RELAXED);
+  if (!(ppc > 0.0)) ppc = 4.0;
+  const double rpp = sc.rec_per_pixel > 0.0 ? sc.rec_per_pixel : g_rec_hint.load();
+  const double spp = sc.seg_per_pixel > 0.0 ? sc.seg_per_pixel : g_seg_hint.load();
+  // render: per (view, cell) key, count, offset; pairs (tile, value, sorted
+  // value); per tile counts and offsets; the image
+  double b = 12.0 * n * ncam + 20.0 * ppc * n * ncam + 12.0 * ntiles + 16.0 * npix;
+  if (what >= 1) b += 36.0 * rpp * npix + 16.0 * spp * npix + 4.0 * npix;   // store-mode state
+  if (what == 2) b += 20.0 * n + 4.0 * rpp * npix + 16.0 * (n / 2.0);      // backward workspace
+  *bytes = (int64_t)(b * 1.1) + (1 << 20);
+  return PF_OK;
 }
 
 void pf_state_release(pf_fwd_state* state) {

@@ -43,6 +43,7 @@ struct Scene {
   int64_t n_faces = 0, n_hidden = 0, n_overflow = 0, n_big = 0;
   double rec_per_pixel = 0.0;      // record-pool sizing hint for store mode (0: none yet)
   double seg_per_pixel = 0.0;      // segment-list sizing hint for store mode
+  double pairs_per_cell = 0.0;     // tile pairs per (view, cell) of the last raster
 };
 
 // Contribution records written by the store-mode forward: one per (pixel,

@@ -483,9 +483,17 @@ __global__ void __launch_bounds__(256) k_start_final(const double* __restrict__ 
   if (threadIdx.x == 0) out[0] = (int32_t)si[0];
 }
 
+// STORE: every contribution is also written as a record (as the store-mode
+// rasteriser does) with a one-record segment; rec_seg must be zeroed by the
+// caller (unused slots of the wave's segment blocks keep count 0).
+template <bool STORE>
 __global__ void __launch_bounds__(256) k_trace(ViewArgs v, SceneDev S, const int32_t* __restrict__ start,
                                                float t_min, int max_steps, float* __restrict__ rgba,
-                                               unsigned long long* __restrict__ truncated) {
+                                               unsigned long long* __restrict__ truncated, int view,
+                                               int4* __restrict__ rec_ri, float4* __restrict__ rec_rf,
+                                               float* __restrict__ rec_rt, int32_t* __restrict__ rec_head,
+                                               unsigned long long* __restrict__ rec_counter,
+                                               int4* __restrict__ rec_seg, int64_t rec_cap, int64_t seg_cap) {
   int px, py;
   tile_pixel(v.tiles_x, px, py);
   const bool inside = px < v.cam.width && py < v.cam.height;
@@ -496,6 +504,14 @@ __global__ void __launch_bounds__(256) k_trace(ViewArgs v, SceneDev S, const int
   int prev = -1;
   double t_cur = 0.0;
   bool cut = false;
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int pix = py * v.cam.width + px;
+  int head = -1;
+  // the wave's current record / segment blocks; the lanes still walking
+  // update them together
+  long long rblk = 0, sblk = 0;
+  int rleft = 0, sleft = 0;
   if (live && cell >= 0) {
     int step = 0;
     for (; step < max_steps; ++step) {
@@ -503,19 +519,57 @@ __global__ void __launch_bounds__(256) k_trace(ViewArgs v, SceneDev S, const int
       const Local L = make_local(R, g.x, g.y, g.z);
       // contribution of this cell (identical code to the rasteriser)
       const float rho = S.cull[cell];
+      bool contrib = false;
+      Piece P;
+      float r = 0.0f, gg = 0.0f, b = 0.0f;
       if (rho >= 0.0f && L.qq < (double)rho * (double)rho) {
         const float* tx = S.tex + (int64_t)cell * (KD * TEXW);
         const int r0 = S.row[cell];
-        const Piece P = piece_geometry(R, L, g.w, S.plane + r0, S.nrast[cell], S.nrm[cell], tx, S.tau);
+        P = piece_geometry(R, L, g.w, S.plane + r0, S.nrast[cell], S.nrm[cell], tx, S.tau);
         if (P.alpha > 0.0f) {
-          float r, gg, b;
           radiance(tx, S.rgb + 3 * (int64_t)cell, P.ux, P.uy, R.fx, R.fy, R.fz, S.tau, r, gg, b);
-          const float wgt = T * P.alpha;
-          cr += wgt * r;
-          cg += wgt * gg;
-          cb += wgt * b;
-          T *= (1.0f - P.alpha);
+          contrib = true;
         }
+      }
+      if constexpr (STORE) {
+        const uint64_t m = __ballot(contrib);
+        if (m) {
+          const int leader = __ffsll((long long)__ballot(true)) - 1;
+          const int cnt = __popcll(m);
+          if (cnt > rleft) {
+            unsigned long long bk = 0;
+            if (lane == leader) bk = atomicAdd(&rec_counter[0], (unsigned long long)RBLK);
+            rblk = (long long)bcast64(bk);
+            rleft = RBLK;
+          }
+          if (cnt > sleft) {
+            unsigned long long bk = 0;
+            if (lane == leader) bk = atomicAdd(&rec_counter[1], (unsigned long long)RBLK);
+            sblk = (long long)bcast64(bk);
+            sleft = RBLK;
+          }
+          if (contrib) {
+            const long long slot = rblk + __popcll(m & lt), sg = sblk + __popcll(m & lt);
+            if (slot < rec_cap) {
+              rec_ri[slot] = make_int4(cell, pix, head, (view << 20) | ((P.bind0 + 2) << 10) | (P.bind1 + 2));
+              rec_rf[slot] = make_float4(P.alpha, r, gg, b);
+              rec_rt[slot] = T;
+              head = (int)slot;
+              if (sg < seg_cap) rec_seg[sg] = make_int4(cell, (int)slot, 1, 0);
+            }
+          }
+          rblk += cnt;
+          rleft -= cnt;
+          sblk += cnt;
+          sleft -= cnt;
+        }
+      }
+      if (contrib) {
+        const float wgt = T * P.alpha;
+        cr += wgt * r;
+        cg += wgt * gg;
+        cb += wgt * b;
+        T *= (1.0f - P.alpha);
       }
       if (T < t_min) break;
       // exit: nearest face ahead of the current position that the ray leaves through
@@ -549,6 +603,7 @@ __global__ void __launch_bounds__(256) k_trace(ViewArgs v, SceneDev S, const int
     o[1] = cg;
     o[2] = cb;
     o[3] = 1.0f - T;
+    if constexpr (STORE) rec_head[pix] = head;
   }
   const uint64_t bc = __ballot(cut);
   if ((threadIdx.x & 63) == 0 && bc) atomicAdd(truncated, (unsigned long long)__popcll(bc));
@@ -596,7 +651,7 @@ bool camera_ok(const pf_camera& c, std::string* why) {
   return true;
 }
 
-pf_status raster_views(const Scene& sc, const pf_camera* cams, int ncam, float t_min, float* rgba, hipStream_t s,
+pf_status raster_views(Scene& sc, const pf_camera* cams, int ncam, float t_min, float* rgba, hipStream_t s,
                        const RecBuf* rec) {
   const int64_t n = sc.n;
   // views are processed in groups so that the per-(view, cell) scan fits 32 bits
@@ -636,6 +691,8 @@ pf_status raster_views(const Scene& sc, const pf_camera* cams, int ncam, float t
     uint32_t np = 0;
     PF_HIP_TRY(hipMemcpyAsync(&np, off.p + nvc, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     PF_HIP_TRY(hipStreamSynchronize(s));
+    double ppc = (double)np / (double)nvc;   // sizing hint (renders may run on several threads)
+    __atomic_store(&sc.pairs_per_cell, &ppc, __ATOMIC_RELAXED);
     Buf<uint32_t> ptile(s);
     Buf<unsigned long long> pval(s), sorted(s);
     PF_HIP_TRY(ptile.alloc(np));
@@ -684,7 +741,7 @@ pf_status seg_record_total(const int4* seg, int64_t nseg, unsigned long long* to
 }
 
 pf_status trace_view(const Scene& sc, const pf_camera& cam, float t_min, int max_steps, float* rgba,
-                     unsigned long long* trunc_dev, hipStream_t s) {
+                     unsigned long long* trunc_dev, hipStream_t s, const RecBuf* rec, int view, int64_t pix_base) {
   const int64_t n = sc.n;
   ViewArgs v;
   v.cam = cam;
@@ -703,8 +760,16 @@ pf_status trace_view(const Scene& sc, const pf_camera& cam, float t_min, int max
   PF_HIP_TRY(hipGetLastError());
   k_start_final<<<1, 256, 0, s>>>(pk.p, pi.p, nb, start.p);
   PF_HIP_TRY(hipGetLastError());
-  ProfScope ps("k_trace", s);
-  k_trace<<<(unsigned)ntiles, 256, 0, s>>>(v, scene_dev(sc), start.p, t_min, max_steps, rgba, trunc_dev);
+  ProfScope ps(rec ? "k_trace_store" : "k_trace", s);
+  if (rec) {
+    const RecBuf& rb = *rec;
+    k_trace<true><<<(unsigned)ntiles, 256, 0, s>>>(v, scene_dev(sc), start.p, t_min, max_steps, rgba, trunc_dev,
+                                                   view, rb.ri, rb.rf, rb.rt, rb.head + pix_base, rb.counter,
+                                                   rb.seg, rb.cap, rb.seg_cap);
+  } else {
+    k_trace<false><<<(unsigned)ntiles, 256, 0, s>>>(v, scene_dev(sc), start.p, t_min, max_steps, rgba, trunc_dev,
+                                                    0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0);
+  }
   PF_HIP_TRY(hipGetLastError());
   return PF_OK;
 }

@@ -22,7 +22,8 @@ def _declared():
 
 def test_header_declares_boundary():
     names = _declared()
-    for n in ("pf_build_scene", "pf_render_raster", "pf_render_trace", "pf_backward", "pf_last_error"):
+    for n in ("pf_build_scene", "pf_update_scene", "pf_render_raster", "pf_render_trace", "pf_backward",
+              "pf_query_workspace", "pf_state_release", "pf_scene_destroy", "pf_last_error"):
         assert n in names
 
 
@@ -38,9 +39,15 @@ def test_binding_struct_sizes_match_header_layout():
     from paper_2604_24994_amd import _lib as L
     assert ctypes.sizeof(L.PfCamera) == 4 * (3 + 12 + 6)
     assert ctypes.sizeof(L.PfParams) == 8 + 4 + 4 + 7 * 8 + 8
-    assert ctypes.sizeof(L.PfRenderOpts) == 8
+    assert ctypes.sizeof(L.PfRenderOpts) == 12
+    assert ctypes.sizeof(L.PfSceneInfo) == 5 * 8 + 6 * 4
     lib = L.load()
     # argument errors are reported without touching a device
     h = ctypes.c_void_p()
     st = lib.pf_build_scene(None, None, None, ctypes.byref(h))
     assert st == L.PF_ERR_INVALID and b"NULL" in lib.pf_last_error()
+    st = lib.pf_update_scene(None, None, None)
+    assert st == L.PF_ERR_INVALID and b"pf_update_scene" in lib.pf_last_error()
+    b = ctypes.c_int64(0)
+    st = lib.pf_query_workspace(None, None, 0, 0, ctypes.byref(b))
+    assert st == L.PF_ERR_INVALID and b"pf_query_workspace" in lib.pf_last_error()

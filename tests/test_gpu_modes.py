@@ -1,0 +1,126 @@
+"""GPU tests of the forward-state variants and scene maintenance:
+  * the walk's backward (records written by pf_render_trace) against the
+    FP64 oracle adjoint and against the raster's backward;
+  * recompute mode (no records kept; pf_backward replays the forward)
+    against store mode;
+  * pf_update_scene against a fresh build of the moved parameters;
+  * pf_query_workspace estimates."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+PARAMS = ("p", "power", "radius", "normal", "occ_logit", "rgb", "tex")
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+def _case(seed=0, n=200, scale=3.0):
+    sc = W.scene_uniform(n, seed=seed)
+    sc.radius = (sc.radius * scale).astype(np.float32)
+    eyes = W.random_eyes(2, 2.7, 30 + seed)
+    cams = [W.pinhole(eyes[0], 20, 16, 60.0), W.pinhole(eyes[1], 18, 14, 70.0)]
+    rng = np.random.default_rng(seed)
+    Gs = [rng.normal(size=(c.n_rays, 4)) for c in cams]
+    return sc, cams, Gs
+
+
+def _grads(pf, sc, cams, Gs, walk=False, mode=0):
+    params = {f: torch.tensor(getattr(sc, f), device="cuda", requires_grad=True) for f in PARAMS}
+    box = None
+    if walk:
+        eyes = np.array([np.asarray(c.c2w).reshape(3, 4)[:, 3] for c in cams])
+        box = (eyes.min(0) - 0.1, eyes.max(0) + 0.1)
+    scene = pf.build_scene(params, sigma_scale=sc.sigma_scale, tau=sc.tau, box=box)
+    fn = pf.render_trace_diff if walk else pf.render_raster_diff
+    imgs = fn(scene, cams, state_mode=mode)
+    loss = sum((img.reshape(-1, 4) * torch.tensor(G, device="cuda", dtype=torch.float32)).sum()
+               for img, G in zip(imgs, Gs))
+    loss.backward()
+    torch.cuda.synchronize()
+    return ({f: params[f].grad.detach().cpu().numpy().astype(np.float64) for f in PARAMS},
+            [img.detach().cpu().numpy().reshape(-1, 4) for img in imgs])
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
+
+
+def test_walk_backward_matches_oracle_and_raster():
+    import paper_2604_24994_amd as pf
+    _flush("case walk backward: 200 sites, radius x3, 2 views")
+    sc, cams, Gs = _case()
+    g_walk, imgs = _grads(pf, sc, cams, Gs, walk=True)
+    g_ras, _ = _grads(pf, sc, cams, Gs, walk=False)
+    g_ref = {f: np.zeros_like(g_walk[f]) for f in PARAMS}
+    for cam, G, img in zip(cams, Gs, imgs):
+        gr, _ = oracle.adjoint_gradients(sc, cam, G)
+        for f in PARAMS:
+            g_ref[f] += gr[f].reshape(g_ref[f].shape)
+        assert np.abs(img - oracle.render_walk(sc, cam)).max() <= 1e-4
+    for f in PARAMS:
+        r_ref, r_ras = _rel(g_walk[f], g_ref[f]), _rel(g_walk[f], g_ras[f])
+        _flush(f"  {f:10s} walk vs oracle rel {r_ref:.3e}  walk vs raster rel {r_ras:.3e}")
+        assert r_ref <= 1e-3, f
+        assert r_ras <= 1e-5, f
+
+
+@pytest.mark.parametrize("walk", [False, True])
+def test_recompute_mode_equals_store_mode(walk):
+    import paper_2604_24994_amd as pf
+    _flush(f"case recompute vs store, walk={walk}")
+    sc, cams, Gs = _case(seed=1, n=300, scale=2.0)
+    g_store, img_s = _grads(pf, sc, cams, Gs, walk=walk, mode=pf.STORE)
+    g_rec, img_r = _grads(pf, sc, cams, Gs, walk=walk, mode=pf.RECOMPUTE)
+    for a, b in zip(img_s, img_r):
+        assert np.array_equal(a, b)
+    for f in PARAMS:
+        r = _rel(g_rec[f], g_store[f])
+        _flush(f"  {f:10s} rel {r:.3e}")
+        assert r <= 1e-6, f
+
+
+def test_update_scene_equals_fresh_build():
+    import paper_2604_24994_amd as pf
+    _flush("case update_scene: 2,000 sites moved by 1e-2")
+    sc = W.scene_uniform(2000, seed=3)
+    rng = np.random.default_rng(3)
+    p1 = (sc.p + rng.normal(scale=1e-2, size=sc.p.shape)).astype(np.float32)
+    scene = pf.build_scene(pf.to_device_params(sc), sigma_scale=sc.sigma_scale, tau=sc.tau)
+    moved = pf.to_device_params(sc)
+    moved["p"] = torch.tensor(p1, device="cuda")
+    pf.update_scene(scene, moved)
+    fresh = pf.build_scene(moved, sigma_scale=sc.sigma_scale, tau=sc.tau)
+    r0, c0 = scene.adjacency()
+    r1, c1 = fresh.adjacency()
+    assert torch.equal(r0, r1) and torch.equal(c0, c1)
+    cam = W.pinhole(W.random_eyes(1, 3.0, 7)[0], 48, 40, 60.0)
+    a = pf.render_raster(scene, cam)[0]
+    b = pf.render_raster(fresh, cam)[0]
+    assert torch.equal(a, b)
+    with pytest.raises(Exception):
+        bad = dict(moved)
+        bad["p"] = moved["p"][:10].contiguous()
+        pf.update_scene(scene, bad)
+
+
+def test_query_workspace_estimates():
+    import paper_2604_24994_amd as pf
+    _flush("case query_workspace: 20,000 sites, one 256x192 view")
+    sc = W.scene_mixture(20000, seed=4)
+    cam = W.pinhole(W.random_eyes(1, 4.0, 8)[0], 256, 192, 60.0)
+    scene = pf.build_scene(pf.to_device_params(sc), sigma_scale=sc.sigma_scale, tau=sc.tau)
+    q0, q1, q2 = (pf.query_workspace(scene, cam, w) for w in (0, 1, 2))
+    assert 0 < q0 < q1 < q2
+    _, state = pf.render_raster_state(scene, cam)
+    nrec = state.info()["records"]
+    q1b = pf.query_workspace(scene, cam, 1)     # now sized from this render's counts
+    _flush(f"  estimates {q0} {q1} {q2}; after a render {q1b}, records {nrec} ({36 * nrec} B)")
+    assert q1b >= 36 * nrec
+    state.release()
