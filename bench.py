@@ -43,6 +43,35 @@ FP32_PEAK_TFLOPS = 157.3          # published MI355X FP32 vector peak (packed FM
 FLOPS_FWD_PER_CONTRIB = 1700
 FLOPS_BWD_PER_CONTRIB = 5100
 
+# HBM bytes per launch on this workload (1,048,576 cells, 8 views 1600x1066)
+# from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), scaled
+# by what the same counters read for a 1 GiB device-to-device copy
+# (FETCH_SIZE reads 0.5 GiB: x2.0; WRITE_SIZE reads 1 GiB: x1.0).  Valid only
+# for the kernel sources with these hashes; otherwise the bench reports null.
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+TRAFFIC = {
+    "k_bwd_cell": {"fetch_kib": 6806427.3, "write_kib": 2406927.8,
+                   "sources": {"pf_backward.hip": "54980780d8382c63", "pf_shade.hpp": "68feb93f5734438a"}},
+    "k_raster_store": {"fetch_kib": 16127326.9, "write_kib": 10842619.0,
+                       "sources": {"pf_render.hip": "bc26bfe8245641a9", "pf_shade.hpp": "68feb93f5734438a"}},
+    "k_clip": {"fetch_kib": 235659.8, "write_kib": 157998.6, "sources": {"pf_build.hip": "e7291eee51bbc5bd"}},
+}
+
+
+def traffic_bytes(kernel: str):
+    """Measured HBM bytes per launch of ``kernel`` if its sources are the
+    ones the counters were taken on, else None."""
+    import hashlib
+    t = TRAFFIC.get(kernel)
+    if t is None:
+        return None
+    csrc = os.path.join(ROOT, "paper_2604_24994_amd", "csrc")
+    for f, h in t["sources"].items():
+        with open(os.path.join(csrc, f), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest()[:16] != h:
+                return None
+    return int(1024 * (FETCH_SCALE * t["fetch_kib"] + WRITE_SCALE * t["write_kib"]))
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -59,6 +88,8 @@ def parse():
     ap.add_argument("--cpu-rays", type=int, default=4, help="oracle sample size for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device once (reference for the HBM byte counters) and exit")
     return ap.parse_args()
 
 
@@ -86,6 +117,15 @@ def cpu_baseline(sc, cam, n_rays: int):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        n = args.copy_calibration << 18          # float32 elements in MIB MiB
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU layout is described in DESIGN.md)", file=sys.stderr)
@@ -184,7 +224,7 @@ def main():
             "achieved": round(achieved, 4) if achieved is not None else None,
             "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / FP32_PEAK_TFLOPS, 5) if achieved is not None else None,
-            "traffic": None, "avg_ms": round(avg_ms, 4),
+            "traffic": traffic_bytes(dom_name), "avg_ms": round(avg_ms, 4),
             "units_per_launch": f"{nrec} contributions x {per} flops" if per else None}
     res = {
         "metric": ("Mrays/s fwd+bwd at 1M cells (raster training step incl. adjacency rebuild)"
