@@ -126,14 +126,53 @@ struct ViewDev {
   int view_id;   // camera index within the call
 };
 
-__device__ inline bool cell_rect(const ViewArgs& v, const float4 g, float rho, int& x0, int& x1, int& y0, int& y1) {
-  if (!(rho >= 0.0f)) return false;
+// A ball that crosses the plane of a pinhole camera (camera outside the
+// ball) has no bounded screen rectangle; the pixel rays that meet it are
+// those within the cone of half-angle asin(rho/|c|) around the direction c
+// to its centre.  A tile is kept when the angle between its centre ray and
+// c is at most that half-angle plus the tile's own angular radius.
+struct Cone {
+  double ax, ay, az;   // unit direction to the centre, camera axes
+  double cmin;         // cosine of the widened half-angle
+};
+
+__device__ inline bool cone_tile(const pf_camera& c, const Cone& k, int tx, int ty) {
+  const double dx = ((double)(tx * TILE) + 0.5 * TILE - (double)c.cx) / (double)c.fx;
+  const double dy = ((double)(ty * TILE) + 0.5 * TILE - (double)c.cy) / (double)c.fy;
+  const double dot = dx * k.ax + dy * k.ay + k.az;
+  // dot / |d| >= cmin, without the square root
+  if (k.cmin <= 0.0 && dot >= 0.0) return true;
+  const double d2 = dx * dx + dy * dy + 1.0;
+  return k.cmin >= 0.0 ? (dot >= 0.0 && dot * dot >= k.cmin * k.cmin * d2) : (dot * dot <= k.cmin * k.cmin * d2);
+}
+
+// Tile footprint of a cell's cull ball in a view: 0 none, 1 the rectangle
+// [x0, x1] x [y0, y1], 2 the tiles of that rectangle (all of the view)
+// accepted by cone_tile(k).
+__device__ inline int cell_rect(const ViewArgs& v, const float4 g, float rho, int& x0, int& x1, int& y0, int& y1,
+                                Cone& k) {
+  if (!(rho >= 0.0f)) return 0;
   const float* m = v.cam.c2w;
   const double ex = (double)g.x - m[3], ey = (double)g.y - m[7], ez = (double)g.z - m[11];
   const double X = m[0] * ex + m[4] * ey + m[8] * ez;
   const double Y = m[1] * ex + m[5] * ey + m[9] * ez;
   const double Z = m[2] * ex + m[6] * ey + m[10] * ez;
-  return ball_rect(v.cam, X, Y, Z, (double)rho * (1.0 + 1e-5) + 1e-7, v.tiles_x, v.tiles_y, x0, x1, y0, y1);
+  const double r = (double)rho * (1.0 + 1e-5) + 1e-7;
+  if (!ball_rect(v.cam, X, Y, Z, r, v.tiles_x, v.tiles_y, x0, x1, y0, y1)) return 0;
+  if (v.cam.model == 0 && Z - r <= 1e-9 * (1.0 + fabs(Z))) {
+    const double L = sqrt(X * X + Y * Y + Z * Z);
+    if (L > r * (1.0 + 1e-9)) {
+      // tile angular radius: half diagonal of a tile plus the one-pixel pad
+      const double tile_ang = (0.5 * TILE + 1.0) * 1.4142135623730951 / fmin((double)v.cam.fx, (double)v.cam.fy);
+      const double ang = asin(r / L) + tile_ang + 1e-6;
+      k.ax = X / L;
+      k.ay = Y / L;
+      k.az = Z / L;
+      k.cmin = ang >= M_PI ? -1.0 : cos(ang);
+      return 2;
+    }
+  }
+  return 1;
 }
 
 // blockIdx.y = view; one thread per (view, cell).
@@ -146,8 +185,15 @@ __global__ void k_view_count(const ViewDev* __restrict__ views, const float4* __
   const int64_t o = (int64_t)blockIdx.y * n + i;
   const float4 g = geo[i];
   int x0, x1, y0, y1;
+  Cone k;
   uint32_t c = 0;
-  if (cell_rect(v, g, cull[i], x0, x1, y0, y1)) c = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+  const int mode = cell_rect(v, g, cull[i], x0, x1, y0, y1, k);
+  if (mode == 1) {
+    c = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+  } else if (mode == 2) {
+    for (int ty = y0; ty <= y1; ++ty)
+      for (int tx = x0; tx <= x1; ++tx) c += cone_tile(v.cam, k, tx, ty) ? 1u : 0u;
+  }
   cnt[o] = c;
   const float* m = v.cam.c2w;
   const double ex = (double)m[3] - g.x, ey = (double)m[7] - g.y, ez = (double)m[11] - g.z;
@@ -163,11 +209,14 @@ __global__ void k_view_emit(const ViewDev* __restrict__ views, const float4* __r
   const ViewDev& vd = views[blockIdx.y];
   const int64_t oi = (int64_t)blockIdx.y * n + i;
   int x0, x1, y0, y1;
-  if (!cell_rect(vd.v, geo[i], cull[i], x0, x1, y0, y1)) return;
+  Cone k;
+  const int mode = cell_rect(vd.v, geo[i], cull[i], x0, x1, y0, y1, k);
+  if (mode == 0) return;
   uint32_t o = off[oi];
   const unsigned long long val = ((unsigned long long)key[oi] << 32) | (uint32_t)i;
   for (int ty = y0; ty <= y1; ++ty)
     for (int tx = x0; tx <= x1; ++tx) {
+      if (mode == 2 && !cone_tile(vd.v.cam, k, tx, ty)) continue;
       const uint32_t t = (uint32_t)(vd.tile_base + ty * vd.v.tiles_x + tx);
       ptile[o] = t;
       pval[o] = val;
