@@ -176,9 +176,12 @@ __device__ inline int cell_rect(const ViewArgs& v, const float4 g, float rho, in
 }
 
 // blockIdx.y = view; one thread per (view, cell).
+// Cells whose footprint needs the per-tile cone test are listed in
+// cone_list (as view * n + cell) and counted by k_cone_count.
 __global__ void k_view_count(const ViewDev* __restrict__ views, const float4* __restrict__ geo,
                              const float* __restrict__ cull, const float* __restrict__ power, int64_t n,
-                             uint32_t* __restrict__ cnt, uint32_t* __restrict__ key) {
+                             uint32_t* __restrict__ cnt, uint32_t* __restrict__ key, uint32_t* __restrict__ cone_list,
+                             uint32_t* __restrict__ cone_n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const ViewArgs& v = views[blockIdx.y].v;
@@ -191,8 +194,7 @@ __global__ void k_view_count(const ViewDev* __restrict__ views, const float4* __
   if (mode == 1) {
     c = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
   } else if (mode == 2) {
-    for (int ty = y0; ty <= y1; ++ty)
-      for (int tx = x0; tx <= x1; ++tx) c += cone_tile(v.cam, k, tx, ty) ? 1u : 0u;
+    cone_list[atomicAdd(cone_n, 1u)] = (uint32_t)o;
   }
   cnt[o] = c;
   const float* m = v.cam.c2w;
@@ -211,18 +213,81 @@ __global__ void k_view_emit(const ViewDev* __restrict__ views, const float4* __r
   int x0, x1, y0, y1;
   Cone k;
   const int mode = cell_rect(vd.v, geo[i], cull[i], x0, x1, y0, y1, k);
-  if (mode == 0) return;
+  if (mode != 1) return;   // cone footprints: k_cone_emit
   uint32_t o = off[oi];
   const unsigned long long val = ((unsigned long long)key[oi] << 32) | (uint32_t)i;
   for (int ty = y0; ty <= y1; ++ty)
     for (int tx = x0; tx <= x1; ++tx) {
-      if (mode == 2 && !cone_tile(vd.v.cam, k, tx, ty)) continue;
       const uint32_t t = (uint32_t)(vd.tile_base + ty * vd.v.tiles_x + tx);
       ptile[o] = t;
       pval[o] = val;
       atomicAdd(&tile_cnt[t], 1u);
       ++o;
     }
+}
+
+// One workgroup per listed (view, cell): its threads test the tiles of the
+// view in parallel.
+__global__ void __launch_bounds__(256) k_cone_count(const ViewDev* __restrict__ views,
+                                                    const float4* __restrict__ geo, const float* __restrict__ cull,
+                                                    int64_t n, const uint32_t* __restrict__ cone_list,
+                                                    uint32_t* __restrict__ cnt) {
+  __shared__ uint32_t part[4];
+  const uint32_t o = cone_list[blockIdx.x];
+  const int64_t i = (int64_t)(o % (uint64_t)n);
+  const ViewArgs& v = views[o / (uint64_t)n].v;
+  int x0, x1, y0, y1;
+  Cone k;
+  (void)cell_rect(v, geo[i], cull[i], x0, x1, y0, y1, k);
+  const int tw = x1 - x0 + 1, nt = tw * (y1 - y0 + 1);
+  uint32_t c = 0;
+  for (int t = threadIdx.x; t < nt; t += 256) c += cone_tile(v.cam, k, x0 + t % tw, y0 + t / tw) ? 1u : 0u;
+  for (int sh = 32; sh > 0; sh >>= 1) c += __shfl_xor(c, sh, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[o] = part[0] + part[1] + part[2] + part[3];
+}
+
+__global__ void __launch_bounds__(256) k_cone_emit(const ViewDev* __restrict__ views, const float4* __restrict__ geo,
+                                                   const float* __restrict__ cull, int64_t n,
+                                                   const uint32_t* __restrict__ off, const uint32_t* __restrict__ key,
+                                                   const uint32_t* __restrict__ cone_list,
+                                                   uint32_t* __restrict__ ptile, unsigned long long* __restrict__ pval,
+                                                   uint32_t* __restrict__ tile_cnt) {
+  __shared__ uint32_t wsum[4];
+  const uint32_t o = cone_list[blockIdx.x];
+  const int64_t i = (int64_t)(o % (uint64_t)n);
+  const ViewDev& vd = views[o / (uint64_t)n];
+  int x0, x1, y0, y1;
+  Cone k;
+  (void)cell_rect(vd.v, geo[i], cull[i], x0, x1, y0, y1, k);
+  const int tw = x1 - x0 + 1, nt = tw * (y1 - y0 + 1);
+  const unsigned long long val = ((unsigned long long)key[o] << 32) | (uint32_t)i;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t base = off[o];
+  for (int t0 = 0; t0 < nt; t0 += 256) {
+    const int t = t0 + threadIdx.x;
+    const int tx = x0 + t % tw, ty = y0 + t / tw;
+    const bool pass = t < nt && cone_tile(vd.v.cam, k, tx, ty);
+    const uint64_t m = __ballot(pass);
+    if (lane == 0) wsum[wv] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int w = 0; w < 4; ++w) {
+      before += w < wv ? wsum[w] : 0u;
+      total += wsum[w];
+    }
+    if (pass) {
+      const uint32_t pos = base + before + (uint32_t)__popcll(m & lt);
+      const uint32_t tile = (uint32_t)(vd.tile_base + ty * vd.v.tiles_x + tx);
+      ptile[pos] = tile;
+      pval[pos] = val;
+      atomicAdd(&tile_cnt[tile], 1u);
+    }
+    base += total;
+    __syncthreads();
+  }
 }
 
 __global__ void k_tile_scatter(const uint32_t* __restrict__ ptile, const unsigned long long* __restrict__ pval,
@@ -732,9 +797,24 @@ pf_status raster_views(Scene& sc, const pf_camera* cams, int ncam, float t_min, 
     PF_HIP_TRY(tcnt.alloc(ntiles + 1));
     PF_HIP_TRY(toff.alloc(ntiles + 1));
     PF_HIP_TRY(fill.alloc(ntiles));
+    Buf<uint32_t> cone_list(s), cone_n(s);
+    PF_HIP_TRY(cone_list.alloc(nvc));
+    PF_HIP_TRY(cone_n.alloc(1));
+    PF_HIP_TRY(hipMemsetAsync(cone_n.p, 0, sizeof(uint32_t), s));
     const dim3 g((unsigned)((n + 255) / 256), (unsigned)nv);
-    k_view_count<<<g, 256, 0, s>>>(views.p, sc.geo, sc.cull, sc.prm.power, n, cnt.p, key.p);
+    {
+      ProfScope ps("k_view_count", s);
+      k_view_count<<<g, 256, 0, s>>>(views.p, sc.geo, sc.cull, sc.prm.power, n, cnt.p, key.p, cone_list.p,
+                                     cone_n.p);
+    }
     PF_HIP_TRY(hipGetLastError());
+    uint32_t ncone = 0;
+    PF_HIP_TRY(hipMemcpyAsync(&ncone, cone_n.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    PF_HIP_TRY(hipStreamSynchronize(s));
+    if (ncone) {
+      k_cone_count<<<ncone, 256, 0, s>>>(views.p, sc.geo, sc.cull, n, cone_list.p, cnt.p);
+      PF_HIP_TRY(hipGetLastError());
+    }
     PF_HIP_TRY(hipMemsetAsync(cnt.p + nvc, 0, sizeof(uint32_t), s));
     PF_HIP_TRY(exclusive_scan_u32(cnt.p, off.p, nvc + 1, nullptr, s));
     uint32_t np = 0;
@@ -752,6 +832,9 @@ pf_status raster_views(Scene& sc, const pf_camera* cams, int ncam, float t_min, 
     {
       ProfScope ps("k_view_emit", s);
       k_view_emit<<<g, 256, 0, s>>>(views.p, sc.geo, sc.cull, n, off.p, key.p, ptile.p, pval.p, tcnt.p);
+      if (ncone)
+        k_cone_emit<<<ncone, 256, 0, s>>>(views.p, sc.geo, sc.cull, n, off.p, key.p, cone_list.p, ptile.p, pval.p,
+                                          tcnt.p);
     }
     PF_HIP_TRY(hipGetLastError());
     PF_HIP_TRY(exclusive_scan_u32(tcnt.p, toff.p, ntiles + 1, nullptr, s));
