@@ -117,6 +117,13 @@ __device__ inline void sum_to(float* acc, int i, bool valid, float v) {
 
 __device__ inline float softplus_b(float x) { return x > 20.0f ? x : log1pf(expf(x)); }
 
+// A wave-uniform double moved to scalar registers.
+__device__ inline double uni(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readfirstlane((int)b), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // 1/x in float64: hardware reciprocal refined by two Newton steps (x != 0).
 __device__ inline double rcp_d(double x) {
   double r = __builtin_amdgcn_rcp(x);
@@ -158,7 +165,7 @@ __device__ inline void sv_backward(const float* __restrict__ tx, double ux, doub
   }
 }
 
-__global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) k_bwd_cell(
+__global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3))) k_bwd_cell(
     const pf_camera* __restrict__ cams, const int4* __restrict__ ri, const float4* __restrict__ rf,
     const int32_t* __restrict__ order, const int4* __restrict__ chunks, const float* __restrict__ prm_p,
     const float* __restrict__ radius, const float* __restrict__ normal, const float* __restrict__ lamv,
@@ -188,20 +195,21 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
   const float sigma = sigma_scale * softplus_b(lam);
   const float tau = tau_;
   // float64 face frame (for the displacement chain)
-  const double dninv = 1.0 / sqrt((double)nrx * nrx + (double)nry * nry + (double)nrz * nrz);
-  const double dnx = nrx * dninv, dny = nry * dninv, dnz = nrz * dninv;
-  const double dsg = copysign(1.0, dnz);
+  // (wave-uniform: held in scalar registers)
+  const double dninv = uni(1.0 / sqrt((double)nrx * nrx + (double)nry * nry + (double)nrz * nrz));
+  const double dnx = uni(nrx * dninv), dny = uni(nry * dninv), dnz = uni(nrz * dninv);
+  const double dsg = uni(copysign(1.0, dnz));
   double d1x, d1y, d1z, d2x, d2y, d2z;
-  const double oa = -1.0 / (dsg + dnz);   // Duff et al. frame constant
+  const double oa = uni(-1.0 / (dsg + dnz));   // Duff et al. frame constant
   {
     const double a = oa;
     const double b = dnx * dny * a;
-    d1x = 1.0 + dsg * dnx * dnx * a;
-    d1y = dsg * b;
-    d1z = -dsg * dnx;
-    d2x = b;
-    d2y = dsg + dny * dny * a;
-    d2z = -dny;
+    d1x = uni(1.0 + dsg * dnx * dnx * a);
+    d1y = uni(dsg * b);
+    d1z = uni(-dsg * dnx);
+    d2x = uni(b);
+    d2y = uni(dsg + dny * dny * a);
+    d2z = uni(-dny);
   }
 
   // (site, axis) owned by this lane in the transposed phase
