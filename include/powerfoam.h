@@ -181,18 +181,52 @@ pf_status pf_render_trace(pf_scene* scene, const pf_camera* cams, int32_t ncam,
                           const pf_render_opts* opts, float* rgba,
                           int64_t* truncated, pf_fwd_state** state, void* stream);
 
+/* Options of pf_backward (host struct; all fields may be zero / NULL).
+   The regularisers of the training objective (supplementary material, loss
+   functions) that depend on the rendered rays:
+     L_normal = sum over rays and cells of T a max(n_i . d, 0)^2,
+   with T the transmittance in front of the cell, a its opacity on the ray,
+   n_i its unit normal and d the unit ray direction, is added to L with the
+   weight lambda_normal.  The sparsity loss summed over cells,
+   sum over rays and cells of T a, equals the sum of the rendered opacity A
+   over the rays, so its gradient is obtained by adding its weight to the A
+   channel of d_rgba.  Statistics (device pointers, accumulated with +=):
+   contribution [n] float, per cell sum over the rays of T a (the per-cell
+   sparsity term and the quantity the pruning schedule tracks, Sec. 3.7);
+   normal_loss [1] double, the value of L_normal over the rays. */
+typedef struct {
+  float lambda_normal;
+  float* contribution;
+  double* normal_loss;
+} pf_backward_opts;
+
 /* Gradients of L with respect to all cell parameters given dL/dRGBA
    (d_rgba, same layout as the forward's rgba), for the forward recorded in
    state (Sec. 3.1 sum differentiated through Sec. 3.2-3.6).  Adds into
-   grads (host struct of device pointers).  A recompute-mode state first
-   replays its forward with records (temporary memory as for store mode) and
-   synchronises the stream.  The state stays valid; pf_backward may run
-   again on it.
-   Errors: INVALID (NULL state/scene mismatch), OOM, HIP. */
-pf_status pf_backward(pf_scene* scene, const pf_fwd_state* state, const float* d_rgba,
-                      const pf_grads* grads, void* stream);
+   grads (host struct of device pointers).  opts (host) may be NULL.  A
+   store-mode state is consumed (its records are overwritten): a second
+   pf_backward on it fails with INVALID.  A recompute-mode state replays its
+   forward with records (temporary memory as for store mode), synchronises
+   the stream, and may be used again.
+   Errors: INVALID (NULL argument, state/scene mismatch, consumed state,
+   non-finite lambda_normal), OOM, HIP. */
+pf_status pf_backward(pf_scene* scene, pf_fwd_state* state, const float* d_rgba,
+                      const pf_grads* grads, const pf_backward_opts* opts, void* stream);
 
 void pf_state_release(pf_fwd_state* state);
+
+/* Connectivity loss (supplementary material, loss functions) over the Cech
+   graph of the scene's spheres as built (pairs i != j with
+   |p_i - p_j| < r_i + r_j):
+     lambda * sum_i sum_{j in Cech(i)} max(r_i + r_j - |p_i - p_j|, 0)^2.
+   Adds its gradient into grads->p and grads->radius (the other fields are
+   ignored; either may be NULL) and its value into *loss (device double, may
+   be NULL).  Uses the positions and radii the scene was last built from.
+   Synchronises the stream.
+   Errors: INVALID (NULL scene/grads, non-finite lambda), OVERFLOW (a cell's
+   tree traversal exceeded its stack), HIP. */
+pf_status pf_connect_loss(const pf_scene* scene, float lambda, const pf_grads* grads, double* loss,
+                          void* stream);
 
 /* Device memory estimate (bytes, host output) of a render of cams (what 0),
    of a render with a store-mode forward state (what 1), or of that plus the

@@ -12,7 +12,8 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "OOM", 3: "HIP", 4: "UNSUPPORTED", 5: 
 
 EXPORTS = ("pf_build_scene", "pf_scene_info_get", "pf_scene_adjacency", "pf_scene_destroy",
            "pf_render_raster", "pf_render_trace", "pf_backward", "pf_state_release", "pf_last_error",
-           "pf_profile_enable", "pf_profile_read", "pf_state_info", "pf_update_scene", "pf_query_workspace")
+           "pf_profile_enable", "pf_profile_read", "pf_state_info", "pf_update_scene", "pf_query_workspace",
+           "pf_connect_loss")
 
 
 class PfParams(C.Structure):
@@ -47,6 +48,10 @@ class PfProfileEntry(C.Structure):
     _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double)]
 
 
+class PfBackwardOpts(C.Structure):
+    _fields_ = [("lambda_normal", C.c_float), ("contribution", C.c_void_p), ("normal_loss", C.c_void_p)]
+
+
 class PfGrads(C.Structure):
     _fields_ = [("p", C.c_void_p), ("power", C.c_void_p), ("radius", C.c_void_p),
                 ("normal", C.c_void_p), ("occ_logit", C.c_void_p), ("rgb", C.c_void_p),
@@ -77,7 +82,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                     C.POINTER(i64), C.POINTER(vp), vp]
     lib.pf_update_scene.argtypes = [vp, C.POINTER(PfParams), vp]
     lib.pf_query_workspace.argtypes = [vp, C.POINTER(PfCamera), i32, i32, C.POINTER(i64)]
-    lib.pf_backward.argtypes = [vp, vp, vp, C.POINTER(PfGrads), vp]
+    lib.pf_connect_loss.argtypes = [vp, C.c_float, C.POINTER(PfGrads), vp, vp]
+    lib.pf_backward.argtypes = [vp, vp, vp, C.POINTER(PfGrads), C.POINTER(PfBackwardOpts), vp]
     lib.pf_state_release.argtypes = [vp]
     lib.pf_state_release.restype = None
     lib.pf_state_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]

@@ -256,6 +256,23 @@ def render_trace_state(scene: Scene, cams, t_min: float = 1e-6, max_steps: int =
     return buf, ForwardState(h.value, scene, shapes)
 
 
+def connect_loss(scene: Scene, lam: float, grads: Optional[Dict[str, torch.Tensor]] = None, stream=None):
+    """pf_connect_loss: ``lam * L_connect`` over the scene's sphere-overlap
+    pairs; adds its gradient into grads['p'] / grads['radius'] (if given)
+    and returns the value as a float64 device tensor [1]."""
+    g = L.PfGrads()
+    for f in ("p", "radius"):
+        t = (grads or {}).get(f)
+        if t is not None:
+            if not (t.is_contiguous() and t.dtype == torch.float32 and t.shape == scene.params[f].shape):
+                raise ValueError(f"gradient buffer {f} must be contiguous float32 shaped like the parameter")
+            setattr(g, f, t.data_ptr())
+    val = torch.zeros(1, dtype=torch.float64, device=scene.params["p"].device)
+    L.check(L.load().pf_connect_loss(scene.handle, float(lam), C.byref(g), C.c_void_p(val.data_ptr()),
+                                     C.c_void_p(_stream_ptr(stream))))
+    return val
+
+
 def query_workspace(scene: Scene, cams, what: int = 0) -> int:
     """pf_query_workspace: estimated device bytes of a render (0), a render
     with a store-mode state (1), or that plus the backward (2)."""
@@ -266,9 +283,12 @@ def query_workspace(scene: Scene, cams, what: int = 0) -> int:
 
 
 def backward(scene: Scene, state: ForwardState, d_rgba: torch.Tensor, grads: Dict[str, torch.Tensor],
-             stream=None) -> None:
+             stream=None, lambda_normal: float = 0.0, contribution: Optional[torch.Tensor] = None,
+             normal_loss: Optional[torch.Tensor] = None) -> None:
     """pf_backward: adds dL/dparams into ``grads`` (dict of float32 device
-    tensors shaped like the parameters; missing keys are skipped)."""
+    tensors shaped like the parameters; missing keys are skipped).
+    ``lambda_normal`` adds the normal loss; ``contribution`` (float32 [n])
+    and ``normal_loss`` (float64 [1]) receive the statistics (+=)."""
     d = d_rgba.contiguous()
     if d.dtype != torch.float32:
         raise TypeError("d_rgba must be float32")
@@ -279,5 +299,15 @@ def backward(scene: Scene, state: ForwardState, d_rgba: torch.Tensor, grads: Dic
             if not (t.is_contiguous() and t.dtype == torch.float32 and t.shape == scene.params[f].shape):
                 raise ValueError(f"gradient buffer {f} must be contiguous float32 shaped like the parameter")
             setattr(g, f, t.data_ptr())
-    L.check(L.load().pf_backward(scene.handle, state.handle, C.c_void_p(d.data_ptr()), C.byref(g),
+    o = L.PfBackwardOpts(lambda_normal=float(lambda_normal))
+    if contribution is not None:
+        if not (contribution.is_contiguous() and contribution.dtype == torch.float32
+                and contribution.numel() == scene.params["p"].shape[0]):
+            raise ValueError("contribution must be a contiguous float32 tensor with one entry per cell")
+        o.contribution = contribution.data_ptr()
+    if normal_loss is not None:
+        if not (normal_loss.dtype == torch.float64 and normal_loss.numel() >= 1):
+            raise ValueError("normal_loss must be a float64 tensor")
+        o.normal_loss = normal_loss.data_ptr()
+    L.check(L.load().pf_backward(scene.handle, state.handle, C.c_void_p(d.data_ptr()), C.byref(g), C.byref(o),
                                  C.c_void_p(_stream_ptr(stream))))

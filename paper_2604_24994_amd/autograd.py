@@ -2,7 +2,7 @@
 or pf_render_trace with a forward state, backward = pf_backward (all HIP)."""
 from __future__ import annotations
 
-from typing import List
+from typing import List, Optional
 
 import torch
 
@@ -15,7 +15,8 @@ LAST_FORWARD = {"records": 0}
 
 class _RenderFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, scene: Scene, cams, walk: bool, t_min: float, state_mode: int, *params):
+    def forward(ctx, scene: Scene, cams, walk: bool, t_min: float, state_mode: int, lambda_normal: float,
+                stats, *params):
         for f, t in zip(PARAM_FIELDS, params):
             if t.data_ptr() != scene.params[f].data_ptr():
                 raise ValueError(f"parameter {f} is not the tensor the scene was built from")
@@ -26,22 +27,35 @@ class _RenderFn(torch.autograd.Function):
         LAST_FORWARD["records"] = state.info()["records"]
         ctx.scene = scene
         ctx.state = state
+        ctx.lambda_normal = lambda_normal
+        ctx.stats = stats
         return buf
 
     @staticmethod
     def backward(ctx, g):
-        scene, state = ctx.scene, ctx.state
+        scene, state, stats = ctx.scene, ctx.state, ctx.stats
         grads = {f: torch.zeros_like(scene.params[f]) for f in PARAM_FIELDS}
-        backward(scene, state, g.contiguous(), grads)
+        contribution = normal_loss = None
+        if stats is not None:
+            dev = scene.params["p"].device
+            contribution = torch.zeros(scene.params["p"].shape[0], dtype=torch.float32, device=dev)
+            normal_loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        backward(scene, state, g.contiguous(), grads, lambda_normal=ctx.lambda_normal, contribution=contribution,
+                 normal_loss=normal_loss)
         state.release()
-        return (None, None, None, None, None) + tuple(grads[f] for f in PARAM_FIELDS)
+        if stats is not None:
+            stats["contribution"] = contribution
+            stats["normal_loss"] = normal_loss
+        return (None,) * 7 + tuple(grads[f] for f in PARAM_FIELDS)
 
 
-def _render_diff(scene: Scene, cams, walk: bool, t_min: float, state_mode: int) -> List[torch.Tensor]:
+def _render_diff(scene: Scene, cams, walk: bool, t_min: float, state_mode: int, lambda_normal: float,
+                 stats) -> List[torch.Tensor]:
     if not isinstance(cams, (list, tuple)):
         cams = [cams]
     p = scene.params
-    flat = _RenderFn.apply(scene, cams, walk, t_min, state_mode, *[p[f] for f in PARAM_FIELDS])
+    flat = _RenderFn.apply(scene, cams, walk, t_min, state_mode, float(lambda_normal), stats,
+                           *[p[f] for f in PARAM_FIELDS])
     out, off = [], 0
     for c in cams:
         n = 4 * c.width * c.height
@@ -50,15 +64,21 @@ def _render_diff(scene: Scene, cams, walk: bool, t_min: float, state_mode: int) 
     return out
 
 
-def render_raster_diff(scene: Scene, cams, t_min: float = 1e-6, state_mode: int = STORE) -> List[torch.Tensor]:
+def render_raster_diff(scene: Scene, cams, t_min: float = 1e-6, state_mode: int = STORE,
+                       lambda_normal: float = 0.0, stats: Optional[dict] = None) -> List[torch.Tensor]:
     """Differentiable raster render: list of [H,W,4] images whose gradient
     flows into ``scene.params`` (build the scene from leaf tensors with
     requires_grad=True).  state_mode RECOMPUTE keeps no records between the
-    forward and the backward."""
-    return _render_diff(scene, cams, False, t_min, state_mode)
+    forward and the backward.  ``lambda_normal`` adds the normal loss of the
+    rendered rays to the objective (its gradient joins the backward); a
+    ``stats`` dict receives, after backward, 'contribution' (per-cell sum of
+    T a) and 'normal_loss' (the unweighted loss value).  The sparsity loss
+    summed over cells is the sum of the A channel of the images."""
+    return _render_diff(scene, cams, False, t_min, state_mode, lambda_normal, stats)
 
 
-def render_trace_diff(scene: Scene, cams, t_min: float = 1e-6, state_mode: int = STORE) -> List[torch.Tensor]:
+def render_trace_diff(scene: Scene, cams, t_min: float = 1e-6, state_mode: int = STORE,
+                      lambda_normal: float = 0.0, stats: Optional[dict] = None) -> List[torch.Tensor]:
     """Differentiable ray-walk render (same images and gradients as the
     raster up to rounding)."""
-    return _render_diff(scene, cams, True, t_min, state_mode)
+    return _render_diff(scene, cams, True, t_min, state_mode, lambda_normal, stats)

@@ -30,6 +30,7 @@ struct pf_fwd_state {
   std::vector<pf_camera> cams;
   int kind = 0;          // 0 raster, 1 ray walk
   int mode = 0;          // 0 records stored, 1 recomputed by pf_backward
+  bool consumed = false; // store mode: pf_backward has overwritten the records
   float t_min = 1e-6f;
   int max_steps = 4096;
 };
@@ -420,12 +421,25 @@ pf_status pf_render_trace(pf_scene* scene, const pf_camera* cams, int32_t ncam, 
   return PF_OK;
 }
 
-pf_status pf_backward(pf_scene* scene, const pf_fwd_state* state, const float* d_rgba, const pf_grads* grads,
-                      void* stream) {
+pf_status pf_backward(pf_scene* scene, pf_fwd_state* state, const float* d_rgba, const pf_grads* grads,
+                      const pf_backward_opts* opts, void* stream) {
   if (!scene || !state || !d_rgba || !grads) return invalid("pf_backward: NULL argument");
   if (state->scene != scene) return invalid("pf_backward: the state belongs to another scene");
+  if (state->consumed)
+    return invalid("pf_backward: this store-mode state was already used by pf_backward (its records are "
+                   "overwritten); render again");
+  pf::BwdOpts bo;
+  if (opts) {
+    if (!std::isfinite(opts->lambda_normal)) return invalid("pf_backward: lambda_normal must be finite");
+    bo.lambda_normal = opts->lambda_normal;
+    bo.contribution = opts->contribution;
+    bo.normal_loss = opts->normal_loss;
+  }
   hipStream_t s = (hipStream_t)stream;
-  if (state->mode == 0) return pf::backward_impl(scene->s, state->st, d_rgba, *grads, s);
+  if (state->mode == 0) {
+    state->consumed = true;
+    return pf::backward_impl(scene->s, state->st, d_rgba, *grads, bo, s);
+  }
   // recompute mode: replay the forward with records into a temporary state
   pf_fwd_state* tmp = nullptr;
   pf_status st = new_state(scene, state->cams.data(), (int32_t)state->cams.size(), state->kind, 0, state->t_min,
@@ -440,7 +454,7 @@ pf_status pf_backward(pf_scene* scene, const pf_fwd_state* state, const float* d
     st = e == hipErrorOutOfMemory ? PF_ERR_OOM : PF_ERR_HIP;
   }
   if (st == PF_OK) st = fill_records(tmp, scratch, trunc, s, "pf_backward");
-  if (st == PF_OK) st = pf::backward_impl(scene->s, tmp->st, d_rgba, *grads, s);
+  if (st == PF_OK) st = pf::backward_impl(scene->s, tmp->st, d_rgba, *grads, bo, s);
   if (st == PF_OK) {
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -453,6 +467,12 @@ pf_status pf_backward(pf_scene* scene, const pf_fwd_state* state, const float* d
   free_state_mem(tmp);
   delete tmp;
   return st;
+}
+
+pf_status pf_connect_loss(const pf_scene* scene, float lambda, const pf_grads* grads, double* loss, void* stream) {
+  if (!scene || !grads) return invalid("pf_connect_loss: NULL argument");
+  if (!std::isfinite(lambda)) return invalid("pf_connect_loss: lambda must be finite");
+  return pf::connect_loss_impl(scene->s, lambda, *grads, loss, (hipStream_t)stream);
 }
 
 pf_status pf_query_workspace(const pf_scene* scene, const pf_camera* cams, int32_t ncam, int32_t what,

@@ -7,6 +7,9 @@
 //                   Cb_{k} = a_k c_k + (1 - a_k) Cb_{k+1},  Ab likewise,
 //                 dL/da_k = T_k (gC.(c_k - Cb_{k+1}) + gA (1 - Ab_{k+1})),
 //                 dL/dc_k = T_k a_k gC                      (Sec. 3.1 sum)
+//                 plus, with the normal loss, the same for the scalar
+//                 channel max(n.d, 0)^2 weighted by lambda_normal; the
+//                 record's T becomes the contribution T a
 //   k_seg_hist /  records grouped by cell through the forward's segment list
 //   k_seg_scatter (one atomic per segment of <= 64 contiguous records)
 //   k_bwd_cell    one wave per chunk of a cell's records, 64 records at a
@@ -35,29 +38,56 @@ constexpr int CHUNK = 2048;         // records per workgroup
 constexpr int FMAX_B = 128;         // faces gathered in LDS; faces beyond add to global directly
 constexpr int NCELL = 12;           // p(3) w r n(3) lambda rgb(3)
 constexpr int NSUM = NCELL + 3 * KD;  // + detail-site s(2), d per site
+constexpr int ISTAT = NSUM;           // + the cell's contribution sum (statistic)
 constexpr int KPAD = 65;            // row pitch of the per-site LDS table (bank spread)
 
 __global__ void k_suffix(const int32_t* __restrict__ head, int64_t npix, const float* __restrict__ d_rgba,
-                         const int4* __restrict__ ri, float4* __restrict__ rf, const float* __restrict__ rt) {
+                         const int4* __restrict__ ri, float4* __restrict__ rf, float* __restrict__ rt,
+                         const pf_camera* __restrict__ cams, const float4* __restrict__ nrm, float lambda_n,
+                         double* __restrict__ normal_loss) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= npix) return;
-  int k = head[i];
-  if (k < 0) return;
-  const float gr = d_rgba[4 * i], gg = d_rgba[4 * i + 1], gb = d_rgba[4 * i + 2], ga = d_rgba[4 * i + 3];
-  float cr = 0.0f, cg = 0.0f, cb = 0.0f, ab = 0.0f;
-  while (k >= 0) {
-    const int4 r = ri[k];
-    const float4 f = rf[k];
-    const float T = rt[k];
-    const float a = f.x;
-    const float g_alpha = T * (gr * (f.y - cr) + gg * (f.z - cg) + gb * (f.w - cb) + ga * (1.0f - ab));
-    const float ta = T * a;
-    rf[k] = make_float4(g_alpha, ta * gr, ta * gg, ta * gb);
-    cr = a * f.y + (1.0f - a) * cr;
-    cg = a * f.z + (1.0f - a) * cg;
-    cb = a * f.w + (1.0f - a) * cb;
-    ab = a + (1.0f - a) * ab;
-    k = r.z;
+  int k = i < npix ? head[i] : -1;
+  double lpix = 0.0;   // this pixel's sum of T a max(n.d, 0)^2
+  if (k >= 0) {
+    const float gr = d_rgba[4 * i], gg = d_rgba[4 * i + 1], gb = d_rgba[4 * i + 2], ga = d_rgba[4 * i + 3];
+    float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+    if (lambda_n != 0.0f || normal_loss) {
+      const int4 r0 = ri[k];
+      const pf_camera& cam = cams[r0.w >> 20];
+      const RayD R = make_ray(cam, r0.y % cam.width + 0.5, r0.y / cam.width + 0.5);
+      fx = R.fx;
+      fy = R.fy;
+      fz = R.fz;
+    }
+    float cr = 0.0f, cg = 0.0f, cb = 0.0f, ab = 0.0f, nb = 0.0f;
+    while (k >= 0) {
+      const int4 r = ri[k];
+      const float4 f = rf[k];
+      const float T = rt[k];
+      const float a = f.x;
+      float nu = 0.0f;
+      if (lambda_n != 0.0f || normal_loss) {
+        const float4 nv = nrm[r.x];
+        const float c = fmaxf(nv.x * fx + nv.y * fy + nv.z * fz, 0.0f);
+        nu = c * c;
+      }
+      const float g_alpha = T * (gr * (f.y - cr) + gg * (f.z - cg) + gb * (f.w - cb) + ga * (1.0f - ab) +
+                                 lambda_n * (nu - nb));
+      const float ta = T * a;
+      rf[k] = make_float4(g_alpha, ta * gr, ta * gg, ta * gb);
+      rt[k] = ta;   // the contribution T a (read by the per-cell pass)
+      lpix += (double)ta * (double)nu;
+      cr = a * f.y + (1.0f - a) * cr;
+      cg = a * f.z + (1.0f - a) * cg;
+      cb = a * f.w + (1.0f - a) * cb;
+      ab = a + (1.0f - a) * ab;
+      nb = a * nu + (1.0f - a) * nb;
+      k = r.z;
+    }
+  }
+  if (normal_loss) {
+    for (int o = 32; o > 0; o >>= 1) lpix += __shfl_xor(lpix, o, 64);
+    if ((threadIdx.x & 63) == 0 && lpix != 0.0) atomicAdd(normal_loss, lpix);
   }
 }
 
@@ -170,11 +200,12 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     const int32_t* __restrict__ order, const int4* __restrict__ chunks, const float* __restrict__ prm_p,
     const float* __restrict__ radius, const float* __restrict__ normal, const float* __restrict__ lamv,
     const float* __restrict__ tex, const int32_t* __restrict__ row, const int32_t* __restrict__ nrast,
-    const int32_t* __restrict__ col, const float4* __restrict__ plane, float sigma_scale, float tau_, pf_grads G) {
+    const int32_t* __restrict__ col, const float4* __restrict__ plane, float sigma_scale, float tau_, pf_grads G,
+    const float* __restrict__ rta, float lambda_n, float* __restrict__ contribution) {
   __shared__ float4 st_dir[64];          // per record: ray direction (float), 0
   __shared__ float4 st_gc[64];           // per record: dL/dc, 0
   __shared__ float2 st_k[KD][KPAD];      // per record and site: softmax shift, dL/dw_k
-  __shared__ float acc[NSUM];
+  __shared__ float acc[NSUM + 1];
   __shared__ float4 facc[FMAX_B];
 
   const int4 ch = chunks[blockIdx.x];
@@ -184,7 +215,7 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
   const int nf = nrast[ci];
   const int nfl = min(nf, FMAX_B);
   const float* __restrict__ txc = tex + (int64_t)ci * KD * TEXW;
-  for (int t = lane; t < NSUM; t += BWD_THREADS) acc[t] = 0.0f;
+  for (int t = lane; t < NSUM + 1; t += BWD_THREADS) acc[t] = 0.0f;
   for (int t = lane; t < nfl; t += BWD_THREADS) facc[t] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 
   // cell constants, computed exactly as the build's per-cell record
@@ -229,10 +260,12 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     const int nvalid = min(64, ch.z - base);
     int4 rec = make_int4(0, 0, -1, 0);
     float4 gf = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float ta = 0.0f;   // the contribution T a
     if (valid) {
       const int ridx = order[idx];
       rec = ri[ridx];
       gf = rf[ridx];
+      ta = rta[ridx];
     }
     const int view = rec.w >> 20;
     const int b0 = ((rec.w >> 10) & 1023) - 2, b1 = (rec.w & 1023) - 2;
@@ -405,6 +438,16 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     double gnzd = gnz_h + g1x * sg * dnx * dnx * oa2 + g1y * sg * dnx * dny * oa2 + g2x * dnx * dny * oa2 +
                   g2y * dny * dny * oa2;
     // nhat = n / |n|
+    // normal loss: d/dnhat of lambda T a max(nhat.d, 0)^2
+    if (lambda_n != 0.0f) {
+      const double c = ddx * dnx + ddy * dny + ddz * dnz;
+      if (c > 0.0) {
+        const double gk = 2.0 * (double)lambda_n * (double)ta * c;
+        gnxd += gk * ddx;
+        gnyd += gk * ddy;
+        gnzd += gk * ddz;
+      }
+    }
     const double gdot = gnxd * dnx + gnyd * dny + gnzd * dnz;
     const float gnx = (float)((gnxd - gdot * dnx) * dninv);
     const float gny = (float)((gnyd - gdot * dny) * dninv);
@@ -471,6 +514,7 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
       const float cellv[NCELL] = {gpx, gpy, gpz, g_wi, g_r, gnx, gny, gnz, g_lam, gcr, gcg, gcb};
 #pragma unroll
       for (int i = 0; i < NCELL; ++i) sum_to(acc, i, valid, cellv[i]);
+      if (contribution) sum_to(acc, ISTAT, valid, ta);
     }
 
     // ---------------- Spherical-Voronoi gradients, lane = (site k, axis m):
@@ -513,6 +557,7 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     }
     if (dst) atomicAdd(dst, v);
   }
+  if (contribution && lane == 0 && acc[ISTAT] != 0.0f) atomicAdd(contribution + ci, acc[ISTAT]);
   if (G.tex) {
     float* gt = G.tex + (int64_t)ci * KD * TEXW + km * TEXW;
     const float va[3] = {gax, gay, gaz}, vc[3] = {gcr_a, gcg_a, gcb_a};
@@ -547,14 +592,15 @@ struct Buf {
 }  // namespace
 
 pf_status backward_impl(const Scene& sc, const BwdState& st, const float* d_rgba, const pf_grads& g,
-                        hipStream_t s) {
+                        const BwdOpts& opt, hipStream_t s) {
   const int64_t n = sc.n;
   const int64_t nrec = st.nrec;
   if (nrec == 0) return PF_OK;
   const unsigned gp = (unsigned)((st.npix + 255) / 256);
   {
     ProfScope ps("k_suffix", s);
-    k_suffix<<<gp, 256, 0, s>>>(st.rec.head, st.npix, d_rgba, st.rec.ri, st.rec.rf, st.rec.rt);
+    k_suffix<<<gp, 256, 0, s>>>(st.rec.head, st.npix, d_rgba, st.rec.ri, st.rec.rf, st.rec.rt, st.cams_dev, sc.nrm,
+                                opt.lambda_normal, opt.normal_loss);
   }
   PF_HIP_TRY(hipGetLastError());
   Buf<uint32_t> cnt(s), off(s), fill(s), nch(s), choff(s);
@@ -594,7 +640,8 @@ pf_status backward_impl(const Scene& sc, const BwdState& st, const float* d_rgba
     ProfScope ps("k_bwd_cell", s);
     k_bwd_cell<<<nchunks, BWD_THREADS, 0, s>>>(st.cams_dev, st.rec.ri, st.rec.rf, order.p, chunks.p, sc.prm.p,
                                                 sc.prm.radius, sc.prm.normal, sc.prm.occ_logit, sc.prm.tex, sc.row,
-                                                sc.nrast, sc.col, sc.plane, sc.prm.sigma_scale, sc.prm.tau, g);
+                                                sc.nrast, sc.col, sc.plane, sc.prm.sigma_scale, sc.prm.tau, g,
+                                                st.rec.rt, opt.lambda_normal, opt.contribution);
   }
   PF_HIP_TRY(hipGetLastError());
   return PF_OK;

@@ -13,7 +13,15 @@ struct BwdState {
   pf_camera* cams_dev = nullptr;
 };
 
+// Options of the backward: normal-loss weight and the statistic outputs
+// (device pointers, may be null).
+struct BwdOpts {
+  float lambda_normal = 0.0f;
+  float* contribution = nullptr;   // [n] += sum of T a per cell
+  double* normal_loss = nullptr;   // [1] += sum of T a max(n.d, 0)^2
+};
+
 pf_status backward_impl(const Scene& sc, const BwdState& st, const float* d_rgba, const pf_grads& g,
-                        hipStream_t s);
+                        const BwdOpts& o, hipStream_t s);
 
 }  // namespace pf

@@ -34,17 +34,11 @@ constexpr int SPL_MID = 4;        // vertex slots per lane of the second pass
 constexpr int PM_BIG = 256;       // plane capacity of the third pass (edge table in HBM)
 constexpr int SPL_BIG = 8;        // vertex slots per lane of the third pass
 constexpr int STACK = 256;       // traversal stack (tree depth x 63 + 64 entries suffice up to ~8M sites)
-constexpr int MAXLVL = 8;
 constexpr int RING_K = 16;        // rank of the leaf mate that sets the first ring radius
 // Upper bound on candidate clips plus node visits per cell; a cell that
 // reaches it is reported as over capacity instead of running on.
 constexpr int WORK_LIMIT = 1 << 22;
 
-struct Levels {
-  int n;                          // number of node levels (>= 1)
-  long long off[MAXLVL];          // offset of level L (1-based) in the node arrays
-  long long cnt[MAXLVL + 1];      // cnt[0] = sites, cnt[L] = nodes at level L
-};
 
 __device__ inline uint32_t spread10(uint32_t v) {
   v &= 1023u;
@@ -152,22 +146,25 @@ __global__ void k_morton(const float* __restrict__ p, int64_t n, float3 lo, floa
 }
 
 __global__ void k_gather_sites(const float* __restrict__ p, const float* __restrict__ w,
-                               const uint32_t* __restrict__ order, int64_t n, float4* __restrict__ sp,
-                               int32_t* __restrict__ sidx) {
+                               const float* __restrict__ r, const uint32_t* __restrict__ order, int64_t n,
+                               float4* __restrict__ sp, int32_t* __restrict__ sidx, float* __restrict__ srad) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   uint32_t i = order[k];
   sp[k] = make_float4(p[3 * i], p[3 * i + 1], p[3 * i + 2], w[i]);
   sidx[k] = (int32_t)i;
+  srad[k] = r[i];
 }
 
 // One wave per parent node: AABB and max weight of up to 64 children.
-__global__ void __launch_bounds__(64) k_tree_level(const float4* __restrict__ sp, const float4* __restrict__ clo,
-                                                   const float4* __restrict__ chi, int64_t nchild,
-                                                   float4* __restrict__ olo, float4* __restrict__ ohi) {
+__global__ void __launch_bounds__(64) k_tree_level(const float4* __restrict__ sp, const float* __restrict__ srad,
+                                                   const float4* __restrict__ clo, const float4* __restrict__ chi,
+                                                   int64_t nchild, float4* __restrict__ olo,
+                                                   float4* __restrict__ ohi) {
   const int lane = threadIdx.x;
   const int64_t c = (int64_t)blockIdx.x * 64 + lane;
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, w = -INFINITY;
+  float rmax = 0.0f;
   if (c < nchild) {
     if (sp) {
       float4 s = sp[c];
@@ -175,10 +172,12 @@ __global__ void __launch_bounds__(64) k_tree_level(const float4* __restrict__ sp
       lo[1] = hi[1] = s.y;
       lo[2] = hi[2] = s.z;
       w = s.w;
+      rmax = srad[c];
     } else {
       float4 a = clo[c], b = chi[c];
       lo[0] = a.x; lo[1] = a.y; lo[2] = a.z; w = a.w;
       hi[0] = b.x; hi[1] = b.y; hi[2] = b.z;
+      rmax = b.w;
     }
   }
 #pragma unroll
@@ -187,9 +186,10 @@ __global__ void __launch_bounds__(64) k_tree_level(const float4* __restrict__ sp
     hi[a] = wave_max(hi[a]);
   }
   w = wave_max(w);
+  rmax = wave_max(rmax);
   if (lane == 0) {
     olo[blockIdx.x] = make_float4(lo[0], lo[1], lo[2], w);
-    ohi[blockIdx.x] = make_float4(hi[0], hi[1], hi[2], 0.0f);
+    ohi[blockIdx.x] = make_float4(hi[0], hi[1], hi[2], rmax);
   }
 }
 
@@ -842,6 +842,95 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
   }
 }
 
+
+// Connectivity loss over the Cech graph (supplementary material, loss
+// functions): one wave per cell i walks the site tree for the spheres that
+// overlap B(p_i, r_i) (nodes pruned by box distance > r_i + largest radius
+// below).  With ov_ij = r_i + r_j - d_ij, each overlapping pair appears in
+// L(i) and in L(j), so the derivative of the total with respect to r_i is
+// 4 lambda sum_j ov_ij and with respect to p_i is
+// 4 lambda sum_j ov_ij (p_j - p_i)/d_ij; every cell adds only its own
+// gradient, so no atomics touch a neighbour.
+__global__ void __launch_bounds__(64) k_connect(const float4* __restrict__ sp, const float* __restrict__ srad,
+                                                const int32_t* __restrict__ sidx, int64_t n,
+                                                const float4* __restrict__ nlo, const float4* __restrict__ nhi,
+                                                Levels lv, float lambda, float* __restrict__ gp,
+                                                float* __restrict__ gr, double* __restrict__ loss,
+                                                unsigned int* __restrict__ overflow) {
+  __shared__ int stack[STACK];
+  const int lane = threadIdx.x;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t k = blockIdx.x;
+  const float4 me = sp[k];
+  const double px = me.x, py = me.y, pz = me.z, ri = srad[k];
+  double lsum = 0.0, gsum = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+  int top = 1;
+  if (lane == 0) stack[0] = (lv.n << 24) | 0;
+  __syncthreads();
+  while (top > 0) {
+    const int ent = stack[top - 1];
+    --top;
+    const int L = ent >> 24;
+    const long long idx = ent & 0xFFFFFF;
+    if (L == 1) {
+      const int64_t j = idx * LEAF + lane;
+      if (j < n && j != k) {
+        const float4 q = sp[j];
+        const double dx = (double)q.x - px, dy = (double)q.y - py, dz = (double)q.z - pz;
+        const double rs = ri + (double)srad[j];
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        if (d2 < rs * rs) {
+          const double d = sqrt(d2);
+          const double ov = rs - d;
+          lsum += ov * ov;
+          gsum += ov;
+          if (d > 0.0) {   // d ov / d p_i = (p_j - p_i) / d
+            gx += ov * dx / d;
+            gy += ov * dy / d;
+            gz += ov * dz / d;
+          }
+        }
+      }
+      continue;
+    }
+    const long long cidx = idx * 64 + lane;
+    bool keep = false;
+    if (cidx < lv.cnt[L - 1]) {
+      const float4 a = nlo[lv.off[L - 1] + cidx], b = nhi[lv.off[L - 1] + cidx];
+      const double ex = fmax(0.0, fmax((double)a.x - px, px - (double)b.x));
+      const double ey = fmax(0.0, fmax((double)a.y - py, py - (double)b.y));
+      const double ez = fmax(0.0, fmax((double)a.z - pz, pz - (double)b.z));
+      const double reach = ri + (double)b.w;
+      keep = ex * ex + ey * ey + ez * ez < reach * reach;
+    }
+    const uint64_t m = __ballot(keep);
+    const int nc = __popcll(m);
+    if (top + nc > STACK) {
+      if (lane == 0) atomicAdd(overflow, 1u);
+      break;
+    }
+    if (keep) stack[top + __popcll(m & lt)] = ((L - 1) << 24) | (int)cidx;
+    top += nc;
+    __syncthreads();
+  }
+  lsum = wave_sum_d(lsum);
+  gsum = wave_sum_d(gsum);
+  gx = wave_sum_d(gx);
+  gy = wave_sum_d(gy);
+  gz = wave_sum_d(gz);
+  if (lane == 0) {
+    const int32_t self = sidx[k];
+    const double f = 4.0 * (double)lambda;
+    if (gr && gsum != 0.0) atomicAdd(gr + self, (float)(f * gsum));
+    if (gp && (gx != 0.0 || gy != 0.0 || gz != 0.0)) {
+      atomicAdd(gp + 3 * (int64_t)self, (float)(f * gx));
+      atomicAdd(gp + 3 * (int64_t)self + 1, (float)(f * gy));
+      atomicAdd(gp + 3 * (int64_t)self + 2, (float)(f * gz));
+    }
+    if (loss && lsum != 0.0) atomicAdd(loss, (double)lambda * lsum);
+  }
+}
+
 __global__ void k_list_overflow(const int32_t* __restrict__ flags, const int32_t* __restrict__ spos, int64_t n,
                                 int32_t* __restrict__ klist, unsigned int* __restrict__ nlist) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -923,14 +1012,42 @@ struct DevBuf {
 
 }  // namespace
 
+pf_status connect_loss_impl(const Scene& sc, float lambda, const pf_grads& g, double* loss_dev, hipStream_t s) {
+  if (!sc.t_sp) {
+    set_error("pf_connect_loss: the scene has no site tree");
+    return PF_ERR_INVALID;
+  }
+  DevBuf<unsigned int> ovf(s);
+  PF_HIP_TRY(ovf.alloc(1));
+  PF_HIP_TRY(hipMemsetAsync(ovf.p, 0, sizeof(unsigned int), s));
+  {
+    ProfScope ps("k_connect", s);
+    k_connect<<<(unsigned)sc.n, 64, 0, s>>>(sc.t_sp, sc.t_srad, sc.t_sidx, sc.n, sc.t_lo, sc.t_hi, sc.t_lv, lambda,
+                                            g.p, g.radius, loss_dev, ovf.p);
+  }
+  PF_HIP_TRY(hipGetLastError());
+  unsigned int h = 0;
+  PF_HIP_TRY(hipMemcpyAsync(&h, ovf.p, sizeof(h), hipMemcpyDeviceToHost, s));
+  PF_HIP_TRY(hipStreamSynchronize(s));
+  if (h) {
+    set_error("pf_connect_loss: " + std::to_string(h) + " cells exceeded the traversal stack");
+    return PF_ERR_OVERFLOW;
+  }
+  return PF_OK;
+}
+
 void free_scene(Scene* sc) {
-  void* ptrs[] = {sc->geo, sc->nrm, sc->cull, sc->flags, sc->row, sc->nrast, sc->col, sc->plane};
+  void* ptrs[] = {sc->geo,  sc->nrm,    sc->cull,   sc->flags, sc->row,  sc->nrast, sc->col,
+                  sc->plane, sc->t_sp, sc->t_sidx, sc->t_srad, sc->t_lo, sc->t_hi};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   sc->geo = sc->nrm = nullptr;
   sc->cull = nullptr;
   sc->flags = sc->row = sc->nrast = sc->col = nullptr;
   sc->plane = nullptr;
+  sc->t_sp = sc->t_lo = sc->t_hi = nullptr;
+  sc->t_sidx = nullptr;
+  sc->t_srad = nullptr;
 }
 
 pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipStream_t s, Scene* sc) {
@@ -991,17 +1108,19 @@ pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipSt
   k_morton<<<g256, 256, 0, s>>>(prm.p, n, bmin, inv, keys.p, order.p);
   PF_HIP_TRY(hipGetLastError());
   PF_HIP_TRY(radix_sort_u32(keys.p, order.p, n, 30, s));
-  DevBuf<float4> sp(s);
-  DevBuf<int32_t> sidx(s);
-  PF_HIP_TRY(sp.alloc(n));
-  PF_HIP_TRY(sidx.alloc(n));
-  k_gather_sites<<<g256, 256, 0, s>>>(prm.p, prm.power, order.p, n, sp.p, sidx.p);
+  // the sorted sites and the tree stay with the scene (sphere-overlap queries)
+  PF_HIP_TRY(hipMalloc((void**)&sc->t_sp, sizeof(float4) * n));
+  PF_HIP_TRY(hipMalloc((void**)&sc->t_sidx, sizeof(int32_t) * n));
+  PF_HIP_TRY(hipMalloc((void**)&sc->t_srad, sizeof(float) * n));
+  struct { float4* p; } sp{sc->t_sp};
+  struct { int32_t* p; } sidx{sc->t_sidx};
+  k_gather_sites<<<g256, 256, 0, s>>>(prm.p, prm.power, prm.radius, order.p, n, sp.p, sidx.p, sc->t_srad);
   PF_HIP_TRY(hipGetLastError());
 
-  // implicit 64-ary tree over n sorted sites: per node the box of its sites
-  // and their largest weight
-  auto build_tree = [&](const float4* sites, int64_t count, Levels& lvl, DevBuf<float4>& lo_b,
-                        DevBuf<float4>& hi_b) -> pf_status {
+  // implicit 64-ary tree over n sorted sites: per node the box of its sites,
+  // their largest weight and largest sphere radius
+  auto build_tree = [&](const float4* sites, const float* srad, int64_t count, Levels& lvl, float4*& lo_p,
+                        float4*& hi_p) -> pf_status {
     lvl = Levels{};
     lvl.cnt[0] = count;
     long long total_nodes = 0;
@@ -1017,24 +1136,24 @@ pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipSt
       total_nodes += lvl.cnt[L];
     } while (lvl.cnt[L] > 1);
     lvl.n = L;
-    PF_HIP_TRY(lo_b.alloc(total_nodes));
-    PF_HIP_TRY(hi_b.alloc(total_nodes));
+    PF_HIP_TRY(hipMalloc((void**)&lo_p, sizeof(float4) * total_nodes));
+    PF_HIP_TRY(hipMalloc((void**)&hi_p, sizeof(float4) * total_nodes));
     for (int l = 1; l <= lvl.n; ++l) {
       const bool from_sites = l == 1;
-      k_tree_level<<<(unsigned)lvl.cnt[l], 64, 0, s>>>(from_sites ? sites : nullptr,
-                                                       from_sites ? nullptr : lo_b.p + lvl.off[l - 1],
-                                                       from_sites ? nullptr : hi_b.p + lvl.off[l - 1],
-                                                       lvl.cnt[l - 1], lo_b.p + lvl.off[l], hi_b.p + lvl.off[l]);
+      k_tree_level<<<(unsigned)lvl.cnt[l], 64, 0, s>>>(from_sites ? sites : nullptr, from_sites ? srad : nullptr,
+                                                       from_sites ? nullptr : lo_p + lvl.off[l - 1],
+                                                       from_sites ? nullptr : hi_p + lvl.off[l - 1],
+                                                       lvl.cnt[l - 1], lo_p + lvl.off[l], hi_p + lvl.off[l]);
       PF_HIP_TRY(hipGetLastError());
     }
     return PF_OK;
   };
-  Levels lv{};
-  DevBuf<float4> nlo(s), nhi(s);
   {
-    const pf_status st = build_tree(sp.p, n, lv, nlo, nhi);
+    const pf_status st = build_tree(sp.p, sc->t_srad, n, sc->t_lv, sc->t_lo, sc->t_hi);
     if (st != PF_OK) return st;
   }
+  const Levels lv = sc->t_lv;
+  struct { float4* p; } nlo{sc->t_lo}, nhi{sc->t_hi};
 
   // per-cell clipping
   PF_HIP_TRY(hipMalloc((void**)&sc->cull, sizeof(float) * n));

@@ -25,6 +25,16 @@ constexpr int FLAG_OVER_PLANES = 8;   //   live planes
 constexpr int FLAG_OVER_WORK = 16;    //   work limit
 constexpr int FLAG_OVER_STACK = 32;   //   traversal stack
 
+// Implicit 64-ary tree over the Morton-sorted sites: level 0 = sites,
+// level L >= 1 = nodes (box of their sites; lo.w = largest weight, hi.w =
+// largest sphere radius).
+constexpr int MAXLVL = 8;
+struct Levels {
+  int n;                          // number of node levels (>= 1)
+  long long off[MAXLVL];          // offset of level L (1-based) in the node arrays
+  long long cnt[MAXLVL + 1];      // cnt[0] = sites, cnt[L] = nodes at level L
+};
+
 struct Scene {
   int64_t n = 0;
   pf_params prm{};                 // caller arrays (device) and constants
@@ -44,6 +54,13 @@ struct Scene {
   double rec_per_pixel = 0.0;      // record-pool sizing hint for store mode (0: none yet)
   double seg_per_pixel = 0.0;      // segment-list sizing hint for store mode
   double pairs_per_cell = 0.0;     // tile pairs per (view, cell) of the last raster
+  // the build's site tree, kept for the sphere-overlap (Cech) queries
+  float4* t_sp = nullptr;          // [n] sorted (p, w)
+  int32_t* t_sidx = nullptr;       // [n] original index
+  float* t_srad = nullptr;         // [n] sorted radius
+  float4* t_lo = nullptr;          // node boxes
+  float4* t_hi = nullptr;
+  Levels t_lv{};
 };
 
 // Contribution records written by the store-mode forward: one per (pixel,
@@ -90,6 +107,9 @@ hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int bits,
 pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt,
                            hipStream_t s, Scene* sc);
 void free_scene(Scene* sc);
+// lambda * sum_i sum_{j overlapping i} max(r_i + r_j - |p_i - p_j|, 0)^2 and
+// its gradient (adds into g.p and g.radius; the value into *loss_dev).
+pf_status connect_loss_impl(const Scene& sc, float lambda, const pf_grads& g, double* loss_dev, hipStream_t s);
 
 // --- kernel timing (pf_api.hip) ----------------------------------------
 bool profiling();
