@@ -50,11 +50,11 @@ FLOPS_BWD_PER_CONTRIB = 5100
 # for the kernel sources with these hashes; otherwise the bench reports null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC = {
-    "k_bwd_cell": {"fetch_kib": 6806427.3, "write_kib": 2406927.8,
-                   "sources": {"pf_backward.hip": "54980780d8382c63", "pf_shade.hpp": "68feb93f5734438a"}},
-    "k_raster_store": {"fetch_kib": 16127326.9, "write_kib": 10842619.0,
-                       "sources": {"pf_render.hip": "bc26bfe8245641a9", "pf_shade.hpp": "68feb93f5734438a"}},
-    "k_clip": {"fetch_kib": 235659.8, "write_kib": 157998.6, "sources": {"pf_build.hip": "e7291eee51bbc5bd"}},
+    "k_bwd_cell": {"fetch_kib": 19504576.4, "write_kib": 12987314.6,
+                   "sources": {"pf_backward.hip": "4ab52cb1a0f0b1f6", "pf_shade.hpp": "68feb93f5734438a"}},
+    "k_raster_store": {"fetch_kib": 15588900.5, "write_kib": 10838922.3,
+                       "sources": {"pf_render.hip": "7c11b6fd407d2604", "pf_shade.hpp": "68feb93f5734438a"}},
+    "k_clip": {"fetch_kib": 235525.2, "write_kib": 158005.2, "sources": {"pf_build.hip": "f80dfac28e6708f5"}},
 }
 
 
