@@ -28,7 +28,7 @@ M_AXES = 8        # Spherical-Voronoi axes per detail site (Sec. 3.6)
 SIGMA_SCALE = 10.0  # density scale per world unit (scene constant)
 TAU = 20.0          # soft-Voronoi temperature per world unit (scene constant)
 
-SEED_SCENE, SEED_CAMERAS, SEED_TARGETS, SEED_REQUESTS, SEED_FD = 0, 1, 2, 3, 4
+SEED_SCENE, SEED_CAMERAS, SEED_TARGETS, SEED_REQUESTS, SEED_FD, SEED_STEINER = 0, 1, 2, 3, 4, 5
 
 
 def tex_width(m_axes: int) -> int:
@@ -259,3 +259,10 @@ def pixel_sample(cam: Camera, n: int, seed: int) -> np.ndarray:
     """``n`` distinct seeded pixel indices (row-major) of a camera's image."""
     rng = np.random.default_rng(seed)
     return np.sort(rng.choice(cam.n_rays, size=min(n, cam.n_rays), replace=False))
+
+
+def steiner_draws(rounds: int, n_cand: int, seed: int = SEED_STEINER) -> np.ndarray:
+    """Standard normal draws ``[rounds, n_cand, 3]`` (float32) for the
+    Steiner-cell candidates of each round."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(size=(rounds, n_cand, 3), dtype=np.float32)
