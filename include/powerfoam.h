@@ -112,7 +112,7 @@ typedef struct {
 typedef struct {
   int64_t n;
   int64_t n_faces;           /* total directed faces in the adjacency         */
-  int64_t n_hidden;          /* cells whose bounded cell is empty             */
+  int64_t n_hidden;          /* cells never rasterised: empty bounded cell or zero density */
   int64_t n_overflow;        /* cells whose build exceeded a capacity (0)     */
   int64_t n_high_degree;     /* cells that took the high-degree build pass    */
   float box_min[3], box_max[3];
@@ -227,6 +227,46 @@ void pf_state_release(pf_fwd_state* state);
    tree traversal exceeded its stack), HIP. */
 pf_status pf_connect_loss(const pf_scene* scene, float lambda, const pf_grads* grads, double* loss,
                           void* stream);
+
+/* Steiner cells for the ray walk (supplementary material, Steiner points,
+   Alg. 1).  In empty space the unbounded power cells that the walk crosses
+   are unconstrained by rendering and can be long and thin; empty cells
+   added there shorten the walk.  Runs `rounds` rounds over the sites of
+   params (n, p, power, radius are read; device arrays):
+     1. candidates x_j = mean + std * z[round][j] per axis, with the mean and
+        population standard deviation of the current sites (the scene's and
+        those kept in earlier rounds), rounded to float32;
+     2. x_j is valid when |x_j - p_i|^2 - r_i^2 > 0 for every current site;
+     3. near = argmin_i |x_j - p_i|^2 - r_i^2 (ties: lower index, scene
+        sites first, then kept sites in the order kept);
+        r_hat = |x_j - p_near| - r_near;
+     4. x_j is kept when lo_ratio * r_near <= r_hat <= hi_ratio * r_near.
+   All candidates of a round are judged against the sites present at its
+   start; the kept ones join, in candidate order, at its end.  Outputs per
+   kept cell k (device, capacity cap; rounds * n_cand always suffices):
+   out_p [cap][3] site, out_radius [cap] float32(r_hat), out_power [cap]
+   weight float32(r_hat^2 - r_near^2 + w_near) (its bisector with the nearest
+   cell lies on that cell's sphere; r_hat^2 when w = r^2), out_near [cap]
+   index of the nearest site in the combined order (may be NULL).
+   round_counts (host, [rounds], may be NULL) receives the number kept per
+   round and *n_out (host) the total.  The caller appends the cells to the
+   scene as empty cells (occ_logit = -inf: zero density; such cells are
+   walked but never rasterised).  z: device [rounds][n_cand][3] standard
+   normal draws.  opts (host): rounds 6, lo_ratio 2, hi_ratio 6 in the
+   paper.  Synchronises the stream once per round.
+   Errors: INVALID (NULL or non-finite arguments, rounds outside 1..64,
+   n_cand < 1, lo_ratio > hi_ratio), OVERFLOW (more than cap cells kept:
+   *n_out = cap and the outputs hold the first cap), OOM, HIP. */
+typedef struct {
+  int64_t n_cand;       /* candidates per round */
+  int32_t rounds;
+  float lo_ratio, hi_ratio;
+  int32_t reserved;     /* 0 */
+} pf_steiner_opts;
+
+pf_status pf_steiner(const pf_params* params, const float* z, const pf_steiner_opts* opts, int64_t cap,
+                     float* out_p, float* out_power, float* out_radius, int32_t* out_near,
+                     int64_t* round_counts, int64_t* n_out, void* stream);
 
 /* Device memory estimate (bytes, host output) of a render of cams (what 0),
    of a render with a store-mode forward state (what 1), or of that plus the

@@ -13,7 +13,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "OOM", 3: "HIP", 4: "UNSUPPORTED", 5: 
 EXPORTS = ("pf_build_scene", "pf_scene_info_get", "pf_scene_adjacency", "pf_scene_destroy",
            "pf_render_raster", "pf_render_trace", "pf_backward", "pf_state_release", "pf_last_error",
            "pf_profile_enable", "pf_profile_read", "pf_state_info", "pf_update_scene", "pf_query_workspace",
-           "pf_connect_loss")
+           "pf_connect_loss", "pf_steiner")
 
 
 class PfParams(C.Structure):
@@ -52,6 +52,11 @@ class PfBackwardOpts(C.Structure):
     _fields_ = [("lambda_normal", C.c_float), ("contribution", C.c_void_p), ("normal_loss", C.c_void_p)]
 
 
+class PfSteinerOpts(C.Structure):
+    _fields_ = [("n_cand", C.c_int64), ("rounds", C.c_int32), ("lo_ratio", C.c_float),
+                ("hi_ratio", C.c_float), ("reserved", C.c_int32)]
+
+
 class PfGrads(C.Structure):
     _fields_ = [("p", C.c_void_p), ("power", C.c_void_p), ("radius", C.c_void_p),
                 ("normal", C.c_void_p), ("occ_logit", C.c_void_p), ("rgb", C.c_void_p),
@@ -83,6 +88,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.pf_update_scene.argtypes = [vp, C.POINTER(PfParams), vp]
     lib.pf_query_workspace.argtypes = [vp, C.POINTER(PfCamera), i32, i32, C.POINTER(i64)]
     lib.pf_connect_loss.argtypes = [vp, C.c_float, C.POINTER(PfGrads), vp, vp]
+    lib.pf_steiner.argtypes = [C.POINTER(PfParams), vp, C.POINTER(PfSteinerOpts), i64, vp, vp, vp, vp,
+                               C.POINTER(i64), C.POINTER(i64), vp]
     lib.pf_backward.argtypes = [vp, vp, vp, C.POINTER(PfGrads), C.POINTER(PfBackwardOpts), vp]
     lib.pf_state_release.argtypes = [vp]
     lib.pf_state_release.restype = None

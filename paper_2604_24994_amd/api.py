@@ -311,3 +311,59 @@ def backward(scene: Scene, state: ForwardState, d_rgba: torch.Tensor, grads: Dic
         o.normal_loss = normal_loss.data_ptr()
     L.check(L.load().pf_backward(scene.handle, state.handle, C.c_void_p(d.data_ptr()), C.byref(g), C.byref(o),
                                  C.c_void_p(_stream_ptr(stream))))
+
+
+def steiner(params, z: torch.Tensor, lo_ratio: float = 2.0, hi_ratio: float = 6.0, cap: Optional[int] = None,
+            stream=None) -> Dict[str, torch.Tensor]:
+    """pf_steiner: Steiner cells for the walk.  ``z``: standard normal draws
+    [rounds, n_cand, 3] (float32, moved to the GPU); ``params``: cell arrays
+    (only p, power and radius are read).  Returns a dict of device tensors
+    for the kept cells (p [A,3], power [A], radius [A], near [A] int32) and
+    ``round_counts`` (list of ints)."""
+    _require_cuda()
+    lib = L.load()
+    get = (lambda k: params[k]) if isinstance(params, dict) else (lambda k: getattr(params, k))
+    t = {f: torch.as_tensor(get(f)).to(device="cuda", dtype=torch.float32).contiguous()
+         for f in ("p", "power", "radius")}
+    dev = t["p"].device
+    zz = torch.as_tensor(z).to(device=dev, dtype=torch.float32).contiguous()
+    if zz.dim() != 3 or zz.shape[2] != 3:
+        raise ValueError("z must be shaped [rounds, n_cand, 3]")
+    rounds, n_cand = int(zz.shape[0]), int(zz.shape[1])
+    cap = rounds * n_cand if cap is None else int(cap)
+    out_p = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=dev)
+    out_w = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+    out_r = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+    out_near = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    pp = L.PfParams(n=int(t["p"].shape[0]), k_detail=0, m_axes=0)
+    pp.p, pp.power, pp.radius = t["p"].data_ptr(), t["power"].data_ptr(), t["radius"].data_ptr()
+    o = L.PfSteinerOpts(n_cand=n_cand, rounds=rounds, lo_ratio=float(lo_ratio), hi_ratio=float(hi_ratio))
+    counts = (C.c_int64 * rounds)()
+    n_out = C.c_int64(0)
+    L.check(lib.pf_steiner(C.byref(pp), C.c_void_p(zz.data_ptr()), C.byref(o), cap, C.c_void_p(out_p.data_ptr()),
+                           C.c_void_p(out_w.data_ptr()), C.c_void_p(out_r.data_ptr()),
+                           C.c_void_p(out_near.data_ptr()), counts, C.byref(n_out),
+                           C.c_void_p(_stream_ptr(stream))))
+    a = int(n_out.value)
+    return {"p": out_p[:a], "power": out_w[:a], "radius": out_r[:a], "near": out_near[:a],
+            "round_counts": [int(c) for c in counts]}
+
+
+def append_empty_cells(params, cells: Dict[str, torch.Tensor]) -> Dict[str, torch.Tensor]:
+    """Scene arrays with ``cells`` (p, power, radius) appended as empty
+    cells: zero density (occ_logit -inf), unit normal +z, zero colour and
+    texture.  Such cells take part in the power diagram, so the walk crosses
+    them, but never contribute to an image."""
+    t = to_device_params(params)
+    a = int(cells["p"].shape[0])
+    dev = t["p"].device
+    extra = {
+        "p": cells["p"].to(dev, torch.float32).reshape(a, 3),
+        "power": cells["power"].to(dev, torch.float32).reshape(a),
+        "radius": cells["radius"].to(dev, torch.float32).reshape(a),
+        "normal": torch.tensor([0.0, 0.0, 1.0], device=dev).expand(a, 3),
+        "occ_logit": torch.full((a,), float("-inf"), device=dev),
+        "rgb": torch.zeros((a, 3), device=dev),
+        "tex": torch.zeros((a,) + tuple(t["tex"].shape[1:]), device=dev),
+    }
+    return {f: torch.cat([t[f], extra[f]]).contiguous() for f in PARAM_FIELDS}

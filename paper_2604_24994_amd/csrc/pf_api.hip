@@ -475,6 +475,25 @@ pf_status pf_connect_loss(const pf_scene* scene, float lambda, const pf_grads* g
   return pf::connect_loss_impl(scene->s, lambda, *grads, loss, (hipStream_t)stream);
 }
 
+pf_status pf_steiner(const pf_params* params, const float* z, const pf_steiner_opts* opts, int64_t cap,
+                     float* out_p, float* out_power, float* out_radius, int32_t* out_near, int64_t* round_counts,
+                     int64_t* n_out, void* stream) {
+  if (!params || !z || !opts || !n_out) return invalid("pf_steiner: NULL argument");
+  const pf_params& p = *params;
+  if (p.n < 1 || p.n >= (1ll << 30)) return invalid("pf_steiner: n must be in 1 .. 2^30 - 1");
+  if (!p.p || !p.power || !p.radius) return invalid("pf_steiner: p, power and radius must not be NULL");
+  const pf_steiner_opts& o = *opts;
+  if (o.rounds < 1 || o.rounds > 64) return invalid("pf_steiner: rounds must be in 1 .. 64");
+  if (o.n_cand < 1 || o.n_cand >= (1ll << 31)) return invalid("pf_steiner: n_cand must be in 1 .. 2^31 - 1");
+  if (!std::isfinite(o.lo_ratio) || !std::isfinite(o.hi_ratio) || o.lo_ratio > o.hi_ratio)
+    return invalid("pf_steiner: lo_ratio and hi_ratio must be finite, lo_ratio <= hi_ratio");
+  if (cap < 0 || p.n + cap >= (1ll << 31)) return invalid("pf_steiner: cap must be >= 0 and n + cap < 2^31");
+  if (cap > 0 && (!out_p || !out_power || !out_radius)) return invalid("pf_steiner: an output array is NULL");
+  *n_out = 0;
+  return pf::steiner_impl(p, z, o, cap, out_p, out_power, out_radius, out_near, round_counts, n_out,
+                          (hipStream_t)stream);
+}
+
 pf_status pf_query_workspace(const pf_scene* scene, const pf_camera* cams, int32_t ncam, int32_t what,
                              int64_t* bytes) {
   if (!scene || !cams || ncam < 1 || !bytes) return invalid("pf_query_workspace: NULL argument or ncam < 1");

@@ -976,15 +976,19 @@ __global__ void k_fill(const float* __restrict__ p, const float* __restrict__ w,
 
 __device__ inline float softplus_f(float x) { return x > 20.0f ? x : log1pf(expf(x)); }
 
+// Packed records; a cell of zero density (e.g. an empty Steiner cell, whose
+// logit is -inf) is never binned for the raster: it cannot contribute.
 __global__ void k_prep(const float* __restrict__ p, const float* __restrict__ r, const float* __restrict__ nrm,
                        const float* __restrict__ lam, float sigma_scale, int64_t n, float4* __restrict__ geo,
-                       float4* __restrict__ onrm) {
+                       float4* __restrict__ onrm, float* __restrict__ cull) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   geo[i] = make_float4(p[3 * i], p[3 * i + 1], p[3 * i + 2], r[i]);
   const float nx = nrm[3 * i], ny = nrm[3 * i + 1], nz = nrm[3 * i + 2];
   const float inv = 1.0f / sqrtf(nx * nx + ny * ny + nz * nz);
-  onrm[i] = make_float4(nx * inv, ny * inv, nz * inv, sigma_scale * softplus_f(lam[i]));
+  const float sigma = sigma_scale * softplus_f(lam[i]);
+  onrm[i] = make_float4(nx * inv, ny * inv, nz * inv, sigma);
+  if (!(sigma > 0.0f)) cull[i] = -1.0f;
 }
 
 // out: [hidden, overflow, over-vertices, over-planes, over-work, over-stack]
@@ -1219,6 +1223,9 @@ pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipSt
     }
   }
 
+  k_prep<<<g256, 256, 0, s>>>(prm.p, prm.radius, prm.normal, prm.occ_logit, prm.sigma_scale, n, sc->geo,
+                              sc->nrm, sc->cull);
+  PF_HIP_TRY(hipGetLastError());
   DevBuf<unsigned long long> cnt(s);
   PF_HIP_TRY(cnt.alloc(6));
   PF_HIP_TRY(hipMemsetAsync(cnt.p, 0, 6 * sizeof(unsigned long long), s));
@@ -1246,9 +1253,6 @@ pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipSt
   k_fill<<<g256, 256, 0, s>>>(prm.p, prm.power, n, faces_tmp.p, faces_big.p, bigslot.p, (const uint32_t*)sc->row,
                               counts.p, bmin, bmax,
                               sc->col, sc->plane);
-  PF_HIP_TRY(hipGetLastError());
-  k_prep<<<g256, 256, 0, s>>>(prm.p, prm.radius, prm.normal, prm.occ_logit, prm.sigma_scale, n, sc->geo,
-                              sc->nrm);
   PF_HIP_TRY(hipGetLastError());
   PF_HIP_TRY(hipStreamSynchronize(s));
   return PF_OK;

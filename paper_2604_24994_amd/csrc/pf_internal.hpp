@@ -111,6 +111,11 @@ void free_scene(Scene* sc);
 // its gradient (adds into g.p and g.radius; the value into *loss_dev).
 pf_status connect_loss_impl(const Scene& sc, float lambda, const pf_grads& g, double* loss_dev, hipStream_t s);
 
+// --- Steiner cells (pf_steiner.hip) --------------------------------------
+pf_status steiner_impl(const pf_params& prm, const float* z, const pf_steiner_opts& opt, int64_t cap, float* out_p,
+                       float* out_power, float* out_radius, int32_t* out_near, int64_t* round_counts,
+                       int64_t* n_out, hipStream_t s);
+
 // --- kernel timing (pf_api.hip) ----------------------------------------
 bool profiling();
 // Records an event pair around a launch; call prof_begin before and

@@ -1,0 +1,450 @@
+// Steiner cells for the ray walk (supplementary material, section on Steiner
+// points, Alg. 1).
+//
+// Per round: the per-axis mean and standard deviation of the current sites
+// (scene cells and the Steiner cells kept so far) turn the caller's standard
+// normal draws into candidate points; a candidate outside every sphere takes
+// the radius `|x - p_near| - r_near` to the sphere of its least-power cell
+// (power `|x - p|^2 - r^2`) and is kept when that radius lies within
+// [lo r_near, hi r_near].  Kept candidates join the site set at the end of
+// the round, in candidate order.  The new cell's power weight
+// `r_hat^2 - r_near^2 + w_near` puts its bisector with the nearest cell on
+// that cell's sphere (`r_hat^2` when w = r^2).
+//
+// Layout: the sites of a round are Morton-sorted into an implicit 64-ary tree
+// (per node: box and largest radius); one wave per candidate walks it depth
+// first, children in increasing order of their power lower bound
+// `dist(x, box)^2 - r_max^2`, 64 children or sites per step.  Powers and
+// radii are formed in float64 from the float32 values without contraction,
+// so every decision is the one the float64 definition takes.
+#include "pf_internal.hpp"
+
+#include <climits>
+#include <vector>
+
+namespace pf {
+
+namespace {
+
+constexpr int ST_THREADS = 256;
+constexpr int ST_BLOCKS = 512;            // fixed, so the statistics' summation order is fixed
+constexpr int ST_STACK = 64 * MAXLVL;     // depth-first stack bound: 64 entries per level
+
+template <typename T>
+struct Tmp {
+  T* p = nullptr;
+  hipStream_t s;
+  explicit Tmp(hipStream_t st) : s(st) {}
+  ~Tmp() { if (p) (void)hipFreeAsync(p, s); }
+  hipError_t alloc(size_t count) { return hipMallocAsync((void**)&p, sizeof(T) * (count ? count : 1), s); }
+};
+
+__device__ inline uint32_t spread10_s(uint32_t v) {
+  v &= 0x3FF;
+  v = (v | (v << 16)) & 0x030000FF;
+  v = (v | (v << 8)) & 0x0300F00F;
+  v = (v | (v << 4)) & 0x030C30C3;
+  v = (v | (v << 2)) & 0x09249249;
+  return v;
+}
+
+// Block sums (float64) of x, y, z and box (float) over the m sites, for
+// stat = {mean[3], std[3], box_lo[3], box_hi[3]}.  pass 0: sums of
+// coordinates and the box; pass 1: sums of squared deviations from the mean.
+__global__ void __launch_bounds__(ST_THREADS) k_st_partial(const float* __restrict__ up, int64_t m, int pass,
+                                                           const double* __restrict__ stat,
+                                                           double* __restrict__ part) {
+#pragma clang fp contract(off)
+  double s[3] = {0.0, 0.0, 0.0};
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  double mu[3] = {0.0, 0.0, 0.0};
+  if (pass == 1)
+    for (int a = 0; a < 3; ++a) mu[a] = stat[a];
+  for (int64_t i = (int64_t)blockIdx.x * ST_THREADS + threadIdx.x; i < m; i += (int64_t)ST_BLOCKS * ST_THREADS) {
+    for (int a = 0; a < 3; ++a) {
+      const float v = up[3 * i + a];
+      if (pass == 0) {
+        s[a] += (double)v;
+        lo[a] = fminf(lo[a], v);
+        hi[a] = fmaxf(hi[a], v);
+      } else {
+        const double d = (double)v - mu[a];
+        s[a] += d * d;
+      }
+    }
+  }
+  __shared__ double red[9][ST_THREADS];
+  for (int a = 0; a < 3; ++a) {
+    red[a][threadIdx.x] = s[a];
+    red[3 + a][threadIdx.x] = lo[a];
+    red[6 + a][threadIdx.x] = hi[a];
+  }
+  __syncthreads();
+  for (int w = ST_THREADS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int a = 0; a < 3; ++a) {
+        red[a][threadIdx.x] += red[a][threadIdx.x + w];
+        red[3 + a][threadIdx.x] = fmin(red[3 + a][threadIdx.x], red[3 + a][threadIdx.x + w]);
+        red[6 + a][threadIdx.x] = fmax(red[6 + a][threadIdx.x], red[6 + a][threadIdx.x + w]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 9) part[blockIdx.x * 9 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(ST_THREADS) k_st_final(const double* __restrict__ part, int64_t m, int pass,
+                                                         double* __restrict__ stat) {
+#pragma clang fp contract(off)
+  __shared__ double red[9][ST_BLOCKS];
+  for (int b = threadIdx.x; b < ST_BLOCKS; b += ST_THREADS)
+    for (int q = 0; q < 9; ++q) red[q][b] = part[b * 9 + q];
+  __syncthreads();
+  for (int w = ST_BLOCKS / 2; w > 0; w >>= 1) {
+    for (int b = threadIdx.x; b < w; b += ST_THREADS)
+      for (int a = 0; a < 3; ++a) {
+        red[a][b] += red[a][b + w];
+        red[3 + a][b] = fmin(red[3 + a][b], red[3 + a][b + w]);
+        red[6 + a][b] = fmax(red[6 + a][b], red[6 + a][b + w]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) {
+    const int a = threadIdx.x;
+    if (pass == 0) {
+      stat[a] = red[a][0] / (double)m;
+      stat[6 + a] = red[3 + a][0];
+      stat[9 + a] = red[6 + a][0];
+    } else {
+      stat[3 + a] = sqrt(red[a][0] / (double)m);
+    }
+  }
+}
+
+__global__ void k_st_morton(const float* __restrict__ up, int64_t m, const double* __restrict__ stat,
+                            uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  uint32_t q[3];
+  for (int a = 0; a < 3; ++a) {
+    const double lo = stat[6 + a], ext = stat[9 + a] - lo;
+    const double t = ext > 0.0 ? ((double)up[3 * i + a] - lo) * (1024.0 / ext) : 0.0;
+    q[a] = (uint32_t)fmin(fmax(t, 0.0), 1023.0);
+  }
+  keys[i] = spread10_s(q[0]) | (spread10_s(q[1]) << 1) | (spread10_s(q[2]) << 2);
+  vals[i] = (uint32_t)i;
+}
+
+__global__ void k_st_gather(const float* __restrict__ up, const float* __restrict__ ur,
+                            const uint32_t* __restrict__ order, int64_t m, float4* __restrict__ sp,
+                            int32_t* __restrict__ sidx) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const uint32_t i = order[k];
+  sp[k] = make_float4(up[3 * i], up[3 * i + 1], up[3 * i + 2], ur[i]);
+  sidx[k] = (int32_t)i;
+}
+
+// One wave per parent node: box and largest radius of up to 64 children.
+__global__ void __launch_bounds__(64) k_st_level(const float4* __restrict__ sp, const float4* __restrict__ clo,
+                                                 const float4* __restrict__ chi, int64_t nchild,
+                                                 float4* __restrict__ olo, float4* __restrict__ ohi) {
+  const int64_t c = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, rmax = 0.0f;
+  if (c < nchild) {
+    if (sp) {
+      const float4 s = sp[c];
+      lo[0] = hi[0] = s.x;
+      lo[1] = hi[1] = s.y;
+      lo[2] = hi[2] = s.z;
+      rmax = s.w;
+    } else {
+      const float4 a = clo[c], b = chi[c];
+      lo[0] = a.x; lo[1] = a.y; lo[2] = a.z;
+      hi[0] = b.x; hi[1] = b.y; hi[2] = b.z;
+      rmax = b.w;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fminf(lo[a], __shfl_xor(lo[a], o, 64));
+      hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o, 64));
+    }
+    rmax = fmaxf(rmax, __shfl_xor(rmax, o, 64));
+  }
+  if (threadIdx.x == 0) {
+    olo[blockIdx.x] = make_float4(lo[0], lo[1], lo[2], 0.0f);
+    ohi[blockIdx.x] = make_float4(hi[0], hi[1], hi[2], rmax);
+  }
+}
+
+__device__ inline double slack(double best) { return 1e-9 * (1.0 + fabs(best)); }
+
+// One wave per candidate: least power over the sites, then the test.
+__global__ void __launch_bounds__(64) k_st_judge(const float* __restrict__ z, int64_t n_cand,
+                                                 const double* __restrict__ stat, const float4* __restrict__ sp,
+                                                 const int32_t* __restrict__ sidx, int64_t m,
+                                                 const float4* __restrict__ nlo, const float4* __restrict__ nhi,
+                                                 Levels lv, const float* __restrict__ up,
+                                                 const float* __restrict__ ur, const float* __restrict__ uw,
+                                                 double lo_ratio, double hi_ratio, uint32_t* __restrict__ flag,
+                                                 float4* __restrict__ cx, float* __restrict__ cw,
+                                                 int32_t* __restrict__ cnear, unsigned int* __restrict__ overflow) {
+#pragma clang fp contract(off)
+  __shared__ int stk[ST_STACK];
+  __shared__ double skey[ST_STACK];
+  __shared__ double lbs[64];
+  const int lane = threadIdx.x;
+  const int64_t j = blockIdx.x;
+  // the candidate, rounded to the float32 site it would become
+  float xf[3];
+  for (int a = 0; a < 3; ++a) {
+    const double t = stat[3 + a] * (double)z[3 * j + a];
+    xf[a] = __double2float_rn(stat[a] + t);
+  }
+  const double x = xf[0], y = xf[1], zc = xf[2];
+  double best = INFINITY;
+  int bi = INT_MAX;
+  int top = 1;
+  if (lane == 0) {
+    stk[0] = lv.n << 24;
+    skey[0] = -INFINITY;
+  }
+  __syncthreads();
+  while (top > 0) {
+    --top;
+    const int ent = stk[top];
+    const double key = skey[top];
+    __syncthreads();
+    if (key > best + slack(best)) continue;
+    const int L = ent >> 24;
+    const long long idx = ent & 0xFFFFFF;
+    if (L == 1) {
+      const int64_t s = idx * 64 + lane;
+      double pw = INFINITY;
+      int id = INT_MAX;
+      if (s < m) {
+        const float4 q = sp[s];
+        const double dx = x - (double)q.x, dy = y - (double)q.y, dz = zc - (double)q.z;
+        const double rr = (double)q.w * (double)q.w;
+        pw = ((dx * dx + dy * dy) + dz * dz) - rr;
+        id = sidx[s];
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double p2 = __shfl_xor(pw, o, 64);
+        const int i2 = __shfl_xor(id, o, 64);
+        if (p2 < pw || (p2 == pw && i2 < id)) {
+          pw = p2;
+          id = i2;
+        }
+      }
+      if (pw < best || (pw == best && id < bi)) {
+        best = pw;
+        bi = id;
+      }
+      continue;
+    }
+    const long long c = idx * 64 + lane;
+    double lb = INFINITY;
+    bool keep = false;
+    if (c < lv.cnt[L - 1]) {
+      const float4 a = nlo[lv.off[L - 1] + c], b = nhi[lv.off[L - 1] + c];
+      const double ex = fmax(0.0, fmax((double)a.x - x, x - (double)b.x));
+      const double ey = fmax(0.0, fmax((double)a.y - y, y - (double)b.y));
+      const double ez = fmax(0.0, fmax((double)a.z - zc, zc - (double)b.z));
+      lb = ((ex * ex + ey * ey) + ez * ez) - (double)b.w * (double)b.w;
+      keep = lb <= best + slack(best);
+    }
+    lbs[lane] = lb;
+    __syncthreads();
+    const uint64_t mk = __ballot(keep);
+    const int nk = __popcll(mk);
+    if (top + nk > ST_STACK) {
+      if (lane == 0) atomicAdd(overflow, 1u);
+      break;
+    }
+    if (keep) {
+      // larger bounds deeper in the stack: the least bound is taken first
+      int rank = 0;
+      for (int k = 0; k < 64; ++k) {
+        if (!((mk >> k) & 1ull)) continue;
+        const double o = lbs[k];
+        rank += (o > lb || (o == lb && k < lane)) ? 1 : 0;
+      }
+      stk[top + rank] = ((L - 1) << 24) | (int)c;
+      skey[top + rank] = lb;
+    }
+    top += nk;
+    __syncthreads();
+  }
+  if (lane != 0) return;
+  uint32_t ok = 0;
+  float rh_f = 0.0f, wh_f = 0.0f;
+  int near = -1;
+  if (best > 0.0 && bi != INT_MAX) {
+    near = bi;
+    const double px = up[3 * (int64_t)bi], py = up[3 * (int64_t)bi + 1], pz = up[3 * (int64_t)bi + 2];
+    const double rn = ur[bi], wn = uw[bi];
+    const double dx = x - px, dy = y - py, dz = zc - pz;
+    const double d = sqrt((dx * dx + dy * dy) + dz * dz);
+    const double rh = d - rn;
+    ok = (lo_ratio * rn <= rh && rh <= hi_ratio * rn) ? 1u : 0u;
+    rh_f = __double2float_rn(rh);
+    wh_f = __double2float_rn((rh * rh - rn * rn) + wn);
+  }
+  flag[j] = ok;
+  cx[j] = make_float4(xf[0], xf[1], xf[2], rh_f);
+  cw[j] = wh_f;
+  cnear[j] = near;
+}
+
+// Kept candidates, in candidate order, to the caller's outputs (from `a`)
+// and to the site set (from `m`).
+__global__ void k_st_emit(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ pos, int64_t n_cand,
+                          const float4* __restrict__ cx, const float* __restrict__ cw,
+                          const int32_t* __restrict__ cnear, int64_t a, int64_t m, int64_t cap,
+                          float* __restrict__ out_p, float* __restrict__ out_w, float* __restrict__ out_r,
+                          int32_t* __restrict__ out_near, float* __restrict__ up, float* __restrict__ ur,
+                          float* __restrict__ uw) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_cand || !flag[j]) return;
+  const int64_t k = pos[j];
+  if (a + k >= cap) return;
+  const float4 c = cx[j];
+  const int64_t o = a + k, u = m + k;
+  out_p[3 * o] = c.x;
+  out_p[3 * o + 1] = c.y;
+  out_p[3 * o + 2] = c.z;
+  out_r[o] = c.w;
+  out_w[o] = cw[j];
+  if (out_near) out_near[o] = cnear[j];
+  up[3 * u] = c.x;
+  up[3 * u + 1] = c.y;
+  up[3 * u + 2] = c.z;
+  ur[u] = c.w;
+  uw[u] = cw[j];
+}
+
+Levels levels_for(int64_t count, long long* total_nodes) {
+  Levels lv{};
+  lv.cnt[0] = count;
+  long long tot = 0;
+  int L = 0;
+  do {
+    ++L;
+    lv.cnt[L] = (lv.cnt[L - 1] + 63) / 64;
+    lv.off[L] = tot;
+    tot += lv.cnt[L];
+  } while (lv.cnt[L] > 1 && L < MAXLVL);
+  lv.n = L;
+  *total_nodes = tot;
+  return lv;
+}
+
+}  // namespace
+
+pf_status steiner_impl(const pf_params& prm, const float* z, const pf_steiner_opts& opt, int64_t cap, float* out_p,
+                       float* out_power, float* out_radius, int32_t* out_near, int64_t* round_counts,
+                       int64_t* n_out, hipStream_t s) {
+  const int64_t n = prm.n, total = n + cap;
+  Tmp<float> up(s), ur(s), uw(s);
+  PF_HIP_TRY(up.alloc(3 * total));
+  PF_HIP_TRY(ur.alloc(total));
+  PF_HIP_TRY(uw.alloc(total));
+  PF_HIP_TRY(hipMemcpyAsync(up.p, prm.p, sizeof(float) * 3 * n, hipMemcpyDeviceToDevice, s));
+  PF_HIP_TRY(hipMemcpyAsync(ur.p, prm.radius, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+  PF_HIP_TRY(hipMemcpyAsync(uw.p, prm.power, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+  long long max_nodes = 0;
+  const Levels lv_max = levels_for(total, &max_nodes);
+  if (lv_max.cnt[lv_max.n] != 1) {
+    set_error("pf_steiner: too many sites for the search tree");
+    return PF_ERR_UNSUPPORTED;
+  }
+  Tmp<double> stat(s), part(s);
+  Tmp<uint32_t> keys(s), order(s), flag(s), pos(s), tot(s);
+  Tmp<float4> sp(s), nlo(s), nhi(s), cx(s);
+  Tmp<int32_t> sidx(s), cnear(s);
+  Tmp<float> cw(s);
+  Tmp<unsigned int> ovf(s);
+  PF_HIP_TRY(stat.alloc(12));
+  PF_HIP_TRY(part.alloc(9 * ST_BLOCKS));
+  PF_HIP_TRY(keys.alloc(total));
+  PF_HIP_TRY(order.alloc(total));
+  PF_HIP_TRY(sp.alloc(total));
+  PF_HIP_TRY(sidx.alloc(total));
+  PF_HIP_TRY(nlo.alloc(max_nodes));
+  PF_HIP_TRY(nhi.alloc(max_nodes));
+  PF_HIP_TRY(flag.alloc(opt.n_cand));
+  PF_HIP_TRY(pos.alloc(opt.n_cand));
+  PF_HIP_TRY(tot.alloc(1));
+  PF_HIP_TRY(cx.alloc(opt.n_cand));
+  PF_HIP_TRY(cw.alloc(opt.n_cand));
+  PF_HIP_TRY(cnear.alloc(opt.n_cand));
+  PF_HIP_TRY(ovf.alloc(1));
+  PF_HIP_TRY(hipMemsetAsync(ovf.p, 0, sizeof(unsigned int), s));
+
+  int64_t a = 0;
+  bool full = false;
+  for (int r = 0; r < opt.rounds; ++r) {
+    const int64_t m = n + a;
+    const unsigned gm = (unsigned)((m + 255) / 256);
+    {
+      ProfScope ps("k_st_stats", s);
+      for (int pass = 0; pass < 2; ++pass) {
+        k_st_partial<<<ST_BLOCKS, ST_THREADS, 0, s>>>(up.p, m, pass, stat.p, part.p);
+        k_st_final<<<1, ST_THREADS, 0, s>>>(part.p, m, pass, stat.p);
+      }
+    }
+    PF_HIP_TRY(hipGetLastError());
+    k_st_morton<<<gm, 256, 0, s>>>(up.p, m, stat.p, keys.p, order.p);
+    PF_HIP_TRY(hipGetLastError());
+    PF_HIP_TRY(radix_sort_u32(keys.p, order.p, m, 30, s));
+    k_st_gather<<<gm, 256, 0, s>>>(up.p, ur.p, order.p, m, sp.p, sidx.p);
+    PF_HIP_TRY(hipGetLastError());
+    long long nodes = 0;
+    const Levels lv = levels_for(m, &nodes);
+    for (int l = 1; l <= lv.n; ++l) {
+      k_st_level<<<(unsigned)lv.cnt[l], 64, 0, s>>>(l == 1 ? sp.p : nullptr, l == 1 ? nullptr : nlo.p + lv.off[l - 1],
+                                                     l == 1 ? nullptr : nhi.p + lv.off[l - 1], lv.cnt[l - 1],
+                                                     nlo.p + lv.off[l], nhi.p + lv.off[l]);
+      PF_HIP_TRY(hipGetLastError());
+    }
+    {
+      ProfScope ps("k_st_judge", s);
+      k_st_judge<<<(unsigned)opt.n_cand, 64, 0, s>>>(z + 3 * opt.n_cand * (int64_t)r, opt.n_cand, stat.p, sp.p,
+                                                     sidx.p, m, nlo.p, nhi.p, lv, up.p, ur.p, uw.p,
+                                                     (double)opt.lo_ratio, (double)opt.hi_ratio, flag.p, cx.p, cw.p,
+                                                     cnear.p, ovf.p);
+    }
+    PF_HIP_TRY(hipGetLastError());
+    PF_HIP_TRY(exclusive_scan_u32(flag.p, pos.p, opt.n_cand, tot.p, s));
+    k_st_emit<<<(unsigned)((opt.n_cand + 255) / 256), 256, 0, s>>>(flag.p, pos.p, opt.n_cand, cx.p, cw.p, cnear.p, a,
+                                                                   m, cap, out_p, out_power, out_radius, out_near,
+                                                                   up.p, ur.p, uw.p);
+    PF_HIP_TRY(hipGetLastError());
+    uint32_t kept = 0;
+    unsigned int over = 0;
+    PF_HIP_TRY(hipMemcpyAsync(&kept, tot.p, sizeof(kept), hipMemcpyDeviceToHost, s));
+    PF_HIP_TRY(hipMemcpyAsync(&over, ovf.p, sizeof(over), hipMemcpyDeviceToHost, s));
+    PF_HIP_TRY(hipStreamSynchronize(s));
+    if (over) {
+      set_error("pf_steiner: search stack exceeded");
+      return PF_ERR_OVERFLOW;
+    }
+    if (round_counts) round_counts[r] = kept;
+    if (a + (int64_t)kept > cap) {
+      a = cap;
+      full = true;
+      break;
+    }
+    a += kept;
+  }
+  *n_out = a;
+  if (full) {
+    set_error("pf_steiner: more cells kept than the output capacity " + std::to_string(cap) +
+              " (rounds * n_cand always suffices)");
+    return PF_ERR_OVERFLOW;
+  }
+  return PF_OK;
+}
+
+}  // namespace pf

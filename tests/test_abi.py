@@ -23,7 +23,8 @@ def _declared():
 def test_header_declares_boundary():
     names = _declared()
     for n in ("pf_build_scene", "pf_update_scene", "pf_render_raster", "pf_render_trace", "pf_backward",
-              "pf_query_workspace", "pf_state_release", "pf_scene_destroy", "pf_last_error"):
+              "pf_query_workspace", "pf_connect_loss", "pf_steiner", "pf_state_release", "pf_scene_destroy",
+              "pf_last_error"):
         assert n in names
 
 
@@ -41,6 +42,7 @@ def test_binding_struct_sizes_match_header_layout():
     assert ctypes.sizeof(L.PfParams) == 8 + 4 + 4 + 7 * 8 + 8
     assert ctypes.sizeof(L.PfRenderOpts) == 12
     assert ctypes.sizeof(L.PfSceneInfo) == 5 * 8 + 6 * 4
+    assert ctypes.sizeof(L.PfSteinerOpts) == 8 + 4 * 4
     lib = L.load()
     # argument errors are reported without touching a device
     h = ctypes.c_void_p()
@@ -51,3 +53,13 @@ def test_binding_struct_sizes_match_header_layout():
     b = ctypes.c_int64(0)
     st = lib.pf_query_workspace(None, None, 0, 0, ctypes.byref(b))
     assert st == L.PF_ERR_INVALID and b"pf_query_workspace" in lib.pf_last_error()
+    n_out = ctypes.c_int64(-1)
+    o = L.PfSteinerOpts(n_cand=16, rounds=0, lo_ratio=2.0, hi_ratio=6.0)
+    pp = L.PfParams(n=4)
+    st = lib.pf_steiner(ctypes.byref(pp), ctypes.c_void_p(8), ctypes.byref(o), 0, None, None, None, None, None,
+                        ctypes.byref(n_out), None)
+    assert st == L.PF_ERR_INVALID and b"pf_steiner" in lib.pf_last_error()
+    o.rounds = 6
+    st = lib.pf_steiner(ctypes.byref(pp), ctypes.c_void_p(8), ctypes.byref(o), 0, None, None, None, None, None,
+                        ctypes.byref(n_out), None)
+    assert st == L.PF_ERR_INVALID and b"NULL" in lib.pf_last_error()   # p, power, radius not given

@@ -1,0 +1,117 @@
+"""GPU parity of the Steiner cells (supplementary material, Alg. 1) against
+the FP64 oracle (pinned in test_oracle_steiner.py), and of rendering scenes
+that hold such empty cells."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+def _gpu(sc, z, **kw):
+    import paper_2604_24994_amd as pf
+    out = pf.steiner(pf.to_device_params(sc), torch.as_tensor(z), **kw)
+    torch.cuda.synchronize()
+    return {k: (v.cpu().numpy() if isinstance(v, torch.Tensor) else v) for k, v in out.items()}
+
+
+@pytest.mark.parametrize("kind,n,rounds,n_cand", [("uniform", 1024, 6, 1000), ("mixture", 8192, 6, 4096)])
+def test_steiner_matches_oracle(kind, n, rounds, n_cand):
+    _flush(f"case steiner {kind} n={n} rounds={rounds} n_cand={n_cand}")
+    sc = W.scene_uniform(n, seed=7) if kind == "uniform" else W.scene_mixture(n, seed=7)
+    z = W.steiner_draws(rounds, n_cand, seed=13)
+    ref = oracle.steiner_points(sc.p, sc.radius, sc.power, z)
+    got = _gpu(sc, z)
+    counts_ref = [int((ref["round"] == r).sum()) for r in range(rounds)]
+    _flush(f"  kept per round gpu {got['round_counts']} oracle {counts_ref}")
+    assert got["round_counts"] == counts_ref
+    assert sum(counts_ref) > 50
+    # decisions and sites are exact; radius and weight are float32 roundings of the same float64 values
+    assert np.array_equal(got["p"], ref["p"])
+    assert np.array_equal(got["near"].astype(np.int64), ref["near"])
+    assert np.array_equal(got["radius"], ref["radius"])
+    assert np.allclose(got["power"], ref["power"], rtol=1e-6, atol=0)
+
+
+def test_steiner_capacity_and_arguments():
+    import paper_2604_24994_amd as pf
+    from paper_2604_24994_amd._lib import PowerFoamError
+    _flush("case steiner capacity")
+    sc = W.scene_uniform(512, seed=2)
+    z = W.steiner_draws(2, 500, seed=3)
+    full = _gpu(sc, z)
+    total = sum(full["round_counts"])
+    assert total > 2
+    with pytest.raises(PowerFoamError, match="capacity"):
+        pf.steiner(pf.to_device_params(sc), torch.as_tensor(z), cap=total - 1)
+    with pytest.raises(PowerFoamError, match="lo_ratio"):
+        pf.steiner(pf.to_device_params(sc), torch.as_tensor(z), lo_ratio=7.0, hi_ratio=6.0)
+
+
+def test_steiner_full_size_first_round_sampled():
+    # 1,048,576 cells: the kept set of the first round equals the oracle's
+    # decisions on a sample of candidates, and every sampled kept cell is one
+    # the oracle keeps with the same radius
+    _flush("case steiner 1M cells, 1 round of 262144 candidates, 48 sampled")
+    sc = W.c3_scene()
+    z = W.steiner_draws(1, 262144, seed=5)
+    got = _gpu(sc, z)
+    P = sc.p.astype(np.float64)
+    R = sc.radius.astype(np.float64)
+    Wt = sc.power.astype(np.float64)
+    x = (P.mean(0) + P.std(0) * z[0].astype(np.float64)).astype(np.float32).astype(np.float64)
+    kept = {tuple(v) for v in got["p"].astype(np.float64)}
+    _flush(f"  kept {len(kept)} of {z.shape[1]}")
+    assert len(kept) > 100
+    rng = np.random.default_rng(0)
+    sample = rng.choice(z.shape[1], 32, replace=False)
+    keep, r_hat, _, near = oracle.judge_candidates(P, R, Wt, x[sample], chunk=4)
+    for j, kj in zip(sample, keep):
+        assert (tuple(x[j]) in kept) == bool(kj), j
+    ks = rng.choice(len(got["p"]), 16, replace=False)
+    keep2, r2, _, near2 = oracle.judge_candidates(P, R, Wt, got["p"][ks].astype(np.float64), chunk=4)
+    assert keep2.all()
+    assert np.array_equal(near2, got["near"][ks].astype(np.int64))
+    assert np.array_equal(r2.astype(np.float32), got["radius"][ks])
+
+
+def _augmented(sc, cells):
+    a = cells["p"].shape[0]
+    return W.Scene(p=np.concatenate([sc.p, cells["p"]]), power=np.concatenate([sc.power, cells["power"]]),
+                   radius=np.concatenate([sc.radius, cells["radius"]]),
+                   normal=np.concatenate([sc.normal, np.tile(np.float32([0, 0, 1]), (a, 1))]),
+                   occ_logit=np.concatenate([sc.occ_logit, np.full(a, -np.inf, np.float32)]),
+                   rgb=np.concatenate([sc.rgb, np.zeros((a, 3), np.float32)]),
+                   tex=np.concatenate([sc.tex, np.zeros((a,) + sc.tex.shape[1:], np.float32)]),
+                   sigma_scale=sc.sigma_scale, tau=sc.tau)
+
+
+def test_scene_with_steiner_cells_renders_like_oracle():
+    import paper_2604_24994_amd as pf
+    _flush("case render with steiner cells: 512 sites + oracle Steiner cells, 40x32")
+    sc = W.scene_uniform(512, seed=8)
+    z = W.steiner_draws(6, 512, seed=9)
+    ref = oracle.steiner_points(sc.p, sc.radius, sc.power, z)
+    aug = _augmented(sc, ref)
+    _flush(f"  {ref['p'].shape[0]} empty cells added")
+    cam = W.pinhole(W.random_eyes(1, 2.5, 4)[0], 40, 32, 60.0)
+    img_ref = oracle.render_walk(aug, cam)
+    # the appended cells through the binding match the numpy concatenation
+    params = pf.append_empty_cells(pf.to_device_params(sc), {k: torch.as_tensor(ref[k]) for k in ("p", "power", "radius")})
+    for f in ("p", "power", "radius", "normal", "occ_logit", "rgb", "tex"):
+        assert np.array_equal(params[f].cpu().numpy(), getattr(aug, f)), f
+    scene = pf.build_scene(params, sigma_scale=sc.sigma_scale, tau=sc.tau, box=(cam.c2w[:, 3], cam.c2w[:, 3]))
+    info = scene.info()
+    ras = pf.render_raster(scene, cam)[0].cpu().numpy().reshape(-1, 4)
+    trc = pf.render_trace(scene, cam)[0].cpu().numpy().reshape(-1, 4)
+    e1, e2 = np.abs(ras - img_ref).max(), np.abs(trc - img_ref).max()
+    _flush(f"  hidden {info['n_hidden']} of {info['n']}; raster err {e1:.2e}, trace err {e2:.2e}")
+    assert info["n_hidden"] >= ref["p"].shape[0]     # empty cells are never binned
+    assert e1 <= 1e-4 and e2 <= 1e-4
