@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--cpu-rays", type=int, default=4, help="oracle sample size for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--steiner-cand", type=int, default=-1,
+                    help="Steiner side measurement: candidates per round (-1: cells / 16, 0: skip)")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device once (reference for the HBM byte counters) and exit")
@@ -113,6 +115,46 @@ def cpu_baseline(sc, cam, n_rays: int):
     return {"value": len(pix) / dt / 1e6, "unit": "Mrays/s", "cores": torch.get_num_threads(),
             "kind": "oracle",
             "sample": f"{len(pix)} seeded central pixels of view 0 at {sc.n} cells, FP64 brute-force walk, {dt:.1f} s"}
+
+
+def _rate(fn, rays):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(2):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return round(rays / (e0.elapsed_time(e1) / 2 * 1e-3) / 1e6, 2)
+
+
+def steiner_side(pf, W, sc, params, cams, out, rays, args):
+    """Steiner cells (6 rounds) on the bench scene: insertion time, cells
+    kept, and forward rates of the scene with them as empty cells."""
+    n_cand = args.steiner_cand if args.steiner_cand > 0 else max(1, args.cells // 16)
+    z = torch.as_tensor(W.steiner_draws(6, n_cand)).cuda()
+    base = {k: v.detach() for k, v in params.items()}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cells = pf.steiner(base, z)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    aug = pf.append_empty_cells(base, cells)
+    t0 = time.perf_counter()
+    scene = pf.build_scene(aug, sigma_scale=sc.sigma_scale, tau=sc.tau)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    ref = pf.render_raster(pf.build_scene(base, sigma_scale=sc.sigma_scale, tau=sc.tau), cams)
+    img = pf.render_raster(scene, cams)
+    change = max(float((a - b).abs().max()) for a, b in zip(img, ref))
+    res = {"candidates_per_round": n_cand, "kept_per_round": cells["round_counts"],
+           "cells_added": int(cells["p"].shape[0]), "insert_ms": round(ms, 1), "build_ms": round(build_ms, 1),
+           "trace_fwd_mrays_s": _rate(lambda: pf.render_trace(scene, cams, out=out), rays),
+           "raster_fwd_mrays_s": _rate(lambda: pf.render_raster(scene, cams, out=out), rays),
+           "max_image_change": float(f"{change:.3g}")}
+    scene.destroy()
+    return res
 
 
 def main():
@@ -198,6 +240,9 @@ def main():
         torch.cuda.synchronize()
         extra[name + "_mrays_s"] = round(rays / (e0.elapsed_time(e1) / 2 * 1e-3) / 1e6, 2)
     log(f"side: {extra}")
+    if args.steiner_cand != 0:
+        extra["steiner"] = steiner_side(pf, W, sc, params, cams, out, rays, args)
+        log(f"steiner: {extra['steiner']}")
     serving = None
     if args.serve_seconds > 0:
         from paper_2604_24994_amd import serve

@@ -115,6 +115,8 @@ typedef struct {
   int64_t n_hidden;          /* cells never rasterised: empty bounded cell or zero density */
   int64_t n_overflow;        /* cells whose build exceeded a capacity (0)     */
   int64_t n_high_degree;     /* cells that took the high-degree build pass    */
+  int64_t n_dropped;         /* zero-density cells dropped for exceeding the
+                                build's face capacity (see pf_build_scene)    */
   float box_min[3], box_max[3];
 } pf_scene_info;
 
@@ -130,9 +132,14 @@ typedef struct {
    per-cell cull radii bounding the non-empty part of each bounded cell, and
    empty-cell flags.  params (host) is copied; its arrays are referenced.
    opts (host) may be NULL.  Synchronises the stream (sizes the adjacency).
+   A cell of zero density (occ_logit = -inf, e.g. a Steiner cell) whose power
+   cell exceeds the face capacity (256 planes) is dropped: the build is
+   repeated as if it were absent (it can never contribute to an image; the
+   walk does not enter it), at most three times; pf_scene_info reports the
+   count.
    Errors: INVALID (n < 1, NULL array, K/M mismatch, non-positive radius),
-   UNSUPPORTED (K or M != 8), OOM, HIP, OVERFLOW (a cell exceeded the face
-   capacity; the scene is not created). */
+   UNSUPPORTED (K or M != 8), OOM, HIP, OVERFLOW (a cell of non-zero density
+   exceeded the face capacity; the scene is not created). */
 pf_status pf_build_scene(const pf_params* params, const pf_build_opts* opts,
                          void* stream, pf_scene** out);
 

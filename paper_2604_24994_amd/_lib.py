@@ -40,7 +40,8 @@ class PfRenderOpts(C.Structure):
 
 class PfSceneInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_faces", C.c_int64), ("n_hidden", C.c_int64),
-                ("n_overflow", C.c_int64), ("n_high_degree", C.c_int64), ("box_min", C.c_float * 3),
+                ("n_overflow", C.c_int64), ("n_high_degree", C.c_int64), ("n_dropped", C.c_int64),
+                ("box_min", C.c_float * 3),
                 ("box_max", C.c_float * 3)]
 
 

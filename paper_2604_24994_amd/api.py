@@ -84,7 +84,8 @@ class Scene:
         inf = L.PfSceneInfo()
         L.check(L.load().pf_scene_info_get(self.handle, C.byref(inf)))
         return {"n": inf.n, "n_faces": inf.n_faces, "n_hidden": inf.n_hidden,
-                "n_overflow": inf.n_overflow, "n_high_degree": inf.n_high_degree, "box_min": list(inf.box_min),
+                "n_overflow": inf.n_overflow, "n_high_degree": inf.n_high_degree,
+                "n_dropped": inf.n_dropped, "box_min": list(inf.box_min),
                 "box_max": list(inf.box_max)}
 
     def adjacency(self, stream=None):

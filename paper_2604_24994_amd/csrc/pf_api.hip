@@ -177,6 +177,7 @@ pf_status pf_scene_info_get(const pf_scene* scene, pf_scene_info* info) {
   info->n_hidden = scene->s.n_hidden;
   info->n_overflow = scene->s.n_overflow;
   info->n_high_degree = scene->s.n_big;
+  info->n_dropped = scene->s.n_dropped;
   for (int a = 0; a < 3; ++a) {
     info->box_min[a] = scene->s.box_min[a];
     info->box_max[a] = scene->s.box_max[a];

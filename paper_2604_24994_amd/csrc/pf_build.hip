@@ -641,13 +641,14 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
   __syncthreads();
   update_bounds(P);
   int nplanes = 6;
-  int status = CUT;
+  // a dropped cell (weight -inf) has an empty power cell and cuts no other
+  int status = wi > -INFINITY ? CUT : EMPTY;
   int work = 0;
 
   // phase 1: the own leaf (Morton neighbours)
   const int64_t leaf = k / LEAF;
-  double dmax;
-  {
+  double dmax = 0.0;
+  if (status == CUT) {
     const int64_t j = leaf * LEAF + lane;
     const bool ok = j < n && j != k;
     double d2 = INFINITY;
@@ -1012,7 +1013,24 @@ struct DevBuf {
   explicit DevBuf(hipStream_t st) : s(st) {}
   ~DevBuf() { if (p) (void)hipFreeAsync(p, s); }
   hipError_t alloc(size_t count) { return hipMallocAsync((void**)&p, sizeof(T) * (count ? count : 1), s); }
+  void reset() {
+    if (p) (void)hipFreeAsync(p, s);
+    p = nullptr;
+  }
 };
+
+// Zero-density cells that overflowed every build pass are dropped: their
+// sorted-site weight becomes -inf, so a rebuild gives them an empty power
+// cell and lets them cut no other cell.
+__global__ void k_drop_void(const int32_t* __restrict__ flags, const int32_t* __restrict__ spos,
+                            const float* __restrict__ lam, float sigma_scale, int64_t n, float4* __restrict__ sp,
+                            unsigned int* __restrict__ ndrop) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !(flags[i] & FLAG_OVERFLOW)) return;
+  if (sigma_scale * softplus_f(lam[i]) > 0.0f) return;
+  sp[spos[i]].w = -INFINITY;
+  atomicAdd(ndrop, 1u);
+}
 
 }  // namespace
 
@@ -1168,23 +1186,14 @@ pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipSt
   PF_HIP_TRY(hipMalloc((void**)&sc->nrm, sizeof(float4) * n));
   DevBuf<int32_t> faces_tmp(s), counts(s), bigslot(s), spos(s), klist(s), faces_big(s);
   DevBuf<unsigned short> eo_big(s);
-  DevBuf<unsigned int> nbig_d(s);
+  DevBuf<unsigned int> nbig_d(s), ndrop_d(s);
   PF_HIP_TRY(faces_tmp.alloc((size_t)n * FACE_CAP));
   PF_HIP_TRY(counts.alloc(n + 1));
   PF_HIP_TRY(bigslot.alloc(n));
-  PF_HIP_TRY(hipMemsetAsync(bigslot.p, 0xFF, sizeof(int32_t) * n, s));
-  {
-    ProfScope ps_clip("k_clip", s);
-    k_clip<2, FACE_CAP, 0><<<(unsigned)n, 64, 0, s>>>(sp.p, sidx.p, n, nlo.p, nhi.p, lv, bmin, bmax, prm.radius,
-                                                         nullptr, nullptr, faces_tmp.p, nullptr, counts.p,
-                                                         sc->nrast, sc->cull, sc->flags);
-  }
-  PF_HIP_TRY(hipGetLastError());
-  // second pass (twice the capacity, edge table still in LDS) for the cells
-  // that overflowed, third pass (4x, edge table in HBM) for what is left
   PF_HIP_TRY(spos.alloc(n));
   PF_HIP_TRY(klist.alloc(n));
   PF_HIP_TRY(nbig_d.alloc(1));
+  PF_HIP_TRY(ndrop_d.alloc(1));
   k_inverse<<<g256, 256, 0, s>>>(sidx.p, n, spos.p);
   PF_HIP_TRY(hipGetLastError());
   auto list_overflow = [&](unsigned int& count) -> pf_status {
@@ -1195,12 +1204,28 @@ pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipSt
     PF_HIP_TRY(hipStreamSynchronize(s));
     return PF_OK;
   };
+  // all passes; repeated (at most 3 more times) while zero-density cells
+  // overflow and are dropped
+  sc->n_dropped = 0;
+  for (int attempt = 0;; ++attempt) {
+  PF_HIP_TRY(hipMemsetAsync(bigslot.p, 0xFF, sizeof(int32_t) * n, s));
+  {
+    ProfScope ps_clip("k_clip", s);
+    k_clip<2, FACE_CAP, 0><<<(unsigned)n, 64, 0, s>>>(sp.p, sidx.p, n, nlo.p, nhi.p, lv, bmin, bmax, prm.radius,
+                                                         nullptr, nullptr, faces_tmp.p, nullptr, counts.p,
+                                                         sc->nrast, sc->cull, sc->flags);
+  }
+  PF_HIP_TRY(hipGetLastError());
+  // second pass (twice the capacity, edge table still in LDS) for the cells
+  // that overflowed, third pass (4x, edge table in HBM) for what is left
   unsigned int nbig = 0;
   {
     const pf_status st = list_overflow(nbig);
     if (st != PF_OK) return st;
   }
   sc->n_big = nbig;
+  faces_big.reset();
+  eo_big.reset();
   if (nbig) {
     PF_HIP_TRY(faces_big.alloc((size_t)nbig * PM_BIG));
     {
@@ -1221,6 +1246,16 @@ pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipSt
                                                      sc->nrast, sc->cull, sc->flags);
       PF_HIP_TRY(hipGetLastError());
     }
+  }
+  if (attempt == 3) break;
+  unsigned int ndrop = 0;
+  PF_HIP_TRY(hipMemsetAsync(ndrop_d.p, 0, sizeof(unsigned int), s));
+  k_drop_void<<<g256, 256, 0, s>>>(sc->flags, spos.p, prm.occ_logit, prm.sigma_scale, n, sp.p, ndrop_d.p);
+  PF_HIP_TRY(hipGetLastError());
+  PF_HIP_TRY(hipMemcpyAsync(&ndrop, ndrop_d.p, sizeof(ndrop), hipMemcpyDeviceToHost, s));
+  PF_HIP_TRY(hipStreamSynchronize(s));
+  if (ndrop == 0) break;
+  sc->n_dropped += ndrop;
   }
 
   k_prep<<<g256, 256, 0, s>>>(prm.p, prm.radius, prm.normal, prm.occ_logit, prm.sigma_scale, n, sc->geo,

@@ -50,7 +50,7 @@ struct Scene {
   int32_t* nrast = nullptr;        // [n] faces that can cut the sphere
   int32_t* col = nullptr;          // [E] neighbour, or -1-f for box face f
   float4* plane = nullptr;         // [E] (m, h): (x - p_i).m <= h
-  int64_t n_faces = 0, n_hidden = 0, n_overflow = 0, n_big = 0;
+  int64_t n_faces = 0, n_hidden = 0, n_overflow = 0, n_big = 0, n_dropped = 0;
   double rec_per_pixel = 0.0;      // record-pool sizing hint for store mode (0: none yet)
   double seg_per_pixel = 0.0;      // segment-list sizing hint for store mode
   double pairs_per_cell = 0.0;     // tile pairs per (view, cell) of the last raster

@@ -41,7 +41,7 @@ def test_binding_struct_sizes_match_header_layout():
     assert ctypes.sizeof(L.PfCamera) == 4 * (3 + 12 + 6)
     assert ctypes.sizeof(L.PfParams) == 8 + 4 + 4 + 7 * 8 + 8
     assert ctypes.sizeof(L.PfRenderOpts) == 12
-    assert ctypes.sizeof(L.PfSceneInfo) == 5 * 8 + 6 * 4
+    assert ctypes.sizeof(L.PfSceneInfo) == 6 * 8 + 6 * 4
     assert ctypes.sizeof(L.PfSteinerOpts) == 8 + 4 * 4
     lib = L.load()
     # argument errors are reported without touching a device

@@ -115,3 +115,44 @@ def test_scene_with_steiner_cells_renders_like_oracle():
     _flush(f"  hidden {info['n_hidden']} of {info['n']}; raster err {e1:.2e}, trace err {e2:.2e}")
     assert info["n_hidden"] >= ref["p"].shape[0]     # empty cells are never binned
     assert e1 <= 1e-4 and e2 <= 1e-4
+
+
+def _hub_scene(n_shell=600, void=True):
+    # a cell at the origin with a large weight whose power cell is bounded by
+    # all n_shell cells on the unit sphere around it (more faces than the
+    # build's largest pass holds)
+    base = W.scene_uniform(n_shell + 1, seed=31)
+    k = np.arange(n_shell) + 0.5
+    phi = np.arccos(1 - 2 * k / n_shell)
+    th = np.pi * (1 + 5 ** 0.5) * k
+    shell = np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], 1)
+    sc = base.copy()
+    sc.p = np.concatenate([np.zeros((1, 3)), shell]).astype(np.float32)
+    sc.radius = np.concatenate([[0.7], np.full(n_shell, 0.15)]).astype(np.float32)
+    sc.power = np.concatenate([[0.5], np.full(n_shell, 0.01)]).astype(np.float32)
+    if void:
+        sc.occ_logit[0] = -np.inf
+    return sc
+
+
+def test_zero_density_hub_cell_is_dropped():
+    import paper_2604_24994_amd as pf
+    from paper_2604_24994_amd._lib import PowerFoamError
+    _flush("case dropped hub: 600 cells on a sphere around one zero-density cell of 600 faces")
+    sc = _hub_scene()
+    cam = W.pinhole(np.array([0.4, -3.0, 0.7]), 32, 24, 60.0)
+    scene = pf.build_scene(pf.to_device_params(sc), sigma_scale=sc.sigma_scale, tau=sc.tau,
+                           box=(cam.c2w[:, 3], cam.c2w[:, 3]))
+    info = scene.info()
+    _flush(f"  {info}")
+    assert info["n_dropped"] == 1 and info["n_overflow"] == 0
+    # as if the cell were absent: the oracle renders the scene without it
+    ref = oracle.render_walk(sc.subset(np.arange(1, sc.n)), cam)
+    ras = pf.render_raster(scene, cam)[0].cpu().numpy().reshape(-1, 4)
+    trc = pf.render_trace(scene, cam)[0].cpu().numpy().reshape(-1, 4)
+    e1, e2 = np.abs(ras - ref).max(), np.abs(trc - ref).max()
+    _flush(f"  raster err {e1:.2e}, trace err {e2:.2e}, mean A {ref[:, 3].mean():.3f}")
+    assert e1 <= 1e-4 and e2 <= 1e-4
+    # the same cell with a density is an error, not dropped
+    with pytest.raises(PowerFoamError, match="capacity"):
+        pf.build_scene(pf.to_device_params(_hub_scene(void=False)), sigma_scale=sc.sigma_scale, tau=sc.tau)
