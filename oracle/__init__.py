@@ -21,7 +21,9 @@ What it computes (all in float64, from the float32 inputs as given):
 * the training regularisers of the supplementary material (normal,
   sparsity, connectivity) and the per-cell contribution statistic;
 * the Steiner cells of the supplementary material (Alg. 1) that fill empty
-  space for the walk.
+  space for the walk;
+* the per-cell error statistic, moving averages, pruning and multinomial
+  densification of Sec. 3.7.
 
 Two independent forms are provided: the brute-force walk (start cell by
 argmin power distance over all sites, each exit by brute force over every
@@ -42,10 +44,12 @@ from .adjoint import adjoint_gradients, loss_from_rgba
 from .dense import dense_sample_ray
 from .regularizers import connect_loss, normal_loss_value, regularized_gradients
 from .steiner import judge_candidates, steiner_points
+from .densify import cell_error, densify_prune, draw, ema
 
 __all__ = [
     "generate_rays", "pixel_rays", "bisector", "onb", "power_distance", "shade",
     "softplus", "sphere_interval", "scene_tensors", "render_walk", "walk_records",
     "render_painter", "adjoint_gradients", "loss_from_rgba", "dense_sample_ray",
     "regularized_gradients", "normal_loss_value", "connect_loss", "judge_candidates", "steiner_points",
+    "cell_error", "densify_prune", "draw", "ema",
 ]
