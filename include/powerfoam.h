@@ -200,11 +200,17 @@ pf_status pf_render_trace(pf_scene* scene, const pf_camera* cams, int32_t ncam,
    channel of d_rgba.  Statistics (device pointers, accumulated with +=):
    contribution [n] float, per cell sum over the rays of T a (the per-cell
    sparsity term and the quantity the pruning schedule tracks, Sec. 3.7);
-   normal_loss [1] double, the value of L_normal over the rays. */
+   normal_loss [1] double, the value of L_normal over the rays;
+   error [n] float, per cell sum over the rays of T a e, given the per-pixel
+   photometric error pixel_error (device, one float per pixel in the image
+   layout without the channel axis): the per-cell error that densification
+   averages (Sec. 3.7).  Both must be given for the error statistic. */
 typedef struct {
   float lambda_normal;
   float* contribution;
   double* normal_loss;
+  const float* pixel_error;
+  float* error;
 } pf_backward_opts;
 
 /* Gradients of L with respect to all cell parameters given dL/dRGBA
@@ -274,6 +280,47 @@ typedef struct {
 pf_status pf_steiner(const pf_params* params, const float* z, const pf_steiner_opts* opts, int64_t cap,
                      float* out_p, float* out_power, float* out_radius, int32_t* out_near,
                      int64_t* round_counts, int64_t* n_out, void* stream);
+
+/* Exponential moving average for the densify/prune schedule (Sec. 3.7):
+   ema[i] = beta * ema[i] + (1 - beta) * value[i] for i < n (device arrays,
+   formed in float64, rounded to float32).  Errors: INVALID (NULL, n < 0,
+   beta outside [0, 1]), HIP. */
+pf_status pf_ema_update(float* ema, const float* value, int64_t n, float beta, void* stream);
+
+/* Densification and pruning (Sec. 3.7).  Cells whose contribution average
+   contrib_ema[i] is below prune_below are removed; the kept cells keep
+   their order.  Then n_new cells are drawn, with replacement, from the
+   multinomial distribution proportional to the kept cells' error averages
+   err_ema: draw k takes the first kept cell whose cumulative weight (float64,
+   in kept order) exceeds u[k] * total, so cells of weight 0 are never drawn;
+   the new cell is a copy of the drawn cell with its site moved to
+   p + spread * r * delta[k].  No cell is drawn when no cell is kept or the
+   total weight is 0.  Inputs (device): params arrays of n cells, err_ema
+   and contrib_ema [n], u [n_new] uniforms in [0, 1), delta [n_new][3]
+   standard normal draws.  Outputs (device, caller-allocated for n + n_new
+   cells, same layouts as pf_params): out (host struct of the output
+   arrays), out_err / out_contrib the averages of
+   the output cells (new cells take their parent's), out_parent [n_new] the
+   drawn cell's input index (may be NULL); *n_kept and *n_drawn (host) the
+   numbers of kept and new cells (the output holds n_kept + n_drawn cells:
+   the kept ones first).  Synchronises the stream.  The caller rebuilds the
+   scene from the output arrays.
+   Errors: INVALID (NULL argument, n_new < 0, non-finite prune_below or
+   spread), HIP, OOM. */
+typedef struct {
+  int64_t n_new;
+  float prune_below;
+  float spread;
+} pf_densify_opts;
+
+typedef struct {
+  float *p, *power, *radius, *normal, *occ_logit, *rgb, *tex;
+} pf_cell_arrays;
+
+pf_status pf_densify_prune(const pf_params* params, const float* err_ema, const float* contrib_ema,
+                           const float* u, const float* delta, const pf_densify_opts* opts,
+                           const pf_cell_arrays* out, float* out_err, float* out_contrib, int32_t* out_parent,
+                           int64_t* n_kept, int64_t* n_drawn, void* stream);
 
 /* Device memory estimate (bytes, host output) of a render of cams (what 0),
    of a render with a store-mode forward state (what 1), or of that plus the

@@ -4,11 +4,11 @@ The compute path is libpowerfoam.so (HIP, gfx950) behind the C ABI in
 include/powerfoam.h; this package is its Python binding.
 """
 from .api import (RECOMPUTE, STORE, ForwardState, Scene, append_empty_cells, backward, build_scene, camera_struct,
-                  connect_loss, query_workspace, steiner,
+                  connect_loss, densify_prune, ema_update, query_workspace, steiner,
                   render_raster, render_raster_state, render_trace, render_trace_state, to_device_params,
                   update_scene)
 from .autograd import render_raster_diff, render_trace_diff
 
-__all__ = ["RECOMPUTE", "STORE", "ForwardState", "Scene", "append_empty_cells", "backward", "build_scene", "camera_struct", "connect_loss",
+__all__ = ["RECOMPUTE", "STORE", "ForwardState", "Scene", "append_empty_cells", "backward", "build_scene", "camera_struct", "connect_loss", "densify_prune", "ema_update",
            "query_workspace", "render_raster", "render_raster_state", "render_raster_diff", "render_trace",
            "render_trace_state", "render_trace_diff", "steiner", "to_device_params", "update_scene"]

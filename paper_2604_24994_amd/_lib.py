@@ -13,7 +13,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "OOM", 3: "HIP", 4: "UNSUPPORTED", 5: 
 EXPORTS = ("pf_build_scene", "pf_scene_info_get", "pf_scene_adjacency", "pf_scene_destroy",
            "pf_render_raster", "pf_render_trace", "pf_backward", "pf_state_release", "pf_last_error",
            "pf_profile_enable", "pf_profile_read", "pf_state_info", "pf_update_scene", "pf_query_workspace",
-           "pf_connect_loss", "pf_steiner")
+           "pf_connect_loss", "pf_steiner", "pf_ema_update", "pf_densify_prune")
 
 
 class PfParams(C.Structure):
@@ -50,7 +50,12 @@ class PfProfileEntry(C.Structure):
 
 
 class PfBackwardOpts(C.Structure):
-    _fields_ = [("lambda_normal", C.c_float), ("contribution", C.c_void_p), ("normal_loss", C.c_void_p)]
+    _fields_ = [("lambda_normal", C.c_float), ("contribution", C.c_void_p), ("normal_loss", C.c_void_p),
+                ("pixel_error", C.c_void_p), ("error", C.c_void_p)]
+
+
+class PfDensifyOpts(C.Structure):
+    _fields_ = [("n_new", C.c_int64), ("prune_below", C.c_float), ("spread", C.c_float)]
 
 
 class PfSteinerOpts(C.Structure):
@@ -59,6 +64,12 @@ class PfSteinerOpts(C.Structure):
 
 
 class PfGrads(C.Structure):
+    _fields_ = [("p", C.c_void_p), ("power", C.c_void_p), ("radius", C.c_void_p),
+                ("normal", C.c_void_p), ("occ_logit", C.c_void_p), ("rgb", C.c_void_p),
+                ("tex", C.c_void_p)]
+
+
+class PfCellArrays(C.Structure):
     _fields_ = [("p", C.c_void_p), ("power", C.c_void_p), ("radius", C.c_void_p),
                 ("normal", C.c_void_p), ("occ_logit", C.c_void_p), ("rgb", C.c_void_p),
                 ("tex", C.c_void_p)]
@@ -91,6 +102,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.pf_connect_loss.argtypes = [vp, C.c_float, C.POINTER(PfGrads), vp, vp]
     lib.pf_steiner.argtypes = [C.POINTER(PfParams), vp, C.POINTER(PfSteinerOpts), i64, vp, vp, vp, vp,
                                C.POINTER(i64), C.POINTER(i64), vp]
+    lib.pf_ema_update.argtypes = [vp, vp, i64, C.c_float, vp]
+    lib.pf_densify_prune.argtypes = [C.POINTER(PfParams), vp, vp, vp, vp, C.POINTER(PfDensifyOpts),
+                                     C.POINTER(PfCellArrays), vp, vp, vp, C.POINTER(i64), C.POINTER(i64), vp]
     lib.pf_backward.argtypes = [vp, vp, vp, C.POINTER(PfGrads), C.POINTER(PfBackwardOpts), vp]
     lib.pf_state_release.argtypes = [vp]
     lib.pf_state_release.restype = None

@@ -285,11 +285,13 @@ def query_workspace(scene: Scene, cams, what: int = 0) -> int:
 
 def backward(scene: Scene, state: ForwardState, d_rgba: torch.Tensor, grads: Dict[str, torch.Tensor],
              stream=None, lambda_normal: float = 0.0, contribution: Optional[torch.Tensor] = None,
-             normal_loss: Optional[torch.Tensor] = None) -> None:
+             normal_loss: Optional[torch.Tensor] = None, pixel_error: Optional[torch.Tensor] = None,
+             error: Optional[torch.Tensor] = None) -> None:
     """pf_backward: adds dL/dparams into ``grads`` (dict of float32 device
     tensors shaped like the parameters; missing keys are skipped).
-    ``lambda_normal`` adds the normal loss; ``contribution`` (float32 [n])
-    and ``normal_loss`` (float64 [1]) receive the statistics (+=)."""
+    ``lambda_normal`` adds the normal loss; ``contribution`` (float32 [n]),
+    ``normal_loss`` (float64 [1]) and, given the per-pixel ``pixel_error``,
+    ``error`` (float32 [n]) receive the statistics (+=)."""
     d = d_rgba.contiguous()
     if d.dtype != torch.float32:
         raise TypeError("d_rgba must be float32")
@@ -310,6 +312,16 @@ def backward(scene: Scene, state: ForwardState, d_rgba: torch.Tensor, grads: Dic
         if not (normal_loss.dtype == torch.float64 and normal_loss.numel() >= 1):
             raise ValueError("normal_loss must be a float64 tensor")
         o.normal_loss = normal_loss.data_ptr()
+    if (pixel_error is None) != (error is None):
+        raise ValueError("pixel_error and error go together")
+    if error is not None:
+        if not (error.is_contiguous() and error.dtype == torch.float32
+                and error.numel() == scene.params["p"].shape[0]):
+            raise ValueError("error must be a contiguous float32 tensor with one entry per cell")
+        pe = pixel_error.to(dtype=torch.float32).contiguous()
+        if pe.numel() * 4 != d.numel():
+            raise ValueError("pixel_error needs one value per pixel")
+        o.pixel_error, o.error = pe.data_ptr(), error.data_ptr()
     L.check(L.load().pf_backward(scene.handle, state.handle, C.c_void_p(d.data_ptr()), C.byref(g), C.byref(o),
                                  C.c_void_p(_stream_ptr(stream))))
 
@@ -368,3 +380,53 @@ def append_empty_cells(params, cells: Dict[str, torch.Tensor]) -> Dict[str, torc
         "tex": torch.zeros((a,) + tuple(t["tex"].shape[1:]), device=dev),
     }
     return {f: torch.cat([t[f], extra[f]]).contiguous() for f in PARAM_FIELDS}
+
+
+def ema_update(ema: torch.Tensor, value: torch.Tensor, beta: float, stream=None) -> torch.Tensor:
+    """pf_ema_update: ``ema = beta ema + (1 - beta) value`` in place
+    (float32 device tensors of the same size)."""
+    if not (ema.is_contiguous() and ema.dtype == torch.float32 and value.dtype == torch.float32
+            and value.numel() == ema.numel()):
+        raise ValueError("ema and value must be float32 tensors of the same size (ema contiguous)")
+    v = value.contiguous()
+    L.check(L.load().pf_ema_update(C.c_void_p(ema.data_ptr()), C.c_void_p(v.data_ptr()), ema.numel(), float(beta),
+                                   C.c_void_p(_stream_ptr(stream))))
+    return ema
+
+
+def densify_prune(params, err_ema: torch.Tensor, contrib_ema: torch.Tensor, u: torch.Tensor, delta: torch.Tensor,
+                  prune_below: float, spread: float, stream=None):
+    """pf_densify_prune.  Returns (new cell arrays as a dict of device
+    tensors, new error average, new contribution average, parent index per
+    new cell).  ``u`` [n_new] uniforms, ``delta`` [n_new, 3] normal draws."""
+    _require_cuda()
+    t = to_device_params(params)
+    n = int(t["p"].shape[0])
+    dev = t["p"].device
+    uu = torch.as_tensor(u).to(device=dev, dtype=torch.float32).contiguous().reshape(-1)
+    dd = torch.as_tensor(delta).to(device=dev, dtype=torch.float32).contiguous().reshape(-1, 3)
+    n_new = int(uu.numel())
+    if dd.shape[0] < n_new:
+        raise ValueError("delta needs one row per draw")
+    ea = err_ema.to(device=dev, dtype=torch.float32).contiguous()
+    ca = contrib_ema.to(device=dev, dtype=torch.float32).contiguous()
+    if ea.numel() != n or ca.numel() != n:
+        raise ValueError("err_ema and contrib_ema need one entry per cell")
+    cap = n + n_new
+    out = {f: torch.empty((cap,) + tuple(t[f].shape[1:]), dtype=torch.float32, device=dev) for f in PARAM_FIELDS}
+    oe = torch.empty(cap, dtype=torch.float32, device=dev)
+    oc = torch.empty(cap, dtype=torch.float32, device=dev)
+    par = torch.empty(max(n_new, 1), dtype=torch.int32, device=dev)
+    pp = L.PfParams(n=n, k_detail=int(t["tex"].shape[1]), m_axes=(int(t["tex"].shape[2]) - 3) // 6)
+    for f in PARAM_FIELDS:
+        setattr(pp, f, t[f].data_ptr())
+    oa = L.PfCellArrays(**{f: out[f].data_ptr() for f in PARAM_FIELDS})
+    o = L.PfDensifyOpts(n_new=n_new, prune_below=float(prune_below), spread=float(spread))
+    nk, nd = C.c_int64(0), C.c_int64(0)
+    L.check(L.load().pf_densify_prune(C.byref(pp), C.c_void_p(ea.data_ptr()), C.c_void_p(ca.data_ptr()),
+                                      C.c_void_p(uu.data_ptr()), C.c_void_p(dd.data_ptr()), C.byref(o), C.byref(oa),
+                                      C.c_void_p(oe.data_ptr()), C.c_void_p(oc.data_ptr()),
+                                      C.c_void_p(par.data_ptr()), C.byref(nk), C.byref(nd),
+                                      C.c_void_p(_stream_ptr(stream))))
+    m = int(nk.value) + int(nd.value)
+    return {f: out[f][:m] for f in PARAM_FIELDS}, oe[:m], oc[:m], par[:int(nd.value)]

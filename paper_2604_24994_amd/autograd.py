@@ -35,17 +35,22 @@ class _RenderFn(torch.autograd.Function):
     def backward(ctx, g):
         scene, state, stats = ctx.scene, ctx.state, ctx.stats
         grads = {f: torch.zeros_like(scene.params[f]) for f in PARAM_FIELDS}
-        contribution = normal_loss = None
+        contribution = normal_loss = error = pixel_error = None
         if stats is not None:
             dev = scene.params["p"].device
             contribution = torch.zeros(scene.params["p"].shape[0], dtype=torch.float32, device=dev)
             normal_loss = torch.zeros(1, dtype=torch.float64, device=dev)
+            pixel_error = stats.get("pixel_error")
+            if pixel_error is not None:
+                error = torch.zeros_like(contribution)
         backward(scene, state, g.contiguous(), grads, lambda_normal=ctx.lambda_normal, contribution=contribution,
-                 normal_loss=normal_loss)
+                 normal_loss=normal_loss, pixel_error=pixel_error, error=error)
         state.release()
         if stats is not None:
             stats["contribution"] = contribution
             stats["normal_loss"] = normal_loss
+            if error is not None:
+                stats["error"] = error
         return (None,) * 7 + tuple(grads[f] for f in PARAM_FIELDS)
 
 
@@ -72,8 +77,11 @@ def render_raster_diff(scene: Scene, cams, t_min: float = 1e-6, state_mode: int 
     forward and the backward.  ``lambda_normal`` adds the normal loss of the
     rendered rays to the objective (its gradient joins the backward); a
     ``stats`` dict receives, after backward, 'contribution' (per-cell sum of
-    T a) and 'normal_loss' (the unweighted loss value).  The sparsity loss
-    summed over cells is the sum of the A channel of the images."""
+    T a) and 'normal_loss' (the unweighted loss value); if it holds a
+    'pixel_error' tensor (one value per pixel of all images, set before the
+    backward runs) it also receives 'error' (per-cell sum of T a e, the
+    statistic densification averages).  The sparsity loss summed over cells
+    is the sum of the A channel of the images."""
     return _render_diff(scene, cams, False, t_min, state_mode, lambda_normal, stats)
 
 

@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpowerfoam.so")
-SOURCES = ["pf_util.hip", "pf_build.hip", "pf_render.hip", "pf_backward.hip", "pf_steiner.hip", "pf_api.hip"]
+SOURCES = ["pf_util.hip", "pf_build.hip", "pf_render.hip", "pf_backward.hip", "pf_steiner.hip", "pf_densify.hip",
+           "pf_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -435,6 +435,8 @@ pf_status pf_backward(pf_scene* scene, pf_fwd_state* state, const float* d_rgba,
     bo.lambda_normal = opts->lambda_normal;
     bo.contribution = opts->contribution;
     bo.normal_loss = opts->normal_loss;
+    bo.pixel_error = opts->pixel_error;
+    bo.error = opts->error;
   }
   hipStream_t s = (hipStream_t)stream;
   if (state->mode == 0) {
@@ -493,6 +495,36 @@ pf_status pf_steiner(const pf_params* params, const float* z, const pf_steiner_o
   *n_out = 0;
   return pf::steiner_impl(p, z, o, cap, out_p, out_power, out_radius, out_near, round_counts, n_out,
                           (hipStream_t)stream);
+}
+
+pf_status pf_ema_update(float* ema, const float* value, int64_t n, float beta, void* stream) {
+  if (!ema || !value || n < 0) return invalid("pf_ema_update: NULL argument or n < 0");
+  if (!(beta >= 0.0f && beta <= 1.0f)) return invalid("pf_ema_update: beta must be in [0, 1]");
+  if (n == 0) return PF_OK;
+  return pf::ema_impl(ema, value, n, beta, (hipStream_t)stream);
+}
+
+pf_status pf_densify_prune(const pf_params* params, const float* err_ema, const float* contrib_ema, const float* u,
+                           const float* delta, const pf_densify_opts* opts, const pf_cell_arrays* out, float* out_err,
+                           float* out_contrib, int32_t* out_parent, int64_t* n_kept, int64_t* n_drawn,
+                           void* stream) {
+  if (!opts || !out || !err_ema || !contrib_ema || !out_err || !out_contrib || !n_kept || !n_drawn)
+    return invalid("pf_densify_prune: NULL argument");
+  {
+    const pf_status st = check_params(params, "pf_densify_prune");
+    if (st != PF_OK) return st;
+  }
+  const pf_cell_arrays& o = *out;
+  if (!o.p || !o.power || !o.radius || !o.normal || !o.occ_logit || !o.rgb || !o.tex)
+    return invalid("pf_densify_prune: an output array is NULL");
+  if (opts->n_new < 0 || params->n + opts->n_new >= (1ll << 30))
+    return invalid("pf_densify_prune: n_new must be >= 0 and n + n_new < 2^30");
+  if (opts->n_new > 0 && (!u || !delta)) return invalid("pf_densify_prune: u and delta are needed for n_new > 0");
+  if (!std::isfinite(opts->prune_below) || !std::isfinite(opts->spread))
+    return invalid("pf_densify_prune: prune_below and spread must be finite");
+  *n_kept = *n_drawn = 0;
+  return pf::densify_impl(*params, err_ema, contrib_ema, u, delta, *opts, o, out_err, out_contrib, out_parent, n_kept,
+                          n_drawn, (hipStream_t)stream);
 }
 
 pf_status pf_query_workspace(const pf_scene* scene, const pf_camera* cams, int32_t ncam, int32_t what,

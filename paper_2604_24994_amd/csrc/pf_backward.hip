@@ -44,11 +44,13 @@ constexpr int KPAD = 65;            // row pitch of the per-site LDS table (bank
 __global__ void k_suffix(const int32_t* __restrict__ head, int64_t npix, const float* __restrict__ d_rgba,
                          const int4* __restrict__ ri, float4* __restrict__ rf, float* __restrict__ rt,
                          const pf_camera* __restrict__ cams, const float4* __restrict__ nrm, float lambda_n,
-                         double* __restrict__ normal_loss) {
+                         double* __restrict__ normal_loss, const float* __restrict__ pix_err,
+                         float* __restrict__ rte) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int k = i < npix ? head[i] : -1;
   double lpix = 0.0;   // this pixel's sum of T a max(n.d, 0)^2
   if (k >= 0) {
+    const float e = pix_err ? pix_err[i] : 0.0f;
     const float gr = d_rgba[4 * i], gg = d_rgba[4 * i + 1], gb = d_rgba[4 * i + 2], ga = d_rgba[4 * i + 3];
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
     if (lambda_n != 0.0f || normal_loss) {
@@ -76,6 +78,7 @@ __global__ void k_suffix(const int32_t* __restrict__ head, int64_t npix, const f
       const float ta = T * a;
       rf[k] = make_float4(g_alpha, ta * gr, ta * gg, ta * gb);
       rt[k] = ta;   // the contribution T a (read by the per-cell pass)
+      if (rte) rte[k] = ta * e;   // its share of the pixel's error
       lpix += (double)ta * (double)nu;
       cr = a * f.y + (1.0f - a) * cr;
       cg = a * f.z + (1.0f - a) * cg;
@@ -580,6 +583,17 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
   }
 }
 
+// Per-cell error statistic: sum over a cell's records of T a e (one wave per
+// chunk of a cell's records, one atomic per chunk).
+__global__ void __launch_bounds__(64) k_cell_err(const int4* __restrict__ chunks, const int32_t* __restrict__ order,
+                                                 const float* __restrict__ rte, float* __restrict__ err) {
+  const int4 ch = chunks[blockIdx.x];
+  float v = 0.0f;
+  for (int idx = ch.y + (int)threadIdx.x; idx < ch.z; idx += 64) v += rte[order[idx]];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (threadIdx.x == 0 && v != 0.0f) atomicAdd(err + ch.x, v);
+}
+
 template <typename T>
 struct Buf {
   T* p = nullptr;
@@ -597,10 +611,16 @@ pf_status backward_impl(const Scene& sc, const BwdState& st, const float* d_rgba
   const int64_t nrec = st.nrec;
   if (nrec == 0) return PF_OK;
   const unsigned gp = (unsigned)((st.npix + 255) / 256);
+  const bool want_err = opt.error && opt.pixel_error;
+  Buf<float> rte(s);
+  // indexed like the records: slots are reserved per wave in blocks, so
+  // indices run up to the pool capacity, not to the record count
+  if (want_err) PF_HIP_TRY(rte.alloc(st.rec.cap));
   {
     ProfScope ps("k_suffix", s);
     k_suffix<<<gp, 256, 0, s>>>(st.rec.head, st.npix, d_rgba, st.rec.ri, st.rec.rf, st.rec.rt, st.cams_dev, sc.nrm,
-                                opt.lambda_normal, opt.normal_loss);
+                                opt.lambda_normal, opt.normal_loss, want_err ? opt.pixel_error : nullptr,
+                                want_err ? rte.p : nullptr);
   }
   PF_HIP_TRY(hipGetLastError());
   Buf<uint32_t> cnt(s), off(s), fill(s), nch(s), choff(s);
@@ -644,6 +664,10 @@ pf_status backward_impl(const Scene& sc, const BwdState& st, const float* d_rgba
                                                 st.rec.rt, opt.lambda_normal, opt.contribution);
   }
   PF_HIP_TRY(hipGetLastError());
+  if (want_err && nchunks) {
+    k_cell_err<<<nchunks, 64, 0, s>>>(chunks.p, order.p, rte.p, opt.error);
+    PF_HIP_TRY(hipGetLastError());
+  }
   return PF_OK;
 }
 

@@ -19,6 +19,8 @@ struct BwdOpts {
   float lambda_normal = 0.0f;
   float* contribution = nullptr;   // [n] += sum of T a per cell
   double* normal_loss = nullptr;   // [1] += sum of T a max(n.d, 0)^2
+  const float* pixel_error = nullptr;   // [pixels] per-pixel error e
+  float* error = nullptr;          // [n] += sum of T a e per cell
 };
 
 pf_status backward_impl(const Scene& sc, const BwdState& st, const float* d_rgba, const pf_grads& g,

@@ -116,6 +116,12 @@ pf_status steiner_impl(const pf_params& prm, const float* z, const pf_steiner_op
                        float* out_power, float* out_radius, int32_t* out_near, int64_t* round_counts,
                        int64_t* n_out, hipStream_t s);
 
+// --- densify / prune (pf_densify.hip) ------------------------------------
+pf_status ema_impl(float* ema, const float* value, int64_t n, float beta, hipStream_t s);
+pf_status densify_impl(const pf_params& in, const float* err_ema, const float* contrib_ema, const float* u,
+                       const float* delta, const pf_densify_opts& o, const pf_cell_arrays& out, float* out_err,
+                       float* out_contrib, int32_t* out_parent, int64_t* n_kept, int64_t* n_drawn, hipStream_t s);
+
 // --- kernel timing (pf_api.hip) ----------------------------------------
 bool profiling();
 // Records an event pair around a launch; call prof_begin before and

@@ -23,8 +23,8 @@ def _declared():
 def test_header_declares_boundary():
     names = _declared()
     for n in ("pf_build_scene", "pf_update_scene", "pf_render_raster", "pf_render_trace", "pf_backward",
-              "pf_query_workspace", "pf_connect_loss", "pf_steiner", "pf_state_release", "pf_scene_destroy",
-              "pf_last_error"):
+              "pf_query_workspace", "pf_connect_loss", "pf_steiner", "pf_ema_update", "pf_densify_prune",
+              "pf_state_release", "pf_scene_destroy", "pf_last_error"):
         assert n in names
 
 
@@ -43,6 +43,9 @@ def test_binding_struct_sizes_match_header_layout():
     assert ctypes.sizeof(L.PfRenderOpts) == 12
     assert ctypes.sizeof(L.PfSceneInfo) == 6 * 8 + 6 * 4
     assert ctypes.sizeof(L.PfSteinerOpts) == 8 + 4 * 4
+    assert ctypes.sizeof(L.PfBackwardOpts) == 8 * 5
+    assert ctypes.sizeof(L.PfDensifyOpts) == 16
+    assert ctypes.sizeof(L.PfCellArrays) == 7 * 8
     lib = L.load()
     # argument errors are reported without touching a device
     h = ctypes.c_void_p()
@@ -63,3 +66,11 @@ def test_binding_struct_sizes_match_header_layout():
     st = lib.pf_steiner(ctypes.byref(pp), ctypes.c_void_p(8), ctypes.byref(o), 0, None, None, None, None, None,
                         ctypes.byref(n_out), None)
     assert st == L.PF_ERR_INVALID and b"NULL" in lib.pf_last_error()   # p, power, radius not given
+    st = lib.pf_ema_update(None, None, 4, ctypes.c_float(0.9), None)
+    assert st == L.PF_ERR_INVALID and b"pf_ema_update" in lib.pf_last_error()
+    st = lib.pf_ema_update(ctypes.c_void_p(8), ctypes.c_void_p(8), 4, ctypes.c_float(1.5), None)
+    assert st == L.PF_ERR_INVALID and b"beta" in lib.pf_last_error()
+    nk, nd = ctypes.c_int64(-1), ctypes.c_int64(-1)
+    st = lib.pf_densify_prune(None, None, None, None, None, None, None, None, None, None, ctypes.byref(nk),
+                              ctypes.byref(nd), None)
+    assert st == L.PF_ERR_INVALID and b"pf_densify_prune" in lib.pf_last_error()
