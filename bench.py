@@ -87,6 +87,7 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--cpu-rays", type=int, default=4, help="oracle sample size for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-densify", action="store_true", help="skip the densify/prune side measurement")
     ap.add_argument("--steiner-cand", type=int, default=-1,
                     help="Steiner side measurement: candidates per round (-1: cells / 16, 0: skip)")
     ap.add_argument("--verbose", action="store_true")
@@ -153,6 +154,36 @@ def steiner_side(pf, W, sc, params, cams, out, rays, args):
            "trace_fwd_mrays_s": _rate(lambda: pf.render_trace(scene, cams, out=out), rays),
            "raster_fwd_mrays_s": _rate(lambda: pf.render_raster(scene, cams, out=out), rays),
            "max_image_change": float(f"{change:.3g}")}
+    scene.destroy()
+    return res
+
+
+def densify_side(pf, sc, params, args):
+    """One densify-and-prune update on the bench scene (moving averages of
+    seeded per-cell statistics, prune the lowest 5% by contribution, draw 1%
+    new cells) followed by the rebuild of the new cell set."""
+    n = args.cells
+    g = torch.Generator(device="cuda").manual_seed(7)
+    stat = torch.rand(n, device="cuda", generator=g)
+    ema_e = torch.zeros(n, device="cuda")
+    ema_c = torch.zeros(n, device="cuda")
+    n_new = max(1, n // 100)
+    u = torch.rand(n_new, device="cuda", generator=g)
+    delta = torch.randn(n_new, 3, device="cuda", generator=g)
+    base = {k: v.detach() for k, v in params.items()}
+    below = float(torch.quantile(stat[:65536], 0.05)) * 0.1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pf.ema_update(ema_e, stat, 0.9)
+    pf.ema_update(ema_c, stat, 0.9)
+    out, _, _, par = pf.densify_prune(base, ema_e, ema_c, u, delta, below, 0.5)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    scene = pf.build_scene(out, sigma_scale=sc.sigma_scale, tau=sc.tau)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    res = {"cells_in": n, "cells_out": int(out["p"].shape[0]), "drawn": int(par.numel()),
+           "update_ms": round((t1 - t0) * 1e3, 2), "rebuild_ms": round((t2 - t1) * 1e3, 2)}
     scene.destroy()
     return res
 
@@ -240,6 +271,9 @@ def main():
         torch.cuda.synchronize()
         extra[name + "_mrays_s"] = round(rays / (e0.elapsed_time(e1) / 2 * 1e-3) / 1e6, 2)
     log(f"side: {extra}")
+    if not args.no_densify:
+        extra["densify"] = densify_side(pf, sc, params, args)
+        log(f"densify: {extra['densify']}")
     if args.steiner_cand != 0:
         extra["steiner"] = steiner_side(pf, W, sc, params, cams, out, rays, args)
         log(f"steiner: {extra['steiner']}")

@@ -245,9 +245,14 @@ pf_status new_state(pf_scene* scene, const pf_camera* cams, int32_t ncam, int ki
   fs->mode = mode;
   fs->t_min = t_min;
   fs->max_steps = max_steps;
-  int64_t npix = 0;
-  for (int c = 0; c < ncam; ++c) npix += (int64_t)cams[c].width * cams[c].height;
+  int64_t npix = 0, ntiles = 0;
+  for (int c = 0; c < ncam; ++c) {
+    npix += (int64_t)cams[c].width * cams[c].height;
+    ntiles += (int64_t)((cams[c].width + pf::TILE - 1) / pf::TILE) * ((cams[c].height + pf::TILE - 1) / pf::TILE);
+  }
   fs->st.npix = npix;
+  fs->st.ncam = ncam;
+  fs->st.ntiles = ntiles;
   hipError_t e = hipMalloc((void**)&fs->st.cams_dev, sizeof(pf_camera) * ncam);
   if (e == hipSuccess) e = hipMemcpyAsync(fs->st.cams_dev, cams, sizeof(pf_camera) * ncam, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) {

@@ -41,13 +41,30 @@ constexpr int NSUM = NCELL + 3 * KD;  // + detail-site s(2), d per site
 constexpr int ISTAT = NSUM;           // + the cell's contribution sum (statistic)
 constexpr int KPAD = 65;            // row pitch of the per-site LDS table (bank spread)
 
-__global__ void k_suffix(const int32_t* __restrict__ head, int64_t npix, const float* __restrict__ d_rgba,
-                         const int4* __restrict__ ri, float4* __restrict__ rf, float* __restrict__ rt,
-                         const pf_camera* __restrict__ cams, const float4* __restrict__ nrm, float lambda_n,
-                         double* __restrict__ normal_loss, const float* __restrict__ pix_err,
-                         float* __restrict__ rte) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int k = i < npix ? head[i] : -1;
+// One workgroup per 16x16 tile of a view, one wave per 8x8 quadrant, lanes
+// row-major in the quadrant: the pixel layout of the store-mode raster, so
+// that the lanes of a wave walk records its raster wave appended side by side.
+__global__ void __launch_bounds__(256) k_suffix(const int32_t* __restrict__ head, int ncam,
+                                                const float* __restrict__ d_rgba, const int4* __restrict__ ri,
+                                                float4* __restrict__ rf, float* __restrict__ rt,
+                                                const pf_camera* __restrict__ cams, const float4* __restrict__ nrm,
+                                                float lambda_n, double* __restrict__ normal_loss,
+                                                const float* __restrict__ pix_err, float* __restrict__ rte) {
+  int64_t tile = blockIdx.x, base = 0;
+  int v = 0;
+  for (; v < ncam - 1; ++v) {
+    const int nt = ((cams[v].width + TILE - 1) / TILE) * ((cams[v].height + TILE - 1) / TILE);
+    if (tile < nt) break;
+    tile -= nt;
+    base += (int64_t)cams[v].width * cams[v].height;
+  }
+  const int W = cams[v].width, H = cams[v].height, tiles_x = (W + TILE - 1) / TILE;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int px = (int)(tile % tiles_x) * TILE + (w & 1) * 8 + (lane & 7);
+  const int py = (int)(tile / tiles_x) * TILE + (w >> 1) * 8 + (lane >> 3);
+  const bool inside = px < W && py < H;
+  const int64_t i = base + (int64_t)py * W + px;
+  int k = inside ? head[i] : -1;
   double lpix = 0.0;   // this pixel's sum of T a max(n.d, 0)^2
   if (k >= 0) {
     const float e = pix_err ? pix_err[i] : 0.0f;
@@ -610,7 +627,7 @@ pf_status backward_impl(const Scene& sc, const BwdState& st, const float* d_rgba
   const int64_t n = sc.n;
   const int64_t nrec = st.nrec;
   if (nrec == 0) return PF_OK;
-  const unsigned gp = (unsigned)((st.npix + 255) / 256);
+  const unsigned gp = (unsigned)st.ntiles;
   const bool want_err = opt.error && opt.pixel_error;
   Buf<float> rte(s);
   // indexed like the records: slots are reserved per wave in blocks, so
@@ -618,7 +635,7 @@ pf_status backward_impl(const Scene& sc, const BwdState& st, const float* d_rgba
   if (want_err) PF_HIP_TRY(rte.alloc(st.rec.cap));
   {
     ProfScope ps("k_suffix", s);
-    k_suffix<<<gp, 256, 0, s>>>(st.rec.head, st.npix, d_rgba, st.rec.ri, st.rec.rf, st.rec.rt, st.cams_dev, sc.nrm,
+    k_suffix<<<gp, 256, 0, s>>>(st.rec.head, st.ncam, d_rgba, st.rec.ri, st.rec.rf, st.rec.rt, st.cams_dev, sc.nrm,
                                 opt.lambda_normal, opt.normal_loss, want_err ? opt.pixel_error : nullptr,
                                 want_err ? rte.p : nullptr);
   }

@@ -10,6 +10,8 @@ struct BwdState {
   int64_t nrec = 0;           // records written
   int64_t nseg = 0;           // segments written
   int64_t npix = 0;           // pixels of all views
+  int32_t ncam = 0;           // views
+  int64_t ntiles = 0;         // 16x16 tiles of all views
   pf_camera* cams_dev = nullptr;
 };
 
