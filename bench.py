@@ -201,7 +201,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU layout is described in DESIGN.md)", file=sys.stderr)
+              "(one process drives one GPU; the multi-GPU layout is not built)", file=sys.stderr)
         sys.exit(2)
     import workloads as W
     import paper_2604_24994_amd as pf

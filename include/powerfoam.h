@@ -254,7 +254,7 @@ pf_status pf_connect_loss(const pf_scene* scene, float lambda, const pf_grads* g
         sites first, then kept sites in the order kept);
         r_hat = |x_j - p_near| - r_near;
      4. x_j is kept when lo_ratio * r_near <= r_hat <= hi_ratio * r_near.
-   All candidates of a round are judged against the sites present at its
+   All candidates of a round are tested against the sites present at its
    start; the kept ones join, in candidate order, at its end.  Outputs per
    kept cell k (device, capacity cap; rounds * n_cand always suffices):
    out_p [cap][3] site, out_radius [cap] float32(r_hat), out_power [cap]

@@ -43,13 +43,13 @@ from .painter import render_painter
 from .adjoint import adjoint_gradients, loss_from_rgba
 from .dense import dense_sample_ray
 from .regularizers import connect_loss, normal_loss_value, regularized_gradients
-from .steiner import judge_candidates, steiner_points
+from .steiner import evaluate_candidates, steiner_points
 from .densify import cell_error, densify_prune, draw, ema
 
 __all__ = [
     "generate_rays", "pixel_rays", "bisector", "onb", "power_distance", "shade",
     "softplus", "sphere_interval", "scene_tensors", "render_walk", "walk_records",
     "render_painter", "adjoint_gradients", "loss_from_rgba", "dense_sample_ray",
-    "regularized_gradients", "normal_loss_value", "connect_loss", "judge_candidates", "steiner_points",
+    "regularized_gradients", "normal_loss_value", "connect_loss", "evaluate_candidates", "steiner_points",
     "cell_error", "densify_prune", "draw", "ema",
 ]

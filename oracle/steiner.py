@@ -22,9 +22,9 @@ Readings (the paper is silent on them):
   and the candidate is ``mean + std * z`` per axis (population standard
   deviation), rounded to float32 because it becomes a float32 site; every
   test is made on that float32 point in float64 arithmetic;
-* within a round every candidate is judged against the cells present when
+* within a round every candidate is tested against the cells present when
   the round starts, and the kept candidates join together at the end of the
-  round (the printed loop adds each one as it is kept; judging candidates of
+  round (the printed loop adds each one as it is kept; testing candidates of
   one random sample against each other would make the result depend on the
   sample's order, and the round-at-a-time reading keeps the rounds
   data-parallel);
@@ -46,7 +46,7 @@ import numpy as np
 F64 = np.float64
 
 
-def judge_candidates(P, R, W, x, lo: float = 2.0, hi: float = 6.0, chunk: int = 256):
+def evaluate_candidates(P, R, W, x, lo: float = 2.0, hi: float = 6.0, chunk: int = 256):
     """One pass of the test over candidate points ``x`` [S,3] (float64
     values of float32 points) against cells ``P`` [M,3], radii ``R`` [M]
     and weights ``W`` [M] (float64).  Returns (keep [S] bool, r_hat [S],
@@ -93,7 +93,7 @@ def steiner_points(p, radius, power, z, lo: float = 2.0, hi: float = 6.0):
         mean = P.mean(axis=0)
         std = P.std(axis=0)
         x = (mean[None, :] + std[None, :] * z[it]).astype(np.float32).astype(F64)
-        keep, r_hat, w_hat, near = judge_candidates(P, R, W, x, lo, hi)
+        keep, r_hat, w_hat, near = evaluate_candidates(P, R, W, x, lo, hi)
         idx = np.nonzero(keep)[0]
         np_ = x[idx]
         nr = r_hat[idx].astype(np.float32).astype(F64)

@@ -33,7 +33,9 @@ constexpr int PM_MID = 128;       // plane capacity of the second pass (edge tab
 constexpr int SPL_MID = 4;        // vertex slots per lane of the second pass
 constexpr int PM_BIG = 256;       // plane capacity of the third pass (edge table in HBM)
 constexpr int SPL_BIG = 8;        // vertex slots per lane of the third pass
-constexpr int STACK = 256;       // traversal stack (tree depth x 63 + 64 entries suffice up to ~8M sites)
+// traversal stack: the unvisited siblings along one root-to-leaf path,
+// (levels - 2) x 63 + 64 + the root's children: 190 entries at 16M sites
+constexpr int STACK = 192;
 constexpr int RING_K = 16;        // rank of the leaf mate that sets the first ring radius
 // Upper bound on candidate clips plus node visits per cell; a cell that
 // reaches it is reported as over capacity instead of running on.
@@ -203,13 +205,15 @@ template <int SPL, int PM>
 struct Shared {
   double pl[PM][4];               // planes (m.x, m.y, m.z, h), cell-local
   int nb[PM];                     // neighbour (original index) or -1-f
-  int tid[64 * SPL];              // repack staging: packed plane triple
+  union {                         // never live at the same time (one wave per block)
+    int tid[64 * SPL];            // repack staging: packed plane triple
+    float key[64];                // per-lane ordering keys
+  };
   double tpos[64 * SPL][3];
   int stack[STACK];
   unsigned char used[PM];
   unsigned short remap[PM];
   unsigned long long omask[SPL];  // removed-vertex masks of the current clip
-  float key[64];                  // per-lane ordering keys
   double cpl[64][4];              // flagged candidates in processing order: m, h
   int corig[64];
 };

@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(64) k_st_level(const float4* __restrict__ sp, 
 __device__ inline double slack(double best) { return 1e-9 * (1.0 + fabs(best)); }
 
 // One wave per candidate: least power over the sites, then the test.
-__global__ void __launch_bounds__(64) k_st_judge(const float* __restrict__ z, int64_t n_cand,
+__global__ void __launch_bounds__(64) k_st_eval(const float* __restrict__ z, int64_t n_cand,
                                                  const double* __restrict__ stat, const float4* __restrict__ sp,
                                                  const int32_t* __restrict__ sidx, int64_t m,
                                                  const float4* __restrict__ nlo, const float4* __restrict__ nhi,
@@ -409,8 +409,8 @@ pf_status steiner_impl(const pf_params& prm, const float* z, const pf_steiner_op
       PF_HIP_TRY(hipGetLastError());
     }
     {
-      ProfScope ps("k_st_judge", s);
-      k_st_judge<<<(unsigned)opt.n_cand, 64, 0, s>>>(z + 3 * opt.n_cand * (int64_t)r, opt.n_cand, stat.p, sp.p,
+      ProfScope ps("k_st_eval", s);
+      k_st_eval<<<(unsigned)opt.n_cand, 64, 0, s>>>(z + 3 * opt.n_cand * (int64_t)r, opt.n_cand, stat.p, sp.p,
                                                      sidx.p, m, nlo.p, nhi.p, lv, up.p, ur.p, uw.p,
                                                      (double)opt.lo_ratio, (double)opt.hi_ratio, flag.p, cx.p, cw.p,
                                                      cnear.p, ovf.p);

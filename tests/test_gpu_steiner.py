@@ -72,11 +72,11 @@ def test_steiner_full_size_first_round_sampled():
     assert len(kept) > 100
     rng = np.random.default_rng(0)
     sample = rng.choice(z.shape[1], 32, replace=False)
-    keep, r_hat, _, near = oracle.judge_candidates(P, R, Wt, x[sample], chunk=4)
+    keep, r_hat, _, near = oracle.evaluate_candidates(P, R, Wt, x[sample], chunk=4)
     for j, kj in zip(sample, keep):
         assert (tuple(x[j]) in kept) == bool(kj), j
     ks = rng.choice(len(got["p"]), 16, replace=False)
-    keep2, r2, _, near2 = oracle.judge_candidates(P, R, Wt, got["p"][ks].astype(np.float64), chunk=4)
+    keep2, r2, _, near2 = oracle.evaluate_candidates(P, R, Wt, got["p"][ks].astype(np.float64), chunk=4)
     assert keep2.all()
     assert np.array_equal(near2, got["near"][ks].astype(np.int64))
     assert np.array_equal(r2.astype(np.float32), got["radius"][ks])

@@ -9,21 +9,21 @@ import pytest
 
 import workloads as W
 from oracle.cell import bisector
-from oracle.steiner import judge_candidates, steiner_points
+from oracle.steiner import evaluate_candidates, steiner_points
 from oracle.walk import render_walk
 
 
-def _judge(P, R, x, Wt=None):
+def _evaluate(P, R, x, Wt=None):
     P = np.asarray(P, float)
     R = np.asarray(R, float)
     Wt = R * R if Wt is None else np.asarray(Wt, float)
-    return judge_candidates(P, R, Wt, np.asarray(x, float))
+    return evaluate_candidates(P, R, Wt, np.asarray(x, float))
 
 
 def test_single_sphere_closed_form():
     # sphere at the origin, radius 1: r_hat = |x| - 1, kept for 2 <= r_hat <= 6
     xs = [[0.5, 0, 0], [1.0, 0, 0], [2.5, 0, 0], [3.0, 0, 0], [0, 4.0, 0], [0, 0, 7.0], [7.5, 0, 0]]
-    keep, r_hat, w_hat, near = _judge([[0, 0, 0]], [1.0], xs)
+    keep, r_hat, w_hat, near = _evaluate([[0, 0, 0]], [1.0], xs)
     assert keep.tolist() == [False, False, False, True, True, True, False]
     # inside and on the sphere: not valid at all
     assert near[0] == -1 and near[1] == -1 and np.isnan(r_hat[0]) and np.isnan(r_hat[1])
@@ -37,7 +37,7 @@ def test_nearest_is_by_power_not_by_surface_distance():
     # (0.9 vs 1.0), but x has the smaller power w.r.t. A (1.5 vs 4.41)
     P = [[0, 0, 0], [1.25, 2.9, 0]]
     R = [0.25, 2.0]
-    keep, r_hat, _, near = _judge(P, R, [[1.25, 0, 0]])
+    keep, r_hat, _, near = _evaluate(P, R, [[1.25, 0, 0]])
     assert near[0] == 0 and r_hat[0] == pytest.approx(1.0, abs=1e-15)
     assert keep[0]            # 2 * 0.25 <= 1.0 <= 6 * 0.25; by B's surface it would be 0.9 < 4
 
@@ -48,7 +48,7 @@ def test_new_weight_puts_the_bisector_on_the_nearest_sphere():
     R = rng.uniform(0.05, 0.2, 30)
     Wt = (R / 1.5) ** 2                      # weights unlike r^2, as in the workloads
     x = rng.uniform(-2, 2, (400, 3))
-    keep, r_hat, w_hat, near = _judge(P, R, x, Wt)
+    keep, r_hat, w_hat, near = _evaluate(P, R, x, Wt)
     assert keep.sum() > 5
     for j in np.nonzero(keep)[0]:
         i = near[j]
@@ -93,13 +93,13 @@ def _brute(P, R, Wt, x, lo=2.0, hi=6.0):
     return res
 
 
-def test_vectorised_judge_matches_pure_python_brute_force():
+def test_vectorised_test_matches_pure_python_brute_force():
     rng = np.random.default_rng(5)
     P = rng.uniform(-1, 1, (40, 3))
     R = rng.uniform(0.05, 0.3, 40)
     Wt = R * R
     x = rng.normal(0, 1.2, (97, 3))
-    keep, r_hat, _, near = judge_candidates(P, R, Wt, x, chunk=7)
+    keep, r_hat, _, near = evaluate_candidates(P, R, Wt, x, chunk=7)
     ref = _brute(P, R, Wt, x)
     assert any(v is None for v in ref) and any(v is not None and v[2] for v in ref)
     for j, v in enumerate(ref):
