@@ -217,8 +217,19 @@ def main():
     tgt = torch.cat([torch.as_tensor(t, device="cuda").reshape(-1, 3) for t in W.targets(cams)])
     stream = torch.cuda.current_stream()
 
+    held = {"scene": None}
+    gen = torch.Generator(device="cuda").manual_seed(11)
+
     def step():
-        scene = pf.build_scene(params, sigma_scale=sc.sigma_scale, tau=sc.tau, stream=stream)
+        # the sites move a little between steps, as after an optimiser update,
+        # and the adjacency is rebuilt (seeded by the previous step's)
+        with torch.no_grad():
+            params["p"].add_(torch.randn(params["p"].shape, device="cuda", generator=gen), alpha=1e-4)
+        if held["scene"] is None:
+            held["scene"] = pf.build_scene(params, sigma_scale=sc.sigma_scale, tau=sc.tau, stream=stream)
+        else:
+            pf.update_scene(held["scene"], params, stream=stream)
+        scene = held["scene"]
         if args.mode == "fwd":
             pf.render_raster(scene, cams, stream=stream, out=out)
             return scene
@@ -230,12 +241,11 @@ def main():
         loss.backward()
         return scene
 
-    for i in range(args.warmup):
+    for i in range(max(1, args.warmup)):
         s = step()
         torch.cuda.synchronize()
         if i == 0:
             log(f"scene: {s.info()}")
-        s.destroy()
     log("warmup done")
 
     _lib.profile_enable(True)
@@ -245,7 +255,6 @@ def main():
     ev0.record(stream)
     for _ in range(args.steps):
         s = step()
-        s.destroy()
     ev1.record(stream)
     torch.cuda.synchronize()
     prof = _lib.profile_read()
@@ -312,7 +321,7 @@ def main():
         "unit": "Mrays/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": args.warmup,
+        "warmup": max(1, args.warmup),
         "ms_per_step": round(ms, 3),
         "higher_is_better": True,
         "scaling": "weak",
@@ -320,7 +329,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.cells} cells, {args.views} pinhole views {args.width}x{args.height}, "
-                               + ("build + raster fwd + L2 loss + bwd" if args.mode == "train" else "build + raster fwd"),
+                               + ("site update + adjacency rebuild + raster fwd + L2 loss + bwd" if args.mode == "train"
+                                  else "site update + adjacency rebuild + raster fwd"),
                    "cells": args.cells, "views": args.views, "width": args.width, "height": args.height},
         "kernels_ms_per_step": {k: round(v, 3) for k, v in kms.items()},
         "scene": {"hidden": box["n_hidden"], "faces": box["n_faces"]},

@@ -157,7 +157,7 @@ pf_status pf_update_scene(pf_scene* scene, const pf_params* params, void* stream
     if (st != PF_OK) return st;
   }
   pf::Scene fresh;
-  const pf_status st = pf::build_scene_impl(*params, scene->opts, (hipStream_t)stream, &fresh);
+  const pf_status st = pf::build_scene_impl(*params, scene->opts, (hipStream_t)stream, &fresh, &scene->s);
   if (st != PF_OK) {
     pf::free_scene(&fresh);
     return st;

@@ -36,6 +36,7 @@ constexpr int SPL_BIG = 8;        // vertex slots per lane of the third pass
 // traversal stack: the unvisited siblings along one root-to-leaf path,
 // (levels - 2) x 63 + 64 + the root's children: 190 entries at 16M sites
 constexpr int STACK = 192;
+constexpr int WIT = 8;           // per empty cell: sites whose planes emptied it (seeds of the next build)
 constexpr int RING_K = 16;        // rank of the leaf mate that sets the first ring radius
 // Upper bound on candidate clips plus node visits per cell; a cell that
 // reaches it is reported as over capacity instead of running on.
@@ -216,6 +217,7 @@ struct Shared {
   unsigned long long omask[SPL];  // removed-vertex masks of the current clip
   double cpl[64][4];              // flagged candidates in processing order: m, h
   int corig[64];
+  int wl[64];                     // warm start: the candidates taken from the previous adjacency
 };
 
 enum ClipResult { NOCUT = 0, CUT = 1, EMPTY = 2, OVER_V = 3, OVER_P = 4, OVER_W = 5, OVER_S = 6 };
@@ -593,7 +595,10 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
                                              const int32_t* __restrict__ klist, unsigned short* __restrict__ eo_g,
                                              int32_t* __restrict__ faces, int32_t* __restrict__ bigslot,
                                              int32_t* __restrict__ counts, int32_t* __restrict__ nrast,
-                                             float* __restrict__ cull, int32_t* __restrict__ flags) {
+                                             float* __restrict__ cull, int32_t* __restrict__ flags,
+                                             const int32_t* __restrict__ wrow, const int32_t* __restrict__ wcol,
+                                             const int32_t* __restrict__ wwit, const int32_t* __restrict__ spos,
+                                             int32_t* __restrict__ wit_out) {
   constexpr bool LISTED = MODE >= 1, EO_HBM = MODE == 2;
   using EOT = typename std::conditional<(64 * SPL > 256), unsigned short, unsigned char>::type;
   static_assert(EO_HBM ? std::is_same<EOT, unsigned short>::value : true, "HBM edge table holds 16-bit slots");
@@ -649,12 +654,31 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
   int status = wi > -INFINITY ? CUT : EMPTY;
   int work = 0;
 
-  // phase 1: the own leaf (Morton neighbours)
+  // phase 1, warm start from a previous build: a cell that had faces starts
+  // from its previous neighbours (sites that moved little keep most of
+  // them), then one unrestricted traversal certifies it; a cell that was
+  // empty starts from the sites that emptied it, which usually empty it
+  // again at once.  Otherwise (or if that fails) the own leaf (Morton
+  // neighbours) and rings.
   const int64_t leaf = k / LEAF;
+  const int wb = (MODE <= 1 && wrow) ? wrow[self] : 0;
+  const int wcnt = (MODE <= 1 && wrow) ? wrow[self + 1] - wb : 0;
+  const bool warm = wcnt > 0;
+  int nwl = 0;
   double dmax = 0.0;
-  if (status == CUT) {
+  if (MODE <= 1 && wrow && status == CUT && (warm || wwit)) {
+    nwl = warm ? min(wcnt, 64) : WIT;
+    const int v = lane < nwl ? (warm ? wcol[wb + lane] : wwit[(int64_t)self * WIT + lane]) : -1;
+    const bool ok = v >= 0 && v < n && v != self;
+    S.wl[lane] = ok ? v : -1;
+    __syncthreads();
+    const Cand c = load_cand(sp, sidx, ok ? (int64_t)spos[v] : 0, ok, px, py, pz, wi);
+    process_batch(S, eo, P, nplanes, status, c, self, work);
+    if (warm) dmax = INFINITY;
+  }
+  if (!warm && status == CUT) {
     const int64_t j = leaf * LEAF + lane;
-    const bool ok = j < n && j != k;
+    bool ok = j < n && j != k;
     double d2 = INFINITY;
     if (ok) {
       const float4 q = sp[j];
@@ -671,7 +695,8 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
     __syncthreads();
     const double dk = sel ? __shfl(d2, __ffsll((long long)sel) - 1, 64) : 0.0;
     dmax = fmax(fmin(sqrt(dk), ri), 1e-6);
-    const Cand c = load_cand(sp, sidx, j, ok, px, py, pz, wi);
+    Cand c = load_cand(sp, sidx, j, ok, px, py, pz, wi);
+    for (int q = 0; q < nwl; ++q) c.ok = c.ok && S.wl[q] != c.orig;   // seeds already taken
     process_batch(S, eo, P, nplanes, status, c, self, work);
   }
 
@@ -696,14 +721,16 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
       const int L = ent >> 24;
       const long long idx = ent & 0xFFFFFF;
       if (L == 1) {
-        if (idx == leaf) continue;
+        if (idx == leaf && !warm) continue;
         const int64_t j = idx * LEAF + lane;
-        const bool ok = j < n;
+        const bool ok = j < n && j != k;
         const Cand c0 = load_cand(sp, sidx, j, ok, px, py, pz, wi);
         const bool beyond = ok && c0.mm >= dmax * dmax;
         if (__ballot(beyond && may_cut(P, c0.mx, c0.my, c0.mz, c0.mm, c0.h)) != 0ull) skipped = true;
         Cand c = c0;
         c.ok = ok && !beyond && c0.mm >= dmin * dmin;
+        // a warm-start candidate was already taken
+        for (int q = 0; q < nwl; ++q) c.ok = c.ok && S.wl[q] != c0.orig;
         if (__ballot(c.ok) == 0ull) continue;
         if (!process_batch(S, eo, P, nplanes, status, c, self, work)) break;
         continue;
@@ -785,6 +812,11 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
     out = faces + (int64_t)bigslot[self] * PM_BIG;
   }
   if (status == EMPTY || is_over(status)) {
+    // the most recent planes (the last one emptied the cell), for the next build
+    if (wit_out && lane < WIT) {
+      const int q = nplanes - lane;
+      wit_out[(int64_t)self * WIT + lane] = (status == EMPTY && q >= 0 && q < PM) ? S.nb[q] : -1;
+    }
     if (lane == 0) {
       counts[self] = 0;
       nrast[self] = 0;
@@ -825,16 +857,31 @@ __global__ void __launch_bounds__(64) k_clip(const float4* __restrict__ sp, cons
       }
     }
   }
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  int base = 0, nr = 0;
-  for (int ccat = 0; ccat < 3; ++ccat) {
+  // faces by category, each category in increasing neighbour order (the
+  // order in which the planes were taken does not show in the output)
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const uint64_t m = __ballot(cat[r] == ccat);
-      if (cat[r] == ccat) out[base + __popcll(m & lt)] = S.nb[lane + 64 * r];
-      base += __popcll(m);
+  for (int r = 0; r < NR; ++r)
+    if (lane + 64 * r < PM) S.used[lane + 64 * r] = (unsigned char)cat[r];
+  __syncthreads();
+  int cbase[3] = {0, 0, 0};
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+    for (int ccat = 0; ccat < 3; ++ccat) cbase[ccat] += __popcll(__ballot(cat[r] == ccat));
+  const int nr = cbase[0];
+  const int base = cbase[0] + cbase[1] + cbase[2];
+  cbase[2] = cbase[0] + cbase[1];
+  cbase[1] = cbase[0];
+  cbase[0] = 0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int q = lane + 64 * r;
+    if (cat[r] < 3) {
+      const int me = S.nb[q];
+      int pos = 0;
+      for (int t = 0; t < nplanes; ++t)
+        pos += (S.used[t] == cat[r] && (S.nb[t] < me || (S.nb[t] == me && t < q))) ? 1 : 0;
+      out[cbase[cat[r]] + pos] = me;
     }
-    if (ccat == 0) nr = base;
   }
   viol = wave_max_d(viol);
   const double R = sqrt(P.r2);
@@ -1064,7 +1111,7 @@ pf_status connect_loss_impl(const Scene& sc, float lambda, const pf_grads& g, do
 
 void free_scene(Scene* sc) {
   void* ptrs[] = {sc->geo,  sc->nrm,    sc->cull,   sc->flags, sc->row,  sc->nrast, sc->col,
-                  sc->plane, sc->t_sp, sc->t_sidx, sc->t_srad, sc->t_lo, sc->t_hi};
+                  sc->plane, sc->t_sp, sc->t_sidx, sc->t_srad, sc->t_lo, sc->t_hi, sc->wit};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   sc->geo = sc->nrm = nullptr;
@@ -1074,10 +1121,17 @@ void free_scene(Scene* sc) {
   sc->t_sp = sc->t_lo = sc->t_hi = nullptr;
   sc->t_sidx = nullptr;
   sc->t_srad = nullptr;
+  sc->wit = nullptr;
 }
 
-pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipStream_t s, Scene* sc) {
+pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipStream_t s, Scene* sc,
+                           const Scene* prev) {
   const int64_t n = prm.n;
+  // warm start from a previous build of the same cells
+  const bool use_prev = prev && prev->n == n && prev->row && prev->col;
+  const int32_t* warm_row = use_prev ? prev->row : nullptr;
+  const int32_t* warm_col = use_prev ? prev->col : nullptr;
+  const int32_t* warm_wit = use_prev ? prev->wit : nullptr;
   sc->n = n;
   sc->prm = prm;
 
@@ -1184,6 +1238,8 @@ pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipSt
   // per-cell clipping
   PF_HIP_TRY(hipMalloc((void**)&sc->cull, sizeof(float) * n));
   PF_HIP_TRY(hipMalloc((void**)&sc->flags, sizeof(int32_t) * n));
+  PF_HIP_TRY(hipMalloc((void**)&sc->wit, sizeof(int32_t) * WIT * n));
+  PF_HIP_TRY(hipMemsetAsync(sc->wit, 0xFF, sizeof(int32_t) * WIT * n, s));
   PF_HIP_TRY(hipMalloc((void**)&sc->nrast, sizeof(int32_t) * n));
   PF_HIP_TRY(hipMalloc((void**)&sc->row, sizeof(int32_t) * (n + 1)));
   PF_HIP_TRY(hipMalloc((void**)&sc->geo, sizeof(float4) * n));
@@ -1217,7 +1273,8 @@ pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipSt
     ProfScope ps_clip("k_clip", s);
     k_clip<2, FACE_CAP, 0><<<(unsigned)n, 64, 0, s>>>(sp.p, sidx.p, n, nlo.p, nhi.p, lv, bmin, bmax, prm.radius,
                                                          nullptr, nullptr, faces_tmp.p, nullptr, counts.p,
-                                                         sc->nrast, sc->cull, sc->flags);
+                                                         sc->nrast, sc->cull, sc->flags, warm_row, warm_col,
+                                                         warm_wit, spos.p, sc->wit);
   }
   PF_HIP_TRY(hipGetLastError());
   // second pass (twice the capacity, edge table still in LDS) for the cells
@@ -1236,7 +1293,8 @@ pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipSt
       ProfScope ps_big("k_clip_mid", s);
       k_clip<SPL_MID, PM_MID, 1><<<nbig, 64, 0, s>>>(sp.p, sidx.p, n, nlo.p, nhi.p, lv, bmin, bmax, prm.radius,
                                                     klist.p, nullptr, faces_big.p, bigslot.p, counts.p, sc->nrast,
-                                                    sc->cull, sc->flags);
+                                                    sc->cull, sc->flags, warm_row, warm_col, warm_wit, spos.p,
+                                                    sc->wit);
     }
     PF_HIP_TRY(hipGetLastError());
     unsigned int nbig3 = 0;
@@ -1247,7 +1305,8 @@ pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipSt
       ProfScope ps_big("k_clip_big", s);
       k_clip<SPL_BIG, PM_BIG, 2><<<nbig3, 64, 0, s>>>(sp.p, sidx.p, n, nlo.p, nhi.p, lv, bmin, bmax, prm.radius,
                                                      klist.p, eo_big.p, faces_big.p, bigslot.p, counts.p,
-                                                     sc->nrast, sc->cull, sc->flags);
+                                                     sc->nrast, sc->cull, sc->flags, nullptr, nullptr, nullptr, nullptr,
+                                                     sc->wit);
       PF_HIP_TRY(hipGetLastError());
     }
   }

@@ -45,6 +45,7 @@ struct Scene {
   float* cull = nullptr;           // radius of a ball at p bounding the
                                    // non-empty bounded cell; < 0: hidden
   int32_t* flags = nullptr;
+  int32_t* wit = nullptr;          // [n][8] per empty cell: sites that emptied it (next build's seeds)
   // adjacency, CSR; per cell: raster faces, other neighbour faces, box faces
   int32_t* row = nullptr;          // [n+1]
   int32_t* nrast = nullptr;        // [n] faces that can cut the sphere
@@ -104,8 +105,10 @@ hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int bits,
                           hipStream_t s);
 
 // --- build (pf_build.hip) -------------------------------------------------
+// prev (may be null): a built scene of the same cells whose adjacency seeds
+// each cell's first candidates (the result does not depend on it).
 pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt,
-                           hipStream_t s, Scene* sc);
+                           hipStream_t s, Scene* sc, const Scene* prev = nullptr);
 void free_scene(Scene* sc);
 // lambda * sum_i sum_{j overlapping i} max(r_i + r_j - |p_i - p_j|, 0)^2 and
 // its gradient (adds into g.p and g.radius; the value into *loss_dev).

@@ -86,12 +86,16 @@ def test_recompute_mode_equals_store_mode(walk):
         assert r <= 1e-6, f
 
 
-def test_update_scene_equals_fresh_build():
+@pytest.mark.parametrize("kind,n,move", [("uniform", 2000, 1e-2), ("mixture", 40000, 1e-3), ("mixture", 40000, 1e-1)])
+def test_update_scene_equals_fresh_build(kind, n, move):
+    # the update is seeded by the previous adjacency (faces of non-empty
+    # cells, the sites that emptied empty ones); the result must not depend
+    # on it
     import paper_2604_24994_amd as pf
-    _flush("case update_scene: 2,000 sites moved by 1e-2")
-    sc = W.scene_uniform(2000, seed=3)
+    _flush(f"case update_scene: {n} {kind} sites moved by {move}")
+    sc = W.scene_uniform(n, seed=3) if kind == "uniform" else W.scene_mixture(n, seed=3)
     rng = np.random.default_rng(3)
-    p1 = (sc.p + rng.normal(scale=1e-2, size=sc.p.shape)).astype(np.float32)
+    p1 = (sc.p + rng.normal(scale=move, size=sc.p.shape)).astype(np.float32)
     scene = pf.build_scene(pf.to_device_params(sc), sigma_scale=sc.sigma_scale, tau=sc.tau)
     moved = pf.to_device_params(sc)
     moved["p"] = torch.tensor(p1, device="cuda")
