@@ -109,7 +109,8 @@ hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int bits,
 // each cell's first candidates (the result does not depend on it).
 pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt,
                            hipStream_t s, Scene* sc, const Scene* prev = nullptr);
-void free_scene(Scene* sc);
+// Frees the scene's arrays: stream-ordered on s, or synchronously (s null).
+void free_scene(Scene* sc, hipStream_t s = nullptr);
 // lambda * sum_i sum_{j overlapping i} max(r_i + r_j - |p_i - p_j|, 0)^2 and
 // its gradient (adds into g.p and g.radius; the value into *loss_dev).
 pf_status connect_loss_impl(const Scene& sc, float lambda, const pf_grads& g, double* loss_dev, hipStream_t s);
