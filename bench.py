@@ -50,11 +50,11 @@ FLOPS_BWD_PER_CONTRIB = 5100
 # for the kernel sources with these hashes; otherwise the bench reports null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC = {
-    "k_bwd_cell": {"fetch_kib": 19504576.4, "write_kib": 12987314.6,
-                   "sources": {"pf_backward.hip": "4ab52cb1a0f0b1f6", "pf_shade.hpp": "68feb93f5734438a"}},
-    "k_raster_store": {"fetch_kib": 15588900.5, "write_kib": 10838922.3,
+    "k_bwd_cell": {"fetch_kib": 19445871.0, "write_kib": 12987895.2,
+                   "sources": {"pf_backward.hip": "ffaff656026fb30b", "pf_shade.hpp": "68feb93f5734438a"}},
+    "k_raster_store": {"fetch_kib": 15663741.2, "write_kib": 11225375.5,
                        "sources": {"pf_render.hip": "7c11b6fd407d2604", "pf_shade.hpp": "68feb93f5734438a"}},
-    "k_clip": {"fetch_kib": 235525.2, "write_kib": 158005.2, "sources": {"pf_build.hip": "f80dfac28e6708f5"}},
+    "k_clip": {"fetch_kib": 409390.7, "write_kib": 180377.3, "sources": {"pf_build.hip": "bbeca12176f39233"}},
 }
 
 
