@@ -1,0 +1,128 @@
+"""GPU edge cases against the FP64 oracle: a single cell, coincident sites,
+a camera inside a cell's sphere, a view that sees nothing (no records: the
+backward is a no-op), zero density everywhere, and a fisheye whose field of
+view masks the image corners."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+FIELDS = ("p", "power", "radius", "normal", "occ_logit", "rgb", "tex")
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+def _render_both(pf, sc, cam):
+    eye = cam.c2w[:, 3]
+    lo = np.minimum(eye, sc.p.min(0)) - 0.1
+    hi = np.maximum(eye, sc.p.max(0)) + 0.1
+    scene = pf.build_scene(sc, sigma_scale=sc.sigma_scale, tau=sc.tau, box=(lo, hi))
+    ras = pf.render_raster(scene, cam)[0].cpu().numpy().astype(np.float64).reshape(-1, 4)
+    trc = pf.render_trace(scene, cam)[0].cpu().numpy().astype(np.float64).reshape(-1, 4)
+    return scene, ras, trc
+
+
+def _check(pf, sc, cam, name, min_alpha=0.05):
+    scene, ras, trc = _render_both(pf, sc, cam)
+    ref = oracle.render_walk(sc, cam)
+    e1, e2 = np.abs(ras - ref).max(), np.abs(trc - ref).max()
+    _flush(f"  {name}: raster err {e1:.2e}, trace err {e2:.2e}, max A {ref[:, 3].max():.3f}")
+    assert ref[:, 3].max() >= min_alpha
+    assert e1 <= TOL and e2 <= TOL
+    return scene
+
+
+def test_single_cell_forward_and_backward():
+    import paper_2604_24994_amd as pf
+    _flush("case single cell")
+    sc = W.scene_uniform(1, seed=5)
+    sc.p[:] = 0.0
+    sc.radius[:] = 0.8
+    sc.occ_logit[:] = 1.0
+    cam = W.pinhole(np.array([0.2, -2.5, 0.3]), 24, 20, 60.0)
+    _check(pf, sc, cam, "one cell")
+    params = {f: torch.tensor(getattr(sc, f), device="cuda", requires_grad=True) for f in FIELDS}
+    scene = pf.build_scene(params, sigma_scale=sc.sigma_scale, tau=sc.tau,
+                           box=(np.minimum(cam.c2w[:, 3], -1) - 0.1, np.maximum(cam.c2w[:, 3], 1) + 0.1))
+    G = np.random.default_rng(1).normal(size=(cam.n_rays, 4))
+    img = pf.render_raster_diff(scene, cam)[0]
+    (img.reshape(-1, 4) * torch.tensor(G, device="cuda", dtype=torch.float32)).sum().backward()
+    ref, _ = oracle.adjoint_gradients(sc, cam, G)
+    for f in FIELDS:
+        g = params[f].grad.cpu().numpy().astype(np.float64)
+        r = np.asarray(ref[f]).reshape(g.shape)
+        err = np.abs(g - r).max() / max(np.abs(r).max(), 1e-30)
+        _flush(f"  grad {f:10s} rel {err:.2e}")
+        assert err <= 1e-3, f
+
+
+def test_coincident_sites():
+    import paper_2604_24994_amd as pf
+    _flush("case coincident sites")
+    sc = W.scene_uniform(64, seed=6)
+    sc.radius = (sc.radius * 3.0).astype(np.float32)
+    sc.p[1] = sc.p[0]                  # same site, smaller weight: owns nothing
+    sc.power[1] = sc.power[0] * 0.5
+    sc.p[3] = sc.p[2]
+    sc.power[3] = sc.power[2] * 2.0    # same site, larger weight: owns the cell
+    cam = W.pinhole(W.random_eyes(1, 2.8, 6)[0], 32, 24, 60.0)
+    _check(pf, sc, cam, "coincident")
+
+
+def test_camera_inside_a_sphere():
+    import paper_2604_24994_amd as pf
+    _flush("case camera inside a sphere")
+    sc = W.scene_uniform(200, seed=7)
+    sc.radius = (sc.radius * 3.0).astype(np.float32)
+    eye = sc.p[10] + np.float32(0.3) * sc.radius[10] * np.array([1.0, 0.0, 0.0], np.float32)
+    cam = W.pinhole(eye, 32, 24, 70.0, target=(0.0, 0.0, 0.0))
+    _check(pf, sc, cam, "inside")
+
+
+def test_view_that_sees_nothing_has_empty_backward():
+    import paper_2604_24994_amd as pf
+    _flush("case empty view")
+    sc = W.scene_uniform(100, seed=8)
+    cam = W.pinhole(np.array([0.0, 0.0, 6.0]), 16, 16, 20.0, target=(0.0, 0.0, 20.0))   # looking away
+    params = {f: torch.tensor(getattr(sc, f), device="cuda", requires_grad=True) for f in FIELDS}
+    scene = pf.build_scene(params, sigma_scale=sc.sigma_scale, tau=sc.tau,
+                           box=(np.array([-2, -2, -2]), np.array([2, 2, 7])))
+    img = pf.render_raster_diff(scene, cam)[0]
+    assert float(img.detach().abs().max()) == 0.0
+    img.sum().backward()
+    for f in FIELDS:
+        assert float(params[f].grad.abs().max()) == 0.0, f
+    trc = pf.render_trace(scene, cam)[0]
+    assert float(trc.abs().max()) == 0.0
+
+
+def test_zero_density_everywhere():
+    import paper_2604_24994_amd as pf
+    _flush("case zero density")
+    sc = W.scene_uniform(150, seed=9)
+    sc.sigma_scale = 0.0
+    cam = W.pinhole(W.random_eyes(1, 3.0, 9)[0], 20, 16, 60.0)
+    scene, ras, trc = _render_both(pf, sc, cam)
+    assert scene.info()["n_hidden"] == 150
+    assert np.abs(ras).max() == 0.0 and np.abs(trc).max() == 0.0
+
+
+def test_fisheye_mask_outside_field_of_view():
+    import paper_2604_24994_amd as pf
+    _flush("case fisheye 120 degrees")
+    sc = W.c1_scene()
+    cam = W.fisheye(W.random_eyes(1, 3.0, 10)[0], 40, 40, 120.0)
+    _check(pf, sc, cam, "fisheye 120")
+    _, ras, trc = _render_both(pf, sc, cam)
+    yy, xx = np.mgrid[0:40, 0:40]
+    rho = np.hypot(xx + 0.5 - cam.cx, yy + 0.5 - cam.cy).reshape(-1)
+    outside = rho / cam.f_fish > cam.theta_max * (1 + 1e-6)
+    assert outside.sum() > 50
+    assert np.abs(ras[outside]).max() == 0.0 and np.abs(trc[outside]).max() == 0.0
