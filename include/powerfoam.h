@@ -33,7 +33,11 @@
  *    pointers to the parameter arrays inside a scene, so they must stay
  *    allocated and unchanged until pf_scene_destroy (re-build after changing
  *    them).  Library-owned memory (adjacency, per-view lists, forward state)
- *    is released by pf_scene_destroy / pf_state_release.
+ *    is released by pf_scene_destroy / pf_state_release.  It is allocated
+ *    stream-ordered (hipMallocAsync) from the device's default memory pool,
+ *    whose release threshold the library raises so that freed blocks stay
+ *    in the pool for reuse (this affects every user of that pool in the
+ *    process).
  *  - Images: a call with ncam cameras writes ncam images back to back into
  *    rgba, image c at float offset 4*sum_{c'<c} W_c'*H_c', each [H][W][4]
  *    (R, G, B, A), pixel (x, y) at row y, column x, sampled at its centre.
@@ -145,10 +149,14 @@ pf_status pf_build_scene(const pf_params* params, const pf_build_opts* opts,
 
 /* Rebuilds the adjacency, cull radii and flags of an existing scene for new
    parameter values (the sites moved during training), keeping the scene's
-   build options and sizing hints.  params (host) as for pf_build_scene; the
-   scene then references the new arrays.  Must not overlap a render or
-   backward on the scene.  On error the scene keeps its previous state.
-   Errors: as pf_build_scene. */
+   build options and sizing hints.  The previous adjacency seeds the new one
+   (a cell starts from its previous neighbours, or from the sites that
+   emptied it), which makes small moves cheap; the result is the same as a
+   fresh pf_build_scene (faces are written in a canonical order).  params
+   (host) as for pf_build_scene; the scene then references the new arrays.
+   Must not overlap a render or backward on the scene; the old arrays are
+   freed stream-ordered on `stream`.  On error the scene keeps its previous
+   state.  Errors: as pf_build_scene. */
 pf_status pf_update_scene(pf_scene* scene, const pf_params* params, void* stream);
 
 /* Scene statistics (host struct). */
@@ -226,6 +234,9 @@ typedef struct {
 pf_status pf_backward(pf_scene* scene, pf_fwd_state* state, const float* d_rgba,
                       const pf_grads* grads, const pf_backward_opts* opts, void* stream);
 
+/* Frees a forward state, stream-ordered on the stream it was rendered on
+   (which must still exist); work already queued there that uses it
+   finishes first. */
 void pf_state_release(pf_fwd_state* state);
 
 /* Connectivity loss (supplementary material, loss functions) over the Cech
