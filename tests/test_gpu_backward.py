@@ -52,3 +52,38 @@ def test_backward_matches_oracle_adjoint(seed, n, scale):
         _flush(f"  {f:10s} |g_ref|max {scale_ref:.4e}  max err {err:.3e}  rel {err / max(scale_ref, 1e-30):.3e}")
         assert scale_ref > 0
         assert err <= 1e-3 * scale_ref, f
+
+
+def test_c3_subset_l2_loss_gradients_match_oracle():
+    # a seeded 4,096-site subset of the 1,048,576-cell generator, two views
+    # at distance 4, L2 loss against seeded noise targets
+    import paper_2604_24994_amd as pf
+    _flush("case C3 subset: 4,096 sites, 2 views 64x48, L2 loss")
+    full = W.c3_scene()
+    rng = np.random.default_rng(4)
+    sc = full.subset(np.sort(rng.choice(full.n, 4096, replace=False)))
+    del full
+    cams = [W.pinhole(e, 64, 48, 60.0) for e in W.random_eyes(2, 4.0, 41)]
+    tgts = [np.random.default_rng(50 + i).uniform(0, 1, (c.n_rays, 3)) for i, c in enumerate(cams)]
+    npix = sum(c.n_rays for c in cams)
+    params = {f: torch.tensor(getattr(sc, f), device="cuda", requires_grad=True) for f in PARAMS}
+    scene = pf.build_scene(params, sigma_scale=sc.sigma_scale, tau=sc.tau)
+    imgs = pf.render_raster_diff(scene, cams)
+    loss = sum(((im.reshape(-1, 4)[:, :3] - torch.tensor(t, device="cuda", dtype=torch.float32)) ** 2).sum()
+               for im, t in zip(imgs, tgts)) / (3 * npix)
+    loss.backward()
+    g_ref = {f: np.zeros(getattr(sc, f).shape) for f in PARAMS}
+    for cam, t in zip(cams, tgts):
+        rgba = oracle.render_walk(sc, cam)
+        G = np.zeros((cam.n_rays, 4))
+        G[:, :3] = 2.0 * (rgba[:, :3] - t) / (3 * npix)
+        gr, _ = oracle.adjoint_gradients(sc, cam, G)
+        for f in PARAMS:
+            g_ref[f] += gr[f].reshape(g_ref[f].shape)
+    for f in PARAMS:
+        g = params[f].grad.detach().cpu().numpy().astype(np.float64)
+        scale_ref = np.abs(g_ref[f]).max()
+        err = np.abs(g - g_ref[f]).max()
+        _flush(f"  {f:10s} |g_ref|max {scale_ref:.4e}  rel {err / max(scale_ref, 1e-30):.3e}")
+        assert scale_ref > 0
+        assert err <= 1e-3 * scale_ref, f
