@@ -33,11 +33,11 @@
  *    pointers to the parameter arrays inside a scene, so they must stay
  *    allocated and unchanged until pf_scene_destroy (re-build after changing
  *    them).  Library-owned memory (adjacency, per-view lists, forward state)
- *    is released by pf_scene_destroy / pf_state_release.  It is allocated
- *    stream-ordered (hipMallocAsync) from the device's default memory pool,
- *    whose release threshold the library raises so that freed blocks stay
- *    in the pool for reuse (this affects every user of that pool in the
- *    process).
+ *    is released by pf_scene_destroy / pf_state_release.  The library keeps
+ *    released device blocks in a cache of its own and reuses them
+ *    stream-ordered (a reuse waits for an event recorded where the block
+ *    was released); blocks go back to the runtime when the cache passes
+ *    48 GiB or a device allocation fails.
  *  - Images: a call with ncam cameras writes ncam images back to back into
  *    rgba, image c at float offset 4*sum_{c'<c} W_c'*H_c', each [H][W][4]
  *    (R, G, B, A), pixel (x, y) at row y, column x, sampled at its centre.

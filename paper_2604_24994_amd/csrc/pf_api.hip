@@ -41,7 +41,7 @@ void free_state_mem(pf_fwd_state* s) {
   void* ptrs[] = {s->st.rec.ri,      s->st.rec.rf,  s->st.rec.rt,   s->st.rec.head,
                   s->st.rec.counter, s->st.rec.seg, s->st.cams_dev};
   for (void* q : ptrs)
-    if (q) (void)hipFreeAsync(q, s->stream);
+    if (q) pf::pool_free(q, s->stream);
   s->st.rec = pf::RecBuf{};
   s->st.cams_dev = nullptr;
 }
@@ -100,25 +100,6 @@ int64_t image_floats(const pf_camera* cams, int32_t ncam) {
 
 }  // namespace
 
-namespace {
-// The library's device memory is stream-ordered (hipMallocAsync /
-// hipFreeAsync); the device's default pool keeps what is freed instead of
-// returning it at every synchronisation, so per-step buffers (the record
-// pool, the rebuilt adjacency) are reused without new mappings.
-std::atomic<unsigned long long> g_pool_kept{0};
-void keep_pool() {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
-  const unsigned long long bit = 1ull << dev;
-  if (g_pool_kept.load() & bit) return;
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-    uint64_t thr = UINT64_MAX;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-  }
-  g_pool_kept.fetch_or(bit);
-}
-}  // namespace
 
 extern "C" {
 
@@ -143,7 +124,6 @@ static pf_status check_params(const pf_params* params, const char* who) {
 }
 
 pf_status pf_build_scene(const pf_params* params, const pf_build_opts* opts, void* stream, pf_scene** out) {
-  keep_pool();
   if (!out) return invalid("pf_build_scene: out is NULL");
   *out = nullptr;
   {
@@ -173,7 +153,6 @@ pf_status pf_build_scene(const pf_params* params, const pf_build_opts* opts, voi
 }
 
 pf_status pf_update_scene(pf_scene* scene, const pf_params* params, void* stream) {
-  keep_pool();
   if (!scene) return invalid("pf_update_scene: scene is NULL");
   {
     const pf_status st = check_params(params, "pf_update_scene");
@@ -182,13 +161,13 @@ pf_status pf_update_scene(pf_scene* scene, const pf_params* params, void* stream
   pf::Scene fresh;
   const pf_status st = pf::build_scene_impl(*params, scene->opts, (hipStream_t)stream, &fresh, &scene->s);
   if (st != PF_OK) {
-    pf::free_scene(&fresh, (hipStream_t)stream);
+    pf::free_scene(&fresh, (hipStream_t)stream, true);
     return st;
   }
   fresh.rec_per_pixel = scene->s.rec_per_pixel;
   fresh.seg_per_pixel = scene->s.seg_per_pixel;
   fresh.pairs_per_cell = scene->s.pairs_per_cell;
-  pf::free_scene(&scene->s, (hipStream_t)stream);
+  pf::free_scene(&scene->s, (hipStream_t)stream, true);
   scene->s = fresh;
   return PF_OK;
 }
@@ -277,7 +256,7 @@ pf_status new_state(pf_scene* scene, const pf_camera* cams, int32_t ncam, int ki
   fs->st.npix = npix;
   fs->st.ncam = ncam;
   fs->st.ntiles = ntiles;
-  hipError_t e = hipMallocAsync((void**)&fs->st.cams_dev, sizeof(pf_camera) * ncam, s);
+  hipError_t e = pf::pool_alloc((void**)&fs->st.cams_dev, sizeof(pf_camera) * ncam, s);
   if (e == hipSuccess) e = hipMemcpyAsync(fs->st.cams_dev, cams, sizeof(pf_camera) * ncam, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) {
     pf::set_error(std::string(who) + ": " + hipGetErrorString(e));
@@ -298,8 +277,8 @@ pf_status fill_records(pf_fwd_state* fs, float* rgba, unsigned long long* trunc_
                        const char* who) {
   pf_scene* scene = fs->scene;
   const int64_t npix = fs->st.npix;
-  hipError_t e = hipMallocAsync((void**)&fs->st.rec.head, sizeof(int32_t) * npix, s);
-  if (e == hipSuccess) e = hipMallocAsync((void**)&fs->st.rec.counter, 3 * sizeof(unsigned long long), s);
+  hipError_t e = pf::pool_alloc((void**)&fs->st.rec.head, sizeof(int32_t) * npix, s);
+  if (e == hipSuccess) e = pf::pool_alloc((void**)&fs->st.rec.counter, 3 * sizeof(unsigned long long), s);
   if (e != hipSuccess) {
     pf::set_error(std::string(who) + ": " + hipGetErrorString(e));
     return e == hipErrorOutOfMemory ? PF_ERR_OOM : PF_ERR_HIP;
@@ -307,16 +286,19 @@ pf_status fill_records(pf_fwd_state* fs, float* rgba, unsigned long long* trunc_
   const bool seen = scene->s.rec_per_pixel > 0.0;
   const double rpp = seen ? scene->s.rec_per_pixel : g_rec_hint.load();
   const double spp = seen ? scene->s.seg_per_pixel : g_seg_hint.load();
-  int64_t cap = (int64_t)(rpp * (double)npix) + 4096;
-  int64_t seg_cap = (int64_t)(spp * (double)npix) + 4096;
+  // capacities in coarse steps, so that steps of similar size ask the
+  // memory pool for the same block sizes and reuse them
+  auto coarse = [](int64_t x, int64_t step) { return (x + step - 1) / step * step; };
+  int64_t cap = coarse((int64_t)(rpp * (double)npix) + 4096, 1 << 22);
+  int64_t seg_cap = coarse((int64_t)(spp * (double)npix) + 4096, 1 << 20);
   if (fs->kind == 1) seg_cap = std::max(seg_cap, cap);   // one segment per record on the walk
   for (int attempt = 0; attempt < 2; ++attempt) {
     fs->st.rec.cap = cap;
     fs->st.rec.seg_cap = seg_cap;
-    e = hipMallocAsync((void**)&fs->st.rec.ri, sizeof(int4) * cap, s);
-    if (e == hipSuccess) e = hipMallocAsync((void**)&fs->st.rec.rf, sizeof(float4) * cap, s);
-    if (e == hipSuccess) e = hipMallocAsync((void**)&fs->st.rec.rt, sizeof(float) * cap, s);
-    if (e == hipSuccess) e = hipMallocAsync((void**)&fs->st.rec.seg, sizeof(int4) * seg_cap, s);
+    e = pf::pool_alloc((void**)&fs->st.rec.ri, sizeof(int4) * cap, s);
+    if (e == hipSuccess) e = pf::pool_alloc((void**)&fs->st.rec.rf, sizeof(float4) * cap, s);
+    if (e == hipSuccess) e = pf::pool_alloc((void**)&fs->st.rec.rt, sizeof(float) * cap, s);
+    if (e == hipSuccess) e = pf::pool_alloc((void**)&fs->st.rec.seg, sizeof(int4) * seg_cap, s);
     if (e == hipSuccess) e = hipMemsetAsync(fs->st.rec.counter, 0, 3 * sizeof(unsigned long long), s);
     if (e == hipSuccess && fs->kind == 1) e = hipMemsetAsync(fs->st.rec.seg, 0, sizeof(int4) * seg_cap, s);
     if (e == hipSuccess && trunc_dev) e = hipMemsetAsync(trunc_dev, 0, sizeof(unsigned long long), s);
@@ -353,13 +335,13 @@ pf_status fill_records(pf_fwd_state* fs, float* rgba, unsigned long long* trunc_
       return PF_OK;
     }
     void* pool[] = {fs->st.rec.ri, fs->st.rec.rf, fs->st.rec.rt, fs->st.rec.seg};
-    for (void* q : pool) (void)hipFreeAsync(q, s);
+    for (void* q : pool) pf::pool_free(q, s);
     fs->st.rec.ri = nullptr;
     fs->st.rec.rf = nullptr;
     fs->st.rec.rt = nullptr;
     fs->st.rec.seg = nullptr;
-    cap = std::max(cap, (int64_t)used[0] + 4096);
-    seg_cap = std::max(seg_cap, (int64_t)used[1] + 4096);
+    cap = std::max(cap, coarse((int64_t)used[0] + 4096, 1 << 22));
+    seg_cap = std::max(seg_cap, coarse((int64_t)used[1] + 4096, 1 << 20));
   }
   pf::set_error(std::string(who) + ": record pool sizing failed");
   return PF_ERR_HIP;
@@ -369,7 +351,6 @@ pf_status fill_records(pf_fwd_state* fs, float* rgba, unsigned long long* trunc_
 
 pf_status pf_render_raster(pf_scene* scene, const pf_camera* cams, int32_t ncam, const pf_render_opts* opts,
                            float* rgba, pf_fwd_state** state, void* stream) {
-  keep_pool();
   if (state) *state = nullptr;
   pf_status st = check_render(scene, cams, ncam, rgba, "pf_render_raster");
   if (st != PF_OK) return st;
@@ -397,7 +378,6 @@ pf_status pf_render_raster(pf_scene* scene, const pf_camera* cams, int32_t ncam,
 
 pf_status pf_render_trace(pf_scene* scene, const pf_camera* cams, int32_t ncam, const pf_render_opts* opts,
                           float* rgba, int64_t* truncated, pf_fwd_state** state, void* stream) {
-  keep_pool();
   if (state) *state = nullptr;
   pf_status st = check_render(scene, cams, ncam, rgba, "pf_render_trace");
   if (st != PF_OK) return st;
@@ -415,10 +395,10 @@ pf_status pf_render_trace(pf_scene* scene, const pf_camera* cams, int32_t ncam, 
   if (mode != 0 && mode != 1) return invalid("pf_render_trace: state_mode must be 0 (store) or 1 (recompute)");
   hipStream_t s = (hipStream_t)stream;
   unsigned long long* trunc = nullptr;
-  PF_HIP_TRY(hipMallocAsync((void**)&trunc, sizeof(unsigned long long), s));
+  PF_HIP_TRY(pf::pool_alloc((void**)&trunc, sizeof(unsigned long long), s));
   hipError_t e = hipMemsetAsync(trunc, 0, sizeof(unsigned long long), s);
   if (e != hipSuccess) {
-    (void)hipFreeAsync(trunc, s);
+    pf::pool_free(trunc, s);
     PF_HIP_TRY(e);
   }
   pf_fwd_state* fs = nullptr;
@@ -441,7 +421,7 @@ pf_status pf_render_trace(pf_scene* scene, const pf_camera* cams, int32_t ncam, 
       *truncated = (int64_t)h;
     }
   }
-  (void)hipFreeAsync(trunc, s);
+  pf::pool_free(trunc, s);
   if (st != PF_OK) {
     if (fs) {
       free_state_mem(fs);
@@ -455,7 +435,6 @@ pf_status pf_render_trace(pf_scene* scene, const pf_camera* cams, int32_t ncam, 
 
 pf_status pf_backward(pf_scene* scene, pf_fwd_state* state, const float* d_rgba, const pf_grads* grads,
                       const pf_backward_opts* opts, void* stream) {
-  keep_pool();
   if (!scene || !state || !d_rgba || !grads) return invalid("pf_backward: NULL argument");
   if (state->scene != scene) return invalid("pf_backward: the state belongs to another scene");
   if (state->consumed)
@@ -482,8 +461,8 @@ pf_status pf_backward(pf_scene* scene, pf_fwd_state* state, const float* d_rgba,
   if (st != PF_OK) return st;
   float* scratch = nullptr;
   unsigned long long* trunc = nullptr;
-  hipError_t e = hipMallocAsync((void**)&scratch, sizeof(float) * 4 * tmp->st.npix, s);
-  if (e == hipSuccess && state->kind == 1) e = hipMallocAsync((void**)&trunc, sizeof(unsigned long long), s);
+  hipError_t e = pf::pool_alloc((void**)&scratch, sizeof(float) * 4 * tmp->st.npix, s);
+  if (e == hipSuccess && state->kind == 1) e = pf::pool_alloc((void**)&trunc, sizeof(unsigned long long), s);
   if (e != hipSuccess) {
     pf::set_error(std::string("pf_backward: ") + hipGetErrorString(e));
     st = e == hipErrorOutOfMemory ? PF_ERR_OOM : PF_ERR_HIP;
@@ -497,8 +476,8 @@ pf_status pf_backward(pf_scene* scene, pf_fwd_state* state, const float* d_rgba,
       st = PF_ERR_HIP;
     }
   }
-  if (scratch) (void)hipFreeAsync(scratch, s);
-  if (trunc) (void)hipFreeAsync(trunc, s);
+  if (scratch) pf::pool_free(scratch, s);
+  if (trunc) pf::pool_free(trunc, s);
   free_state_mem(tmp);
   delete tmp;
   return st;
@@ -513,7 +492,6 @@ pf_status pf_connect_loss(const pf_scene* scene, float lambda, const pf_grads* g
 pf_status pf_steiner(const pf_params* params, const float* z, const pf_steiner_opts* opts, int64_t cap,
                      float* out_p, float* out_power, float* out_radius, int32_t* out_near, int64_t* round_counts,
                      int64_t* n_out, void* stream) {
-  keep_pool();
   if (!params || !z || !opts || !n_out) return invalid("pf_steiner: NULL argument");
   const pf_params& p = *params;
   if (p.n < 1 || p.n >= (1ll << 30)) return invalid("pf_steiner: n must be in 1 .. 2^30 - 1");
@@ -541,7 +519,6 @@ pf_status pf_densify_prune(const pf_params* params, const float* err_ema, const 
                            const float* delta, const pf_densify_opts* opts, const pf_cell_arrays* out, float* out_err,
                            float* out_contrib, int32_t* out_parent, int64_t* n_kept, int64_t* n_drawn,
                            void* stream) {
-  keep_pool();
   if (!opts || !out || !err_ema || !contrib_ema || !out_err || !out_contrib || !n_kept || !n_drawn)
     return invalid("pf_densify_prune: NULL argument");
   {

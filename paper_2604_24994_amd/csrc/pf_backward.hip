@@ -616,8 +616,8 @@ struct Buf {
   T* p = nullptr;
   hipStream_t s;
   explicit Buf(hipStream_t st) : s(st) {}
-  ~Buf() { if (p) (void)hipFreeAsync(p, s); }
-  hipError_t alloc(size_t count) { return hipMallocAsync((void**)&p, sizeof(T) * (count ? count : 1), s); }
+  ~Buf() { if (p) pf::pool_free(p, s); }
+  hipError_t alloc(size_t count) { return pf::pool_alloc((void**)&p, sizeof(T) * (count ? count : 1), s); }
 };
 
 }  // namespace

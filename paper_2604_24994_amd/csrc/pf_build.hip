@@ -1062,10 +1062,10 @@ struct DevBuf {
   T* p = nullptr;
   hipStream_t s;
   explicit DevBuf(hipStream_t st) : s(st) {}
-  ~DevBuf() { if (p) (void)hipFreeAsync(p, s); }
-  hipError_t alloc(size_t count) { return hipMallocAsync((void**)&p, sizeof(T) * (count ? count : 1), s); }
+  ~DevBuf() { if (p) pf::pool_free(p, s); }
+  hipError_t alloc(size_t count) { return pf::pool_alloc((void**)&p, sizeof(T) * (count ? count : 1), s); }
   void reset() {
-    if (p) (void)hipFreeAsync(p, s);
+    if (p) pf::pool_free(p, s);
     p = nullptr;
   }
 };
@@ -1109,11 +1109,13 @@ pf_status connect_loss_impl(const Scene& sc, float lambda, const pf_grads& g, do
   return PF_OK;
 }
 
-void free_scene(Scene* sc, hipStream_t s) {
+void free_scene(Scene* sc, hipStream_t s, bool async) {
   void* ptrs[] = {sc->geo,  sc->nrm,    sc->cull,   sc->flags, sc->row,  sc->nrast, sc->col,
                   sc->plane, sc->t_sp, sc->t_sidx, sc->t_srad, sc->t_lo, sc->t_hi, sc->wit};
+  // synchronous: renders on any stream may still read the arrays
+  if (!async) (void)hipDeviceSynchronize();
   for (void* q : ptrs)
-    if (q) (void)(s ? hipFreeAsync(q, s) : hipFree(q));
+    if (q) pf::pool_free(q, async ? s : nullptr);
   sc->geo = sc->nrm = nullptr;
   sc->cull = nullptr;
   sc->flags = sc->row = sc->nrast = sc->col = nullptr;
@@ -1189,9 +1191,9 @@ pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipSt
   PF_HIP_TRY(hipGetLastError());
   PF_HIP_TRY(radix_sort_u32(keys.p, order.p, n, 30, s));
   // the sorted sites and the tree stay with the scene (sphere-overlap queries)
-  PF_HIP_TRY(hipMallocAsync((void**)&sc->t_sp, sizeof(float4) * n, s));
-  PF_HIP_TRY(hipMallocAsync((void**)&sc->t_sidx, sizeof(int32_t) * n, s));
-  PF_HIP_TRY(hipMallocAsync((void**)&sc->t_srad, sizeof(float) * n, s));
+  PF_HIP_TRY(pf::pool_alloc((void**)&sc->t_sp, sizeof(float4) * n, s));
+  PF_HIP_TRY(pf::pool_alloc((void**)&sc->t_sidx, sizeof(int32_t) * n, s));
+  PF_HIP_TRY(pf::pool_alloc((void**)&sc->t_srad, sizeof(float) * n, s));
   struct { float4* p; } sp{sc->t_sp};
   struct { int32_t* p; } sidx{sc->t_sidx};
   k_gather_sites<<<g256, 256, 0, s>>>(prm.p, prm.power, prm.radius, order.p, n, sp.p, sidx.p, sc->t_srad);
@@ -1216,8 +1218,8 @@ pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipSt
       total_nodes += lvl.cnt[L];
     } while (lvl.cnt[L] > 1);
     lvl.n = L;
-    PF_HIP_TRY(hipMallocAsync((void**)&lo_p, sizeof(float4) * total_nodes, s));
-    PF_HIP_TRY(hipMallocAsync((void**)&hi_p, sizeof(float4) * total_nodes, s));
+    PF_HIP_TRY(pf::pool_alloc((void**)&lo_p, sizeof(float4) * total_nodes, s));
+    PF_HIP_TRY(pf::pool_alloc((void**)&hi_p, sizeof(float4) * total_nodes, s));
     for (int l = 1; l <= lvl.n; ++l) {
       const bool from_sites = l == 1;
       k_tree_level<<<(unsigned)lvl.cnt[l], 64, 0, s>>>(from_sites ? sites : nullptr, from_sites ? srad : nullptr,
@@ -1236,14 +1238,14 @@ pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipSt
   struct { float4* p; } nlo{sc->t_lo}, nhi{sc->t_hi};
 
   // per-cell clipping
-  PF_HIP_TRY(hipMallocAsync((void**)&sc->cull, sizeof(float) * n, s));
-  PF_HIP_TRY(hipMallocAsync((void**)&sc->flags, sizeof(int32_t) * n, s));
-  PF_HIP_TRY(hipMallocAsync((void**)&sc->wit, sizeof(int32_t) * WIT * n, s));
+  PF_HIP_TRY(pf::pool_alloc((void**)&sc->cull, sizeof(float) * n, s));
+  PF_HIP_TRY(pf::pool_alloc((void**)&sc->flags, sizeof(int32_t) * n, s));
+  PF_HIP_TRY(pf::pool_alloc((void**)&sc->wit, sizeof(int32_t) * WIT * n, s));
   PF_HIP_TRY(hipMemsetAsync(sc->wit, 0xFF, sizeof(int32_t) * WIT * n, s));
-  PF_HIP_TRY(hipMallocAsync((void**)&sc->nrast, sizeof(int32_t) * n, s));
-  PF_HIP_TRY(hipMallocAsync((void**)&sc->row, sizeof(int32_t) * (n + 1), s));
-  PF_HIP_TRY(hipMallocAsync((void**)&sc->geo, sizeof(float4) * n, s));
-  PF_HIP_TRY(hipMallocAsync((void**)&sc->nrm, sizeof(float4) * n, s));
+  PF_HIP_TRY(pf::pool_alloc((void**)&sc->nrast, sizeof(int32_t) * n, s));
+  PF_HIP_TRY(pf::pool_alloc((void**)&sc->row, sizeof(int32_t) * (n + 1), s));
+  PF_HIP_TRY(pf::pool_alloc((void**)&sc->geo, sizeof(float4) * n, s));
+  PF_HIP_TRY(pf::pool_alloc((void**)&sc->nrm, sizeof(float4) * n, s));
   DevBuf<int32_t> faces_tmp(s), counts(s), bigslot(s), spos(s), klist(s), faces_big(s);
   DevBuf<unsigned short> eo_big(s);
   DevBuf<unsigned int> nbig_d(s), ndrop_d(s);
@@ -1346,8 +1348,10 @@ pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt, hipSt
               "; " + std::to_string(sc->n_big) + " cells took the high-degree pass)");
     return PF_ERR_OVERFLOW;
   }
-  PF_HIP_TRY(hipMallocAsync((void**)&sc->col, sizeof(int32_t) * (total ? total : 1), s));
-  PF_HIP_TRY(hipMallocAsync((void**)&sc->plane, sizeof(float4) * (total ? total : 1), s));
+  // capacity in steps of 2^18 faces: rebuilds of similar size reuse the pool's blocks
+  const size_t fcap = ((size_t)total + (1u << 18)) & ~(size_t)((1u << 18) - 1);
+  PF_HIP_TRY(pf::pool_alloc((void**)&sc->col, sizeof(int32_t) * fcap, s));
+  PF_HIP_TRY(pf::pool_alloc((void**)&sc->plane, sizeof(float4) * fcap, s));
   k_fill<<<g256, 256, 0, s>>>(prm.p, prm.power, n, faces_tmp.p, faces_big.p, bigslot.p, (const uint32_t*)sc->row,
                               counts.p, bmin, bmax,
                               sc->col, sc->plane);

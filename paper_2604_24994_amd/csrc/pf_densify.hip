@@ -24,8 +24,8 @@ struct Tmp {
   T* p = nullptr;
   hipStream_t s;
   explicit Tmp(hipStream_t st) : s(st) {}
-  ~Tmp() { if (p) (void)hipFreeAsync(p, s); }
-  hipError_t alloc(size_t count) { return hipMallocAsync((void**)&p, sizeof(T) * (count ? count : 1), s); }
+  ~Tmp() { if (p) pf::pool_free(p, s); }
+  hipError_t alloc(size_t count) { return pf::pool_alloc((void**)&p, sizeof(T) * (count ? count : 1), s); }
 };
 
 __global__ void k_ema(float* __restrict__ ema, const float* __restrict__ value, int64_t n, float beta) {

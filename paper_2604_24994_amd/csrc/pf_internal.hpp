@@ -94,6 +94,12 @@ void set_error(const std::string& msg);
 bool dmalloc(void** p, size_t bytes, hipStream_t s, const char* what);
 void dfree(void* p, hipStream_t s);
 
+// Library device memory: blocks cached by the library and reused
+// stream-ordered.  pool_alloc returns a block usable on stream s; pool_free
+// gives it back once the work queued on s so far has finished with it.
+hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s);
+void pool_free(void* p, hipStream_t s);
+
 // --- scan / sort utilities (pf_util.hip) ---------------------------------
 // Exclusive prefix sum of n uint32 values; out may alias in.  Returns the
 // total through *total_dev (device, may be null).  Scratch is allocated on
@@ -109,8 +115,8 @@ hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int bits,
 // each cell's first candidates (the result does not depend on it).
 pf_status build_scene_impl(const pf_params& prm, const pf_build_opts& opt,
                            hipStream_t s, Scene* sc, const Scene* prev = nullptr);
-// Frees the scene's arrays: stream-ordered on s, or synchronously (s null).
-void free_scene(Scene* sc, hipStream_t s = nullptr);
+// Frees the scene's arrays: stream-ordered on s (async), or synchronously.
+void free_scene(Scene* sc, hipStream_t s = nullptr, bool async = false);
 // lambda * sum_i sum_{j overlapping i} max(r_i + r_j - |p_i - p_j|, 0)^2 and
 // its gradient (adds into g.p and g.radius; the value into *loss_dev).
 pf_status connect_loss_impl(const Scene& sc, float lambda, const pf_grads& g, double* loss_dev, hipStream_t s);

@@ -35,8 +35,8 @@ struct Tmp {
   T* p = nullptr;
   hipStream_t s;
   explicit Tmp(hipStream_t st) : s(st) {}
-  ~Tmp() { if (p) (void)hipFreeAsync(p, s); }
-  hipError_t alloc(size_t count) { return hipMallocAsync((void**)&p, sizeof(T) * (count ? count : 1), s); }
+  ~Tmp() { if (p) pf::pool_free(p, s); }
+  hipError_t alloc(size_t count) { return pf::pool_alloc((void**)&p, sizeof(T) * (count ? count : 1), s); }
 };
 
 __device__ inline uint32_t spread10_s(uint32_t v) {

@@ -6,7 +6,131 @@
 // equal digits inside a wave with ballot-based matching.
 #include "pf_internal.hpp"
 
+#include <iterator>
+#include <map>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
 namespace pf {
+
+// Device blocks are cached by the library: a freed block is kept, with an
+// event recorded on the stream that freed it, and handed out again (the new
+// stream waits for that event) to an allocation of at most twice its size.
+// The runtime is asked for memory only on a miss; blocks go back to it when
+// the cache exceeds its limit or an allocation fails.
+namespace {
+struct CachedBlock {
+  void* p;
+  size_t bytes;
+  int dev;
+  hipEvent_t ev;
+};
+std::mutex g_cache_mu;
+std::multimap<size_t, CachedBlock> g_cache;                  // free blocks by size
+std::unordered_map<void*, std::pair<size_t, int>> g_live;    // handed-out blocks: size, device
+size_t g_cached_bytes = 0;
+constexpr size_t CACHE_LIMIT = size_t(48) << 30;
+
+size_t round_bytes(size_t bytes) {
+  // above 1 MiB in steps of 1/16 of the power of two (at most 6.25% more)
+  if (bytes <= (1u << 20)) return bytes < 256 ? 256 : (bytes + 255) & ~size_t(255);
+  size_t pw = 1;
+  while (pw < bytes) pw <<= 1;
+  const size_t step = pw >> 4;
+  return (bytes + step - 1) / step * step;
+}
+
+void release_block(const CachedBlock& b) {
+  (void)hipEventSynchronize(b.ev);
+  (void)hipEventDestroy(b.ev);
+  (void)hipFree(b.p);
+}
+
+// Returns the cached blocks of device dev to the runtime.
+void flush_device(int dev) {
+  std::vector<CachedBlock> out;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (auto it = g_cache.begin(); it != g_cache.end();) {
+      if (it->second.dev == dev) {
+        out.push_back(it->second);
+        g_cached_bytes -= it->second.bytes;
+        it = g_cache.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  for (const CachedBlock& b : out) release_block(b);
+}
+}  // namespace
+
+hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s) {
+  bytes = round_bytes(bytes);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  {
+    std::unique_lock<std::mutex> lk(g_cache_mu);
+    for (auto it = g_cache.lower_bound(bytes); it != g_cache.end() && it->first <= 2 * bytes; ++it) {
+      if (it->second.dev != dev) continue;
+      const CachedBlock b = it->second;
+      g_cache.erase(it);
+      g_cached_bytes -= b.bytes;
+      g_live[b.p] = {b.bytes, dev};
+      lk.unlock();
+      e = hipStreamWaitEvent(s, b.ev, 0);
+      (void)hipEventDestroy(b.ev);
+      *p = b.p;
+      return e;
+    }
+  }
+  e = hipMalloc(p, bytes);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    flush_device(dev);
+    e = hipMalloc(p, bytes);
+  }
+  if (e == hipSuccess) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_live[*p] = {bytes, dev};
+  }
+  return e;
+}
+
+void pool_free(void* p, hipStream_t s) {
+  if (!p) return;
+  CachedBlock b{p, 0, 0, nullptr};
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_live.find(p);
+    if (it == g_live.end()) return;   // not from pool_alloc: nothing to do
+    b.bytes = it->second.first;
+    b.dev = it->second.second;
+    g_live.erase(it);
+  }
+  if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(b.ev, s) != hipSuccess) {
+    if (b.ev) (void)hipEventDestroy(b.ev);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(p);
+    return;
+  }
+  std::vector<CachedBlock> out;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_cache.insert({b.bytes, b});
+    g_cached_bytes += b.bytes;
+    while (g_cached_bytes > CACHE_LIMIT && !g_cache.empty()) {
+      auto last = std::prev(g_cache.end());
+      out.push_back(last->second);
+      g_cached_bytes -= last->second.bytes;
+      g_cache.erase(last);
+    }
+  }
+  for (const CachedBlock& v : out) release_block(v);
+}
 
 namespace {
 
@@ -90,7 +214,7 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint
     return hipGetLastError();
   }
   uint32_t* sums = nullptr;
-  hipError_t e = hipMallocAsync((void**)&sums, sizeof(uint32_t) * nb, s);
+  hipError_t e = pf::pool_alloc((void**)&sums, sizeof(uint32_t) * nb, s);
   if (e != hipSuccess) return e;
   k_block_sums<<<(unsigned)nb, SCAN_THREADS, 0, s>>>(in, n, sums);
   e = exclusive_scan_u32(sums, sums, nb, nullptr, s);
@@ -98,8 +222,8 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint
     k_block_apply<<<(unsigned)nb, SCAN_THREADS, 0, s>>>(in, n, sums, out, total_dev);
     e = hipGetLastError();
   }
-  hipError_t e2 = hipFreeAsync(sums, s);
-  return e != hipSuccess ? e : e2;
+  pf::pool_free(sums, s);
+  return e;
 }
 
 namespace {
@@ -176,9 +300,9 @@ hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int bits, h
   if (n <= 1) return hipSuccess;
   const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
   uint32_t *k2 = nullptr, *v2 = nullptr, *hist = nullptr;
-  hipError_t e = hipMallocAsync((void**)&k2, sizeof(uint32_t) * n, s);
-  if (e == hipSuccess) e = hipMallocAsync((void**)&v2, sizeof(uint32_t) * n, s);
-  if (e == hipSuccess) e = hipMallocAsync((void**)&hist, sizeof(uint32_t) * 256 * nb, s);
+  hipError_t e = pf::pool_alloc((void**)&k2, sizeof(uint32_t) * n, s);
+  if (e == hipSuccess) e = pf::pool_alloc((void**)&v2, sizeof(uint32_t) * n, s);
+  if (e == hipSuccess) e = pf::pool_alloc((void**)&hist, sizeof(uint32_t) * 256 * nb, s);
   uint32_t *ka = keys, *va = vals, *kb = k2, *vb = v2;
   int passes = 0;
   for (int shift = 0; e == hipSuccess && shift < bits; shift += 8, ++passes) {
@@ -194,9 +318,9 @@ hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int bits, h
     e = hipMemcpyAsync(keys, ka, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(vals, va, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s);
   }
-  if (k2) (void)hipFreeAsync(k2, s);
-  if (v2) (void)hipFreeAsync(v2, s);
-  if (hist) (void)hipFreeAsync(hist, s);
+  if (k2) pf::pool_free(k2, s);
+  if (v2) pf::pool_free(v2, s);
+  if (hist) pf::pool_free(hist, s);
   return e;
 }
 
