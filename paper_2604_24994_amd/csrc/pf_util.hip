@@ -15,8 +15,10 @@
 namespace pf {
 
 // Device blocks are cached by the library: a freed block is kept, with an
-// event recorded on the stream that freed it, and handed out again (the new
-// stream waits for that event) to an allocation of at most twice its size.
+// event recorded on the stream that freed it, and handed out again to an
+// allocation of at most twice its size on that stream (stream order makes
+// it safe), or on another stream once the event has completed (no stream
+// waits on another, so concurrent streams stay independent).
 // The runtime is asked for memory only on a miss; blocks go back to it when
 // the cache exceeds its limit or an allocation fails.
 namespace {
@@ -25,6 +27,7 @@ struct CachedBlock {
   size_t bytes;
   int dev;
   hipEvent_t ev;
+  hipStream_t freed_on;
 };
 std::mutex g_cache_mu;
 std::multimap<size_t, CachedBlock> g_cache;                  // free blocks by size
@@ -75,15 +78,18 @@ hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s) {
     std::unique_lock<std::mutex> lk(g_cache_mu);
     for (auto it = g_cache.lower_bound(bytes); it != g_cache.end() && it->first <= 2 * bytes; ++it) {
       if (it->second.dev != dev) continue;
+      if (it->second.freed_on != s && hipEventQuery(it->second.ev) != hipSuccess) {
+        (void)hipGetLastError();   // "not ready" is not an error of the caller's
+        continue;
+      }
       const CachedBlock b = it->second;
       g_cache.erase(it);
       g_cached_bytes -= b.bytes;
       g_live[b.p] = {b.bytes, dev};
       lk.unlock();
-      e = hipStreamWaitEvent(s, b.ev, 0);
       (void)hipEventDestroy(b.ev);
       *p = b.p;
-      return e;
+      return hipSuccess;
     }
   }
   e = hipMalloc(p, bytes);
@@ -101,7 +107,7 @@ hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s) {
 
 void pool_free(void* p, hipStream_t s) {
   if (!p) return;
-  CachedBlock b{p, 0, 0, nullptr};
+  CachedBlock b{p, 0, 0, nullptr, s};
   {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto it = g_live.find(p);
