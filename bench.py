@@ -50,11 +50,11 @@ FLOPS_BWD_PER_CONTRIB = 5100
 # for the kernel sources with these hashes; otherwise the bench reports null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC = {
-    "k_bwd_cell": {"fetch_kib": 19445871.0, "write_kib": 12987895.2,
-                   "sources": {"pf_backward.hip": "ffaff656026fb30b", "pf_shade.hpp": "68feb93f5734438a"}},
-    "k_raster_store": {"fetch_kib": 15663741.2, "write_kib": 11225375.5,
-                       "sources": {"pf_render.hip": "7c11b6fd407d2604", "pf_shade.hpp": "68feb93f5734438a"}},
-    "k_clip": {"fetch_kib": 409390.7, "write_kib": 180377.3, "sources": {"pf_build.hip": "bbeca12176f39233"}},
+    "k_bwd_cell": {"fetch_kib": 19495198.9, "write_kib": 12983539.8,
+                   "sources": {"pf_backward.hip": "ec9511a80ef4f081", "pf_shade.hpp": "68feb93f5734438a"}},
+    "k_raster_store": {"fetch_kib": 15663004.3, "write_kib": 11259801.8,
+                       "sources": {"pf_render.hip": "959a93f2bc46f6f7", "pf_shade.hpp": "68feb93f5734438a"}},
+    "k_clip": {"fetch_kib": 409405.6, "write_kib": 180394.4, "sources": {"pf_build.hip": "60ddab952277c61e"}},
 }
 
 
