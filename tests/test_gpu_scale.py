@@ -1,6 +1,9 @@
-"""Parity at the 1,048,576-cell workload (1600x1066 views): forward colours
-and backward gradients on seeded pixels against the FP64 oracle, which
-walks every sampled ray by brute force over all cells."""
+"""Parity at the 1,048,576-cell workload in the launch configuration of the
+timed training step: 8 views of 1600x1066 rendered in one store-mode launch,
+on a scene rebuilt in place after the sites moved by N(0, 1e-4), through the
+autograd path.  Forward colours and backward gradients on seeded pixels are
+checked against the FP64 oracle, which walks every sampled ray by brute
+force over all cells."""
 import time
 
 import numpy as np
@@ -25,49 +28,50 @@ def _pixels(cam, n, seed):
     return np.unique(ys * cam.width + xs)
 
 
-def test_c3_scale_forward_and_gradients_on_sampled_pixels():
+def test_c3_training_step_forward_and_gradients_on_sampled_pixels():
     import paper_2604_24994_amd as pf
-    _flush("case C3 scale: 1,048,576 cells, 2 views 1600x1066, 3 seeded pixels each")
+    _flush("case C3 training step: 1,048,576 cells, 8 views 1600x1066, sites moved and rebuilt, "
+           "2 seeded pixels per view")
     t0 = time.time()
     sc = W.c3_scene()
-    cams = W.c3_cameras(n_views=2)
-    params = {f: torch.tensor(getattr(sc, f), device="cuda") for f in PARAMS}
-    scene = pf.build_scene(params)
-    buf, state = pf.render_raster_state(scene, cams)
-    npix = [c.n_rays for c in cams]
-    d = torch.zeros_like(buf).view(-1, 4)
+    cams = W.c3_cameras(n_views=8)
+    params = {f: torch.tensor(getattr(sc, f), device="cuda", requires_grad=True) for f in PARAMS}
+    scene = pf.build_scene(params, sigma_scale=sc.sigma_scale, tau=sc.tau)
+    # the sites move as after an optimiser update; the adjacency is rebuilt
+    # in place, seeded by the first build
+    z = np.random.default_rng(13).standard_normal(sc.p.shape).astype(np.float32)
+    sc.p = (sc.p + np.float32(1e-4) * z).astype(np.float32)
+    with torch.no_grad():
+        params["p"].copy_(torch.tensor(sc.p))
+    pf.update_scene(scene, params)
+    imgs = pf.render_raster_diff(scene, cams)
     rng = np.random.default_rng(4)
-    picks, Gs = [], []
-    base = 0
-    for c, n in zip(cams, npix):
-        pix = _pixels(c, 3, seed=base + 7)
+    picks, Gs, loss = [], [], 0.0
+    for v, (c, im) in enumerate(zip(cams, imgs)):
+        pix = _pixels(c, 2, seed=100 + v)
         G = rng.normal(size=(len(pix), 4))
-        d[base + torch.as_tensor(pix, device="cuda")] = torch.tensor(G, dtype=torch.float32, device="cuda")
+        sel = im.reshape(-1, 4)[torch.as_tensor(pix, device="cuda")]
+        loss = loss + (sel * torch.tensor(G, dtype=torch.float32, device="cuda")).sum()
         picks.append(pix)
         Gs.append(G)
-        base += n
-    grads = {f: torch.zeros_like(params[f]) for f in PARAMS}
-    pf.backward(scene, state, d.reshape(-1), grads)
+    loss.backward()
     torch.cuda.synchronize()
     _flush(f"  GPU done in {time.time() - t0:.1f}s")
-    img = buf.view(-1, 4).cpu().numpy().astype(np.float64)
-    g_gpu = {f: grads[f].cpu().numpy().astype(np.float64) for f in PARAMS}
+    g_gpu = {f: params[f].grad.cpu().numpy().astype(np.float64) for f in PARAMS}
     g_ref = {f: np.zeros_like(g_gpu[f]) for f in PARAMS}
-    from oracle.cell import scene_tensors
-    S = scene_tensors(sc)
-    base = 0
-    for c, n, pix, G in zip(cams, npix, picks, Gs):
+    for v, (c, im, pix, G) in enumerate(zip(cams, imgs, picks, Gs)):
         t1 = time.time()
         gr, _, rec, _, rgba = oracle.adjoint_gradients(sc, c, G, pix=pix, return_records=True)
-        err = np.abs(img[base + pix] - rgba).max()
-        _flush(f"  view: oracle {time.time() - t1:.1f}s, colour err {err:.3e}, contributions {rec.cell.numel()}")
+        got = im.detach().reshape(-1, 4)[torch.as_tensor(pix, device="cuda")].cpu().numpy().astype(np.float64)
+        err = np.abs(got - rgba).max()
+        _flush(f"  view {v}: oracle {time.time() - t1:.1f}s, colour err {err:.3e}, "
+               f"contributions {rec.cell.numel()}")
         assert err <= 1e-4
         for f in PARAMS:
             g_ref[f] += gr[f].reshape(g_ref[f].shape)
-        base += n
     for f in PARAMS:
         scale = np.abs(g_ref[f]).max()
         e = np.abs(g_gpu[f] - g_ref[f]).max()
         _flush(f"  {f:10s} |g_ref|max {scale:.4e} err {e:.3e} rel {e / max(scale, 1e-30):.3e}")
         assert scale > 0 and e <= 1e-3 * scale, f
-    state.release()
+    scene.destroy()
