@@ -227,6 +227,7 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
   __shared__ float2 st_k[KD][KPAD];      // per record and site: softmax shift, dL/dw_k
   __shared__ float acc[NSUM + 1];
   __shared__ float4 facc[FMAX_B];
+  __shared__ double s_fr[12];            // the cell's face frame (wave-uniform)
 
   const int4 ch = chunks[blockIdx.x];
   const int ci = ch.x;
@@ -245,23 +246,23 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
   const float lam = lamv[ci];
   const float sigma = sigma_scale * softplus_b(lam);
   const float tau = tau_;
-  // float64 face frame (for the displacement chain)
-  // (wave-uniform: held in scalar registers)
-  const double dninv = uni(1.0 / sqrt((double)nrx * nrx + (double)nry * nry + (double)nrz * nrz));
-  const double dnx = uni(nrx * dninv), dny = uni(nry * dninv), dnz = uni(nrz * dninv);
-  const double dsg = uni(copysign(1.0, dnz));
-  double d1x, d1y, d1z, d2x, d2y, d2z;
-  const double oa = uni(-1.0 / (dsg + dnz));   // Duff et al. frame constant
-  {
-    const double a = oa;
+  // float64 face frame (for the displacement chain): n_hat, t1, t2 of
+  // Duff et al., the sign and frame constant, 1/|n|.  It is wave-uniform but
+  // float64 arithmetic runs on the vector unit, so it is kept in LDS and
+  // re-read where used rather than held in (and spilled from) vector
+  // registers across the record loop.
+  if (lane == 0) {
+    const double dninv = 1.0 / sqrt((double)nrx * nrx + (double)nry * nry + (double)nrz * nrz);
+    const double dnx = nrx * dninv, dny = nry * dninv, dnz = nrz * dninv;
+    const double dsg = copysign(1.0, dnz);
+    const double a = -1.0 / (dsg + dnz);
     const double b = dnx * dny * a;
-    d1x = uni(1.0 + dsg * dnx * dnx * a);
-    d1y = uni(dsg * b);
-    d1z = uni(-dsg * dnx);
-    d2x = uni(b);
-    d2y = uni(dsg + dny * dny * a);
-    d2z = uni(-dny);
+    s_fr[0] = dnx; s_fr[1] = dny; s_fr[2] = dnz;
+    s_fr[3] = 1.0 + dsg * dnx * dnx * a; s_fr[4] = dsg * b; s_fr[5] = -dsg * dnx;
+    s_fr[6] = b; s_fr[7] = dsg + dny * dny * a; s_fr[8] = -dny;
+    s_fr[9] = dsg; s_fr[10] = a; s_fr[11] = dninv;
   }
+  __syncthreads();
 
   // (site, axis) owned by this lane in the transposed phase
   const int km = lane >> 3, mm = lane & 7;
@@ -302,8 +303,13 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     // piece_geometry; the face frame, displacement and texture point in
     // float64: for rays nearly parallel to the face the derivatives with
     // respect to the normal are small differences of terms ~1/(d.n)^2.
-    const Local L = make_local(R, px, py, pz);
-    const double Dd = (double)rad * (double)rad - L.qq;
+    // the cell's site and radius pass an opaque copy, so that their float64
+    // conversions are made here rather than hoisted out of the loop (and
+    // spilled)
+    float cpx = px, cpy = py, cpz = pz, crad = rad;
+    asm volatile("" : "+s"(cpx), "+s"(cpy), "+s"(cpz), "+s"(crad));
+    const Local L = make_local(R, cpx, cpy, cpz);
+    const double Dd = (double)crad * (double)crad - L.qq;
     const float sq = sqrtf((float)fmax(Dd, 1e-30));
     const float4 pl0 = (b0 >= 0 && b0 < nf) ? plane[r0 + b0] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const float4 pl1 = (b1 >= 0 && b1 < nf) ? plane[r0 + b1] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -315,6 +321,12 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     const float s1 = (b1 == -1) ? sq : (pl1.w - (L.qx * pl1.x + L.qy * pl1.y + L.qz * pl1.z)) * frcp(a1);
     const double ddx = R.dx, ddy = R.dy, ddz = R.dz;
     const double qdx = L.dqx, qdy = L.dqy, qdz = L.dqz;
+    // (an opaque offset, so that the frame is read here, not hoisted)
+    int fo = 0;
+    asm volatile("" : "+v"(fo));
+    double dnx = s_fr[fo], dny = s_fr[fo + 1], dnz = s_fr[fo + 2];
+    double d1x = s_fr[fo + 3], d1y = s_fr[fo + 4], d1z = s_fr[fo + 5];
+    double d2x = s_fr[fo + 6], d2y = s_fr[fo + 7], d2z = s_fr[fo + 8];
     const double den = ddx * dnx + ddy * dny + ddz * dnz;
     const double qn = qdx * dnx + qdy * dny + qdz * dnz;
     const double qt1 = qdx * d1x + qdy * d1y + qdz * d1z;
@@ -444,6 +456,10 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     }
 
     // ---------------- frame: q.nhat, d.nhat, q.t1, d.t1, q.t2, d.t2 (float64)
+    asm volatile("" : "+v"(fo));
+    dnx = s_fr[fo]; dny = s_fr[fo + 1]; dnz = s_fr[fo + 2];
+    d1x = s_fr[fo + 3]; d1y = s_fr[fo + 4]; d1z = s_fr[fo + 5];
+    d2x = s_fr[fo + 6]; d2y = s_fr[fo + 7]; d2z = s_fr[fo + 8];
     float gqx = (float)(g_qn * dnx + g_qt1 * d1x + g_qt2 * d2x);
     float gqy = (float)(g_qn * dny + g_qt1 * d1y + g_qt2 * d2y);
     float gqz = (float)(g_qn * dnz + g_qt1 * d1z + g_qt2 * d2z);
@@ -451,7 +467,7 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     const double g1x = g_qt1 * qdx + g_dt1 * ddx, g1y = g_qt1 * qdy + g_dt1 * ddy, g1z = g_qt1 * qdz + g_dt1 * ddz;
     const double g2x = g_qt2 * qdx + g_dt2 * ddx, g2y = g_qt2 * qdy + g_dt2 * ddy, g2z = g_qt2 * qdz + g_dt2 * ddz;
     // orthonormal basis of Duff et al. (JCGT 2017), differentiated
-    const double sg = dsg;
+    const double sg = s_fr[fo + 9], oa = s_fr[fo + 10], dninv = s_fr[fo + 11];
     const double oa2 = oa * oa;
     double gnxd = gnx_h + g1x * (2.0 * sg * dnx * oa) + g1y * sg * dny * oa - g1z * sg + g2x * dny * oa;
     double gnyd = gny_h + g1y * sg * dnx * oa + g2x * dnx * oa + g2y * 2.0 * dny * oa - g2z;

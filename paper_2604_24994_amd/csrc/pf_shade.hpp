@@ -23,6 +23,19 @@ struct RayD {
   bool valid;
 };
 
+// Equidistant fisheye: camera-frame direction at polar angle th of the
+// pixel offset (ex, ey), rho = |(ex, ey)|.  Out of line, so that the float64
+// sine and cosine constants stay in this function instead of occupying
+// registers across the loops of the kernels that generate rays.
+__device__ __attribute__((noinline)) double3 fisheye_dir(double ex, double ey, double rho, double th) {
+  const double st = sin(th);
+  double3 d;
+  d.x = rho > 0.0 ? st * ex / rho : 0.0;
+  d.y = rho > 0.0 ? st * ey / rho : 0.0;
+  d.z = cos(th);
+  return d;
+}
+
 // Ray through pixel-centre coordinates (u, v).
 __device__ inline RayD make_ray(const pf_camera& c, double u, double v) {
   RayD r;
@@ -37,15 +50,10 @@ __device__ inline RayD make_ray(const pf_camera& c, double u, double v) {
     const double rho = sqrt(ex * ex + ey * ey);
     const double th = rho / (double)c.f_fish;
     r.valid = th <= (double)c.theta_max;
-    const double st = sin(th);
-    if (rho > 0.0) {
-      dcx = st * ex / rho;
-      dcy = st * ey / rho;
-    } else {
-      dcx = 0.0;
-      dcy = 0.0;
-    }
-    dcz = cos(th);
+    const double3 d = fisheye_dir(ex, ey, rho, th);
+    dcx = d.x;
+    dcy = d.y;
+    dcz = d.z;
   }
   const float* m = c.c2w;
   double wx = (double)m[0] * dcx + (double)m[1] * dcy + (double)m[2] * dcz;
