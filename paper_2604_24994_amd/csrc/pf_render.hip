@@ -600,8 +600,12 @@ __global__ void __launch_bounds__(256) k_start_final(const double* __restrict__ 
 // STORE: every contribution is also written as a record (as the store-mode
 // rasteriser does) with a one-record segment; rec_seg must be zeroed by the
 // caller (unused slots of the wave's segment blocks keep count 0).
+// Six waves per SIMD (at most 80 VGPRs): the walk is bound by the latency of
+// its per-step gathers, and occupancy hides it (100 Mrays/s at the three
+// waves that 136 unconstrained VGPRs allow, 125 at six).
 template <bool STORE>
-__global__ void __launch_bounds__(256) k_trace(ViewArgs v, SceneDev S, const int32_t* __restrict__ start,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6)))
+k_trace(ViewArgs v, SceneDev S, const int32_t* __restrict__ start,
                                                float t_min, int max_steps, float* __restrict__ rgba,
                                                unsigned long long* __restrict__ truncated, int view,
                                                int4* __restrict__ rec_ri, float4* __restrict__ rec_rf,
