@@ -38,8 +38,8 @@ struct pf_fwd_state {
 
 namespace {
 void free_state_mem(pf_fwd_state* s) {
-  void* ptrs[] = {s->st.rec.ri,      s->st.rec.rf,  s->st.rec.rt,   s->st.rec.head,
-                  s->st.rec.counter, s->st.rec.seg, s->st.cams_dev};
+  void* ptrs[] = {s->st.rec.ri,      s->st.rec.rf,  s->st.rec.rt,    s->st.rec.head,
+                  s->st.rec.counter, s->st.rec.seg, s->st.rec.wtail, s->st.cams_dev};
   for (void* q : ptrs)
     if (q) pf::pool_free(q, s->stream);
   s->st.rec = pf::RecBuf{};
@@ -279,6 +279,8 @@ pf_status fill_records(pf_fwd_state* fs, float* rgba, unsigned long long* trunc_
   const int64_t npix = fs->st.npix;
   hipError_t e = pf::pool_alloc((void**)&fs->st.rec.head, sizeof(int32_t) * npix, s);
   if (e == hipSuccess) e = pf::pool_alloc((void**)&fs->st.rec.counter, 3 * sizeof(unsigned long long), s);
+  // the raster lists each wave's last segment block (4 waves per tile)
+  if (e == hipSuccess && fs->kind == 0) e = pf::pool_alloc((void**)&fs->st.rec.wtail, sizeof(int2) * 4 * fs->st.ntiles, s);
   if (e != hipSuccess) {
     pf::set_error(std::string(who) + ": " + hipGetErrorString(e));
     return e == hipErrorOutOfMemory ? PF_ERR_OOM : PF_ERR_HIP;
@@ -293,6 +295,9 @@ pf_status fill_records(pf_fwd_state* fs, float* rgba, unsigned long long* trunc_
   int64_t seg_cap = coarse((int64_t)(spp * (double)npix) + 4096, 1 << 20);
   if (fs->kind == 1) seg_cap = std::max(seg_cap, cap);   // one segment per record on the walk
   for (int attempt = 0; attempt < 2; ++attempt) {
+    // record and segment indices are stored as 32-bit integers
+    cap = std::min<int64_t>(cap, INT32_MAX - 1);
+    seg_cap = std::min<int64_t>(seg_cap, INT32_MAX - 1);
     fs->st.rec.cap = cap;
     fs->st.rec.seg_cap = seg_cap;
     e = pf::pool_alloc((void**)&fs->st.rec.ri, sizeof(int4) * cap, s);
@@ -321,8 +326,8 @@ pf_status fill_records(pf_fwd_state* fs, float* rgba, unsigned long long* trunc_
       pf::set_error(std::string(who) + ": " + hipGetErrorString(e));
       return PF_ERR_HIP;
     }
-    if (used[0] > (unsigned long long)INT32_MAX)
-      return invalid(std::string(who) + ": more than 2^31 - 1 contributions in one call; render fewer views");
+    if (used[0] >= (unsigned long long)INT32_MAX || used[1] >= (unsigned long long)INT32_MAX)
+      return invalid(std::string(who) + ": more than 2^31 - 2 contributions or segments in one call; render fewer views");
     if (fs->kind == 0) {
       scene->s.rec_per_pixel = 1.05 * (double)used[0] / (double)npix;
       scene->s.seg_per_pixel = 1.05 * (double)used[1] / (double)npix;

@@ -111,11 +111,95 @@ __global__ void __launch_bounds__(256) k_suffix(const int32_t* __restrict__ head
   }
 }
 
+// The same pass over a raster's records without the chains: each wave walks
+// the segments its raster wave appended, last block first and, in a block,
+// last segment first, so that every pixel of the wave meets its records back
+// to front as along its chain (the arithmetic is the same, in the same
+// order).  A segment's records are contiguous and its cell is uniform: the
+// loads and stores are coalesced and no record waits for the one behind it.
+__global__ void __launch_bounds__(256) k_suffix_seg(const int4* __restrict__ seg, const int2* __restrict__ wtail,
+                                                    int ncam, const float* __restrict__ d_rgba,
+                                                    float4* __restrict__ rf, float* __restrict__ rt,
+                                                    const pf_camera* __restrict__ cams, const float4* __restrict__ nrm,
+                                                    float lambda_n, double* __restrict__ normal_loss,
+                                                    const float* __restrict__ pix_err, float* __restrict__ rte) {
+  int64_t tile = blockIdx.x, base = 0;
+  int v = 0;
+  for (; v < ncam - 1; ++v) {
+    const int nt = ((cams[v].width + TILE - 1) / TILE) * ((cams[v].height + TILE - 1) / TILE);
+    if (tile < nt) break;
+    tile -= nt;
+    base += (int64_t)cams[v].width * cams[v].height;
+  }
+  const int W = cams[v].width, H = cams[v].height, tiles_x = (W + TILE - 1) / TILE;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int px = (int)(tile % tiles_x) * TILE + (w & 1) * 8 + (lane & 7);
+  const int py = (int)(tile / tiles_x) * TILE + (w >> 1) * 8 + (lane >> 3);
+  const bool inside = px < W && py < H;
+  const int64_t i = base + (int64_t)py * W + px;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const bool nl = lambda_n != 0.0f || normal_loss;
+  float e = 0.0f, gr = 0.0f, gg = 0.0f, gb = 0.0f, ga = 0.0f, fx = 0.0f, fy = 0.0f, fz = 0.0f;
+  if (inside) {
+    e = pix_err ? pix_err[i] : 0.0f;
+    gr = d_rgba[4 * i];
+    gg = d_rgba[4 * i + 1];
+    gb = d_rgba[4 * i + 2];
+    ga = d_rgba[4 * i + 3];
+    if (nl) {
+      const RayD R = make_ray(cams[v], px + 0.5, py + 0.5);
+      fx = R.fx;
+      fy = R.fy;
+      fz = R.fz;
+    }
+  }
+  float cr = 0.0f, cg = 0.0f, cb = 0.0f, ab = 0.0f, nb = 0.0f;
+  double lpix = 0.0;   // this pixel's sum of T a max(n.d, 0)^2
+  const int2 tl = wtail[(int64_t)blockIdx.x * 4 + w];
+  int blk = tl.x, top = tl.y;   // the wave's last block and the slots used in it
+  while (blk >= 0) {
+    for (int j = top - 1; j >= 1; --j) {   // slot 0 is the block's header
+      const int4 g = seg[(int64_t)blk + j];
+      const uint64_t m = (uint64_t)(uint32_t)g.z | ((uint64_t)(uint32_t)g.w << 32);
+      if (!((m >> lane) & 1ull)) continue;
+      const int64_t k = (int64_t)g.y + __popcll(m & lt);
+      const float4 f = rf[k];
+      const float T = rt[k];
+      const float a = f.x;
+      float nu = 0.0f;
+      if (nl) {
+        const float4 nv = nrm[g.x];
+        const float c = fmaxf(nv.x * fx + nv.y * fy + nv.z * fz, 0.0f);
+        nu = c * c;
+      }
+      const float g_alpha = T * (gr * (f.y - cr) + gg * (f.z - cg) + gb * (f.w - cb) + ga * (1.0f - ab) +
+                                 lambda_n * (nu - nb));
+      const float ta = T * a;
+      rf[k] = make_float4(g_alpha, ta * gr, ta * gg, ta * gb);
+      rt[k] = ta;
+      if (rte) rte[k] = ta * e;
+      lpix += (double)ta * (double)nu;
+      cr = a * f.y + (1.0f - a) * cr;
+      cg = a * f.z + (1.0f - a) * cg;
+      cb = a * f.w + (1.0f - a) * cb;
+      ab = a + (1.0f - a) * ab;
+      nb = a * nu + (1.0f - a) * nb;
+    }
+    blk = seg[blk].y;   // the header's link to the wave's previous (full) block
+    top = SEG_BLOCK;
+  }
+  if (normal_loss) {
+    for (int o = 32; o > 0; o >>= 1) lpix += __shfl_xor(lpix, o, 64);
+    if ((threadIdx.x & 63) == 0 && lpix != 0.0) atomicAdd(normal_loss, lpix);
+  }
+}
+
 __global__ void k_seg_hist(const int4* __restrict__ seg, int64_t nseg, uint32_t* __restrict__ cnt) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nseg) {
     const int4 g = seg[i];
-    if (g.z > 0) atomicAdd(&cnt[g.x], (uint32_t)g.z);
+    const int c = seg_count(g);
+    if (c > 0) atomicAdd(&cnt[g.x], (uint32_t)c);
   }
 }
 
@@ -124,9 +208,10 @@ __global__ void k_seg_scatter(const int4* __restrict__ seg, int64_t nseg, const 
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nseg) return;
   const int4 g = seg[i];
-  if (g.z <= 0) return;   // unused slot of a segment block
-  const uint32_t at = off[g.x] + atomicAdd(&fill[g.x], (uint32_t)g.z);
-  for (int j = 0; j < g.z; ++j) order[at + j] = g.y + j;
+  const int c = seg_count(g);
+  if (c == 0) return;   // block header or unused slot
+  const uint32_t at = off[g.x] + atomicAdd(&fill[g.x], (uint32_t)c);
+  for (int j = 0; j < c; ++j) order[at + j] = g.y + j;
 }
 
 __global__ void k_chunk_count(const uint32_t* __restrict__ cnt, int64_t n, uint32_t* __restrict__ nch) {
@@ -651,9 +736,14 @@ pf_status backward_impl(const Scene& sc, const BwdState& st, const float* d_rgba
   if (want_err) PF_HIP_TRY(rte.alloc(st.rec.cap));
   {
     ProfScope ps("k_suffix", s);
-    k_suffix<<<gp, 256, 0, s>>>(st.rec.head, st.ncam, d_rgba, st.rec.ri, st.rec.rf, st.rec.rt, st.cams_dev, sc.nrm,
-                                opt.lambda_normal, opt.normal_loss, want_err ? opt.pixel_error : nullptr,
-                                want_err ? rte.p : nullptr);
+    if (st.rec.wtail)   // raster records: walk the waves' segments
+      k_suffix_seg<<<gp, 256, 0, s>>>(st.rec.seg, st.rec.wtail, st.ncam, d_rgba, st.rec.rf, st.rec.rt, st.cams_dev,
+                                      sc.nrm, opt.lambda_normal, opt.normal_loss,
+                                      want_err ? opt.pixel_error : nullptr, want_err ? rte.p : nullptr);
+    else                // ray-walk records: follow the per-pixel chains
+      k_suffix<<<gp, 256, 0, s>>>(st.rec.head, st.ncam, d_rgba, st.rec.ri, st.rec.rf, st.rec.rt, st.cams_dev, sc.nrm,
+                                  opt.lambda_normal, opt.normal_loss, want_err ? opt.pixel_error : nullptr,
+                                  want_err ? rte.p : nullptr);
   }
   PF_HIP_TRY(hipGetLastError());
   Buf<uint32_t> cnt(s), off(s), fill(s), nch(s), choff(s);

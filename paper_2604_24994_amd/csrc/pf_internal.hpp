@@ -72,9 +72,21 @@ struct Scene {
 //   rt = transmittance in front of the contribution
 // bind: -1 sphere, -2 ray start, f >= 0 raster face index of the cell.
 // Every wave-wide append of one cell's records is also listed as a segment
-// (cell, first record, count, 0): the records of a segment are contiguous
-// and belong to one cell, which lets the backward group records by cell with
-// one atomic per segment.
+// (cell, first record, lane mask low 32 bits, high 32 bits): the records of
+// a segment are contiguous, belong to one cell and, in lane order, to the
+// lanes of the mask (count = popcount of the mask), which lets the backward
+// group records by cell with one atomic per segment.  A wave reserves its
+// segment slots in blocks; the first slot of a block is a header
+// (-1, previous block of the wave or -1, 0, 0) with an empty mask, and the
+// raster records each wave's last block, so that the backward can walk a
+// wave's segments in reverse append order (back to front for every pixel of
+// the wave).  The walk lists one-record segments (mask 1), without headers.
+// Segment slots a raster wave reserves at a time (header included).
+constexpr int SEG_BLOCK = 32;
+
+// Records listed by a segment (0 for headers and unused slots).
+__device__ inline int seg_count(const int4& g) { return __popc((uint32_t)g.z) + __popc((uint32_t)g.w); }
+
 struct RecBuf {
   int4* ri = nullptr;
   float4* rf = nullptr;
@@ -82,6 +94,7 @@ struct RecBuf {
   int32_t* head = nullptr;            // [pixels of all views] last record or -1
   unsigned long long* counter = nullptr;   // [2]: records, segments appended
   int4* seg = nullptr;
+  int2* wtail = nullptr;              // raster: [4 x tiles] (last segment block or -1, slots used in it)
   int64_t cap = 0;                    // record capacity
   int64_t seg_cap = 0;                // segment capacity
 };

@@ -357,7 +357,7 @@ struct SceneDev {
 
 constexpr int RB = 256;     // tile-list entries staged in LDS per batch
 constexpr int RBLK = 256;   // record slots reserved per wave at a time
-constexpr int SBLK = 32;    // segment slots reserved per wave at a time
+constexpr int SBLK = SEG_BLOCK;   // segment slots reserved per wave at a time
 
 __device__ inline unsigned long long bcast64(unsigned long long x) {
   const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)x);
@@ -381,7 +381,8 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
                                                 float4* __restrict__ rec_rf, float* __restrict__ rec_rt,
                                                 int32_t* __restrict__ rec_head,
                                                 unsigned long long* __restrict__ rec_counter,
-                                                int4* __restrict__ rec_seg, int64_t rec_cap, int64_t seg_cap) {
+                                                int4* __restrict__ rec_seg, int2* __restrict__ rec_wtail,
+                                                int64_t tile0, int64_t rec_cap, int64_t seg_cap) {
   // the tile's sorted cells are staged RB at a time: list entry and the cell
   // record fields every lane needs, loaded by the whole workgroup at once
   __shared__ int s_ci[RB];
@@ -415,6 +416,7 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
   const int pix = py * v.cam.width + px;
   const uint32_t e0 = tile_off[blockIdx.x], e1 = tile_off[blockIdx.x + 1];
   long long rblk = 0, sblk = 0;   // the wave's current record / segment block
+  long long cblk = -1;            // first slot (header) of the wave's current segment block
   int rleft = 0, sleft = 0;
   for (uint32_t b0 = e0; b0 < e1; b0 += RB) {
     {
@@ -464,15 +466,20 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
           if (sleft == 0) {
             unsigned long long bk = 0;
             if (lane == 0) bk = atomicAdd(&rec_counter[1], (unsigned long long)SBLK);
-            sblk = (long long)bcast64(bk);
-            sleft = SBLK;
+            const long long nb = (long long)bcast64(bk);
+            // the block's header links it to the wave's previous block
+            if (lane == 0 && nb < seg_cap) rec_seg[nb] = make_int4(-1, (int)cblk, 0, 0);
+            cblk = nb;
+            sblk = nb + 1;
+            sleft = SBLK - 1;
           }
           const long long base = rblk, sg = sblk;
           rblk += cnt;
           rleft -= cnt;
           sblk += 1;
           sleft -= 1;
-          if (lane == 0 && sg < seg_cap && base + cnt <= rec_cap) rec_seg[sg] = make_int4(ci, (int)base, cnt, 0);
+          if (lane == 0 && sg < seg_cap && base + cnt <= rec_cap)
+            rec_seg[sg] = make_int4(ci, (int)base, (int)(uint32_t)m, (int)(uint32_t)(m >> 32));
           if (contrib) {
             const long long slot = base + __popcll(m & lt);
             if (slot < rec_cap) {
@@ -509,9 +516,10 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
     if constexpr (STORE) rec_head[pix_base + pix] = head;
   }
   if constexpr (STORE) {
-    // unused slots of the last segment block are marked empty (count 0)
+    // unused slots of the last segment block are marked empty (mask 0)
     for (int j = lane; j < sleft; j += 64)
       if (sblk + j < seg_cap) rec_seg[sblk + j] = make_int4(0, 0, 0, 0);
+    if (lane == 0) rec_wtail[(tile0 + blockIdx.x) * 4 + wave] = make_int2((int)cblk, SBLK - sleft);
   }
 }
 
@@ -522,7 +530,7 @@ __global__ void __launch_bounds__(256) k_seg_total(const int4* __restrict__ seg,
   __shared__ unsigned long long part[4];
   unsigned long long acc = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nseg; i += (int64_t)gridDim.x * blockDim.x)
-    acc += (unsigned long long)seg[i].z;
+    acc += (unsigned long long)seg_count(seg[i]);
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
   __syncthreads();
@@ -673,7 +681,7 @@ k_trace(ViewArgs v, SceneDev S, const int32_t* __restrict__ start,
               rec_rf[slot] = make_float4(P.alpha, r, gg, b);
               rec_rt[slot] = T;
               head = (int)slot;
-              if (sg < seg_cap) rec_seg[sg] = make_int4(cell, (int)slot, 1, 0);
+              if (sg < seg_cap) rec_seg[sg] = make_int4(cell, (int)slot, 1, 0);   // mask 1: one record
             }
           }
           rblk += cnt;
@@ -774,7 +782,7 @@ pf_status raster_views(Scene& sc, const pf_camera* cams, int ncam, float t_min, 
   const int64_t n = sc.n;
   // views are processed in groups so that the per-(view, cell) scan fits 32 bits
   const int group = (int)std::max<int64_t>(1, std::min<int64_t>(ncam, ((int64_t)1 << 28) / n));
-  int64_t pix_done = 0;
+  int64_t pix_done = 0, tiles_done = 0;
   for (int c0 = 0; c0 < ncam; c0 += group) {
     const int nv = std::min(group, ncam - c0);
     std::vector<ViewDev> hv(nv);
@@ -854,14 +862,16 @@ pf_status raster_views(Scene& sc, const pf_camera* cams, int ncam, float t_min, 
       if (rec) {
         const RecBuf& rb = *rec;
         k_raster<true><<<(unsigned)ntiles, 256, 0, s>>>(views.p, nv, scene_dev(sc), sorted.p, toff.p, t_min, rgba,
-                                                        rb.ri, rb.rf, rb.rt, rb.head, rb.counter, rb.seg, rb.cap,
-                                                        rb.seg_cap);
+                                                        rb.ri, rb.rf, rb.rt, rb.head, rb.counter, rb.seg, rb.wtail,
+                                                        tiles_done, rb.cap, rb.seg_cap);
       } else {
         k_raster<false><<<(unsigned)ntiles, 256, 0, s>>>(views.p, nv, scene_dev(sc), sorted.p, toff.p, t_min, rgba,
-                                                         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0);
+                                                         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                                         nullptr, 0, 0, 0);
       }
     }
     PF_HIP_TRY(hipGetLastError());
+    tiles_done += ntiles;
   }
   return PF_OK;
 }
