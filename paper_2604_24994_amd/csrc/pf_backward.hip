@@ -9,7 +9,9 @@
 //                 dL/dc_k = T_k a_k gC                      (Sec. 3.1 sum)
 //                 plus, with the normal loss, the same for the scalar
 //                 channel max(n.d, 0)^2 weighted by lambda_normal; the
-//                 record's T becomes the contribution T a
+//                 record's T becomes the contribution T a.  Raster records:
+//                 k_suffix_seg walks each wave's segments in reverse append
+//                 order; walk records: k_suffix follows the pixel chains
 //   k_seg_hist /  records grouped by cell through the forward's segment list
 //   k_seg_scatter (one atomic per segment of <= 64 contiguous records)
 //   k_bwd_cell    one wave per chunk of a cell's records, 64 records at a
