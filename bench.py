@@ -50,11 +50,14 @@ FLOPS_BWD_PER_CONTRIB = 5100
 # for the kernel sources with these hashes; otherwise the bench reports null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC = {
-    "k_bwd_cell": {"fetch_kib": 8375739.8, "write_kib": 5372747.6,
-                   "sources": {"pf_backward.hip": "1b733f12ac4e814a", "pf_shade.hpp": "116bd29c86c7c2be"}},
-    "k_raster_store": {"fetch_kib": 15672921.6, "write_kib": 11259882.5,
-                       "sources": {"pf_render.hip": "959a93f2bc46f6f7", "pf_shade.hpp": "116bd29c86c7c2be"}},
-    "k_clip": {"fetch_kib": 409405.6, "write_kib": 180394.4, "sources": {"pf_build.hip": "60ddab952277c61e"}},
+    "k_bwd_cell": {"fetch_kib": 8375527.2, "write_kib": 5371955.5,
+                   "sources": {"pf_backward.hip": "e13c95196636adce", "pf_shade.hpp": "116bd29c86c7c2be",
+                               "pf_internal.hpp": "95396ae9bc7369b2"}},
+    "k_raster_store": {"fetch_kib": 15637422.8, "write_kib": 11282241.8,
+                       "sources": {"pf_render.hip": "08c4b47e1d54f880", "pf_shade.hpp": "116bd29c86c7c2be",
+                                   "pf_internal.hpp": "95396ae9bc7369b2"}},
+    "k_clip": {"fetch_kib": 409609.8, "write_kib": 180470.2,
+               "sources": {"pf_build.hip": "60ddab952277c61e", "pf_internal.hpp": "95396ae9bc7369b2"}},
 }
 
 
