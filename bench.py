@@ -88,7 +88,7 @@ def parse():
     ap.add_argument("--mode", choices=["train", "fwd"], default="train")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--cpu-rays", type=int, default=4, help="oracle sample size for the CPU baseline")
+    ap.add_argument("--cpu-rays", type=int, default=8, help="oracle sample size for the CPU baseline (about 2 s per ray)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-densify", action="store_true", help="skip the densify/prune side measurement")
     ap.add_argument("--steiner-cand", type=int, default=-1,
