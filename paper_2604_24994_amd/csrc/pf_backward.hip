@@ -269,6 +269,23 @@ __device__ inline double rcp_d(double x) {
   return r;
 }
 
+// Length and reciprocal length of a 2-vector from its squared length x2
+// (float64): hardware reciprocal square root refined by two Newton steps
+// (r <- r (3 - x2 r^2) / 2), then |v| = x2 / |v|.  Both are 0 for x2 = 0.
+__device__ inline void len_rlen(double x2, double& len, double& rlen) {
+  if (x2 > 0.0) {
+    double r = __builtin_amdgcn_rsq(x2);
+    const double hx = 0.5 * x2;
+    r = r * fma(-hx * r, r, 1.5);
+    r = r * fma(-hx * r, r, 1.5);
+    rlen = r;
+    len = x2 * r;
+  } else {
+    rlen = 0.0;
+    len = 0.0;
+  }
+}
+
 // Softmax backward of the soft-Voronoi weights at texture point u (float64).
 // With z_k = -tau (|u - s_k| - |u|) and ge_k = dL/dz_k, accumulates dL/du
 // into (gux, guy) and the wave's sum of dL/ds_k into acc.  d/du of the shifted
@@ -277,14 +294,14 @@ __device__ inline double rcp_d(double x) {
 // is far from the sites (grazing rays).
 __device__ inline void sv_backward(const float* __restrict__ tx, double ux, double uy, const double* ge, double& gux,
                                    double& guy, float* acc, bool valid) {
-  const double un = sqrt(ux * ux + uy * uy);
-  const double iun = un > 0.0 ? rcp_d(un) : 0.0;
+  double un, iun;
+  len_rlen(ux * ux + uy * uy, un, iun);
 #pragma unroll
   for (int k = 0; k < KD; ++k) {
     const double sx = tx[k * TEXW], sy = tx[k * TEXW + 1];
     const double ex = ux - sx, ey = uy - sy;
-    const double dist = sqrt(ex * ex + ey * ey);
-    const double rd = dist > 0.0 ? rcp_d(dist) : 0.0;
+    double dist, rd;
+    len_rlen(ex * ex + ey * ey, dist, rd);
     double lx, ly;
     if (un > 0.0 && dist > 0.0) {
       const double e = (sx * sx + sy * sy - 2.0 * (ux * sx + uy * sy)) * rcp_d(dist + un);   // |u - s| - |u|
