@@ -500,9 +500,10 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
         mx = fmaxf(mx, lg[m]);
       }
       float sum = 0.0f, sr = 0.0f, sg = 0.0f, sb = 0.0f;
+      const float mxl = mx * LOG2E_F;
 #pragma unroll
       for (int m = 0; m < MA; ++m) {
-        const float e = __expf(lg[m] - mx);
+        const float e = exp_shifted(lg[m], mxl);
         sum += e;
         sr += e * t[3 + 3 * MA + 3 * m];
         sg += e * t[4 + 3 * MA + 3 * m];

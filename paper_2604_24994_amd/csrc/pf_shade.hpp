@@ -74,6 +74,14 @@ __device__ inline RayD make_ray(const pf_camera& c, double u, double v) {
 
 __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+constexpr float LOG2E_F = 1.4426950408889634f;
+
+// exp(x - shift) as one fused multiply-add and the hardware exp2, with
+// shift_l2 = shift * log2(e) formed once per softmax.
+__device__ inline float exp_shifted(float x, float shift_l2) {
+  return __builtin_amdgcn_exp2f(fmaf(x, LOG2E_F, -shift_l2));
+}
+
 // Local frame of the ray at a cell: q (float), beta = s at t = 0, and the
 // squared closest-approach distance in float64.
 struct Local {
@@ -134,9 +142,10 @@ __device__ inline void sv_weights(const float* __restrict__ tx, float ux, float 
     mx = fmaxf(mx, w[k]);
   }
   float sum = 0.0f;
+  const float mxl = mx * LOG2E_F;
 #pragma unroll
   for (int k = 0; k < KD; ++k) {
-    w[k] = __expf(w[k] - mx);
+    w[k] = exp_shifted(w[k], mxl);
     sum += w[k];
   }
   const float inv = frcp(sum);
@@ -255,9 +264,10 @@ __device__ inline void radiance(const float* __restrict__ tx, const float* __res
       mx = fmaxf(mx, lg[m]);
     }
     float sum = 0.0f, sr = 0.0f, sg = 0.0f, sb = 0.0f;
+    const float mxl = mx * LOG2E_F;
 #pragma unroll
     for (int m = 0; m < MA; ++m) {
-      const float e = __expf(lg[m] - mx);
+      const float e = exp_shifted(lg[m], mxl);
       sum += e;
       sr += e * t[3 + 3 * MA + 3 * m];
       sg += e * t[4 + 3 * MA + 3 * m];
