@@ -180,19 +180,24 @@ __device__ inline Piece piece_geometry(const RayD& R, const Local& L, float r, c
   float s0 = -sq, s1 = sq;
   int b0 = -1, b1 = -1;
   const float fx = R.fx, fy = R.fy, fz = R.fz;
+  // exit (a > 0) and entry (a < 0) bounds by selects rather than branches;
+  // a face parallel to the ray (a = 0) empties the interval when the ray
+  // lies on its outer side
+  // (the next face is loaded while this one is tested)
+  float4 nxt = nfaces > 0 ? faces[0] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   for (int f = 0; f < nfaces; ++f) {
-    const float4 pl = faces[f];
+    const float4 pl = nxt;
+    if (f + 1 < nfaces) nxt = faces[f + 1];
     const float a = fx * pl.x + fy * pl.y + fz * pl.z;
     const float bb = pl.w - (L.qx * pl.x + L.qy * pl.y + L.qz * pl.z);
-    if (a > 0.0f) {
-      const float s = bb * frcp(a);
-      if (s < s1) { s1 = s; b1 = f; }
-    } else if (a < 0.0f) {
-      const float s = bb * frcp(a);
-      if (s > s0) { s0 = s; b0 = f; }
-    } else if (bb < 0.0f) {
-      s1 = -INFINITY;
-    }
+    const float s = bb * frcp(a);
+    const bool out = a > 0.0f && s < s1;
+    const bool in = a < 0.0f && s > s0;
+    s1 = out ? s : s1;
+    b1 = out ? f : b1;
+    s0 = in ? s : s0;
+    b0 = in ? f : b0;
+    s1 = (a == 0.0f && bb < 0.0f) ? -INFINITY : s1;
   }
   if (L.beta > s0) { s0 = L.beta; b0 = -2; }
   P.s0 = s0;
