@@ -113,7 +113,7 @@ __device__ inline Local make_local(const RayD& R, float px, float py, float pz) 
 __device__ inline void onb(float nx, float ny, float nz, float& t1x, float& t1y, float& t1z, float& t2x,
                            float& t2y, float& t2z) {
   const float sign = copysignf(1.0f, nz);
-  const float a = -1.0f / (sign + nz);
+  const float a = -frcp(sign + nz);   // |sign + nz| >= 1
   const float b = nx * ny * a;
   t1x = 1.0f + sign * nx * nx * a;
   t1y = sign * b;
@@ -218,7 +218,7 @@ __device__ inline Piece piece_geometry(const RayD& R, const Local& L, float r, c
   P.den = den;
   float j0 = s0, j1 = s1;
   if (den != 0.0f) {
-    const float idn = 1.0f / den;
+    const float idn = frcp(den);
     const float sbar = -qn * idn;
     float w[KD];
     sv_weights(tx, qt1 + sbar * dt1, qt2 + sbar * dt2, tau, w);
