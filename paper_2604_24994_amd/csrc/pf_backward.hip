@@ -414,7 +414,7 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     asm volatile("" : "+s"(cpx), "+s"(cpy), "+s"(cpz), "+s"(crad));
     const Local L = make_local(R, cpx, cpy, cpz);
     const double Dd = (double)crad * (double)crad - L.qq;
-    const float sq = sqrtf((float)fmax(Dd, 1e-30));
+    const float sq = fsqrt((float)fmax(Dd, 1e-30));
     const float4 pl0 = (b0 >= 0 && b0 < nf) ? plane[r0 + b0] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const float4 pl1 = (b1 >= 0 && b1 < nf) ? plane[r0 + b1] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const float a0 = fx * pl0.x + fy * pl0.y + fz * pl0.z;

@@ -5,8 +5,9 @@
 // Numerics: the ray is generated in float64 and, per cell, re-expressed in
 // the cell's local frame in float64: q = closest-approach offset from p_i,
 // s = t - t_closest, so that x(t) - p_i = q + s d.  All lengths below are
-// then small numbers near the cell, computed in float32 (IEEE division is
-// replaced by the hardware reciprocal, <= 1 ulp).  The sphere discriminant is
+// then small numbers near the cell, computed in float32 (IEEE division and
+// square root are replaced by the hardware reciprocal and square root,
+// <= 1 ulp).  The sphere discriminant is
 // formed in float64 (it cancels near tangency).
 #pragma once
 
@@ -73,6 +74,9 @@ __device__ inline RayD make_ray(const pf_camera& c, double u, double v) {
 }
 
 __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// Hardware square root (<= 1 ulp; the correctly rounded expansion costs a
+// dozen instructions).
+__device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 constexpr float LOG2E_F = 1.4426950408889634f;
 
@@ -128,13 +132,13 @@ __device__ inline void onb(float nx, float ny, float nz, float& t1x, float& t1y,
 //   |u - s_k| - |u| = (|s_k|^2 - 2 u.s_k) / (|u - s_k| + |u|),
 // which keeps them accurate when u is far from the sites (grazing rays).
 __device__ inline void sv_weights(const float* __restrict__ tx, float ux, float uy, float tau, float* w) {
-  const float un = sqrtf(ux * ux + uy * uy);
+  const float un = fsqrt(ux * ux + uy * uy);
   float mx = -INFINITY;
 #pragma unroll
   for (int k = 0; k < KD; ++k) {
     const float sx = tx[k * TEXW + 0], sy = tx[k * TEXW + 1];
     const float ex = ux - sx, ey = uy - sy;
-    const float dist = sqrtf(ex * ex + ey * ey);
+    const float dist = fsqrt(ex * ex + ey * ey);
     const float num = sx * sx + sy * sy - 2.0f * (ux * sx + uy * sy);
     const float den = dist + un;
     const float e = den > 0.0f ? num * frcp(den) : 0.0f;
@@ -176,7 +180,7 @@ __device__ inline Piece piece_geometry(const RayD& R, const Local& L, float r, c
   P.s0 = 1.0f;
   P.s1 = 0.0f;
   if (D <= 0.0) return P;
-  const float sq = sqrtf((float)D);
+  const float sq = fsqrt((float)D);
   float s0 = -sq, s1 = sq;
   int b0 = -1, b1 = -1;
   const float fx = R.fx, fy = R.fy, fz = R.fz;
