@@ -476,7 +476,7 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     const float om = 1.0f - alpha;
     const float g_ell = (ell > 0.0f) ? g_alpha * sigma * om : 0.0f;
     const float g_sigma = g_alpha * ell * om;
-    const float g_lam = g_sigma * sigma_scale / (1.0f + __expf(-lam));
+    const float g_lam = g_sigma * sigma_scale * frcp(1.0f + __expf(-lam));
     float g_s0 = 0.0f, g_s1 = 0.0f;
     double g_sx = 0.0;
     if (nzden || qn < 0.0) {
@@ -600,7 +600,7 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     auto end_grad = [&](int b, const float4& pl, float s, float a, float ge, bool upper) {
       if (ge == 0.0f) return;
       if (b == -1) {                       // s = +-sqrt(r^2 - |q|^2)
-        const float inv = 1.0f / sq;
+        const float inv = frcp(sq);
         const float sgn = upper ? 1.0f : -1.0f;
         gqx -= sgn * ge * L.qx * inv;
         gqy -= sgn * ge * L.qy * inv;
@@ -609,7 +609,7 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
       } else if (b == -2) {                // s = beta (ray start)
         g_beta += ge;
       } else if (b < nf) {                 // s = (h - q.m)/(d.m), neighbour face
-        const float ia = 1.0f / a;
+        const float ia = frcp(a);
         gqx -= ge * pl.x * ia;
         gqy -= ge * pl.y * ia;
         gqz -= ge * pl.z * ia;

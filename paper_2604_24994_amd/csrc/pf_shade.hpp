@@ -60,7 +60,11 @@ __device__ inline RayD make_ray(const pf_camera& c, double u, double v) {
   double wx = (double)m[0] * dcx + (double)m[1] * dcy + (double)m[2] * dcz;
   double wy = (double)m[4] * dcx + (double)m[5] * dcy + (double)m[6] * dcz;
   double wz = (double)m[8] * dcx + (double)m[9] * dcy + (double)m[10] * dcz;
-  const double inv = 1.0 / sqrt(wx * wx + wy * wy + wz * wz);
+  // 1/|w|: hardware reciprocal square root refined by two Newton steps
+  const double w2 = wx * wx + wy * wy + wz * wz;
+  double inv = __builtin_amdgcn_rsq(w2);
+  inv = inv * fma(-0.5 * w2 * inv, inv, 1.5);
+  inv = inv * fma(-0.5 * w2 * inv, inv, 1.5);
   r.dx = wx * inv;
   r.dy = wy * inv;
   r.dz = wz * inv;
