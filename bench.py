@@ -50,13 +50,13 @@ FLOPS_BWD_PER_CONTRIB = 5100
 # for the kernel sources with these hashes; otherwise the bench reports null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC = {
-    "k_bwd_cell": {"fetch_kib": 8375527.2, "write_kib": 5371955.5,
-                   "sources": {"pf_backward.hip": "e13c95196636adce", "pf_shade.hpp": "116bd29c86c7c2be",
+    "k_bwd_cell": {"fetch_kib": 8209004.9, "write_kib": 4483412.9,
+                   "sources": {"pf_backward.hip": "458b6967458821ba", "pf_shade.hpp": "a630fdb381c7dae7",
                                "pf_internal.hpp": "95396ae9bc7369b2"}},
-    "k_raster_store": {"fetch_kib": 15637422.8, "write_kib": 11282241.8,
-                       "sources": {"pf_render.hip": "08c4b47e1d54f880", "pf_shade.hpp": "116bd29c86c7c2be",
+    "k_raster_store": {"fetch_kib": 16565845.6, "write_kib": 11283653.3,
+                       "sources": {"pf_render.hip": "08c4b47e1d54f880", "pf_shade.hpp": "a630fdb381c7dae7",
                                    "pf_internal.hpp": "95396ae9bc7369b2"}},
-    "k_clip": {"fetch_kib": 409609.8, "write_kib": 180470.2,
+    "k_clip": {"fetch_kib": 409618.1, "write_kib": 180464.1,
                "sources": {"pf_build.hip": "60ddab952277c61e", "pf_internal.hpp": "95396ae9bc7369b2"}},
 }
 
