@@ -562,7 +562,8 @@ pf_status pf_query_workspace(const pf_scene* scene, const pf_camera* cams, int32
   // render: per (view, cell) key, count, offset; pairs (tile, value, sorted
   // value); per tile counts and offsets; the image
   double b = 12.0 * n * ncam + 20.0 * ppc * n * ncam + 12.0 * ntiles + 16.0 * npix;
-  if (what >= 1) b += 36.0 * rpp * npix + 16.0 * spp * npix + 4.0 * npix;   // store-mode state
+  // store-mode state: records, segments, per-pixel heads, per-wave segment tails
+  if (what >= 1) b += 36.0 * rpp * npix + 16.0 * spp * npix + 4.0 * npix + 32.0 * ntiles;
   if (what == 2) b += 20.0 * n + 4.0 * rpp * npix + 16.0 * (n / 2.0);      // backward workspace
   *bytes = (int64_t)(b * 1.1) + (1 << 20);
   return PF_OK;
