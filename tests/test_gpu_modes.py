@@ -128,3 +128,39 @@ def test_query_workspace_estimates():
     _flush(f"  estimates {q0} {q1} {q2}; after a render {q1b}, records {nrec} ({36 * nrec} B)")
     assert q1b >= 36 * nrec
     state.release()
+
+
+def test_raster_over_view_groups_equals_views_one_by_one():
+    # 1,048,576 cells x 257 views exceed the 2^28 (view, cell) pairs that one
+    # binning pass takes: the views are rendered in two groups, whose waves'
+    # segment tails sit at the tile offset of their group, and the backward
+    # walks the segments of both
+    import paper_2604_24994_amd as pf
+    _flush("case 257 views of 16x16 on 1,048,576 cells (two view groups)")
+    sc = W.c3_scene()
+    cams = [W.pinhole(e, 16, 16, 8.0) for e in W.random_eyes(257, 4.0, 77)]
+    rng = np.random.default_rng(3)
+    Gt = [torch.tensor(rng.normal(size=(c.n_rays, 4)), device="cuda", dtype=torch.float32) for c in cams]
+    params = {f: torch.tensor(getattr(sc, f), device="cuda", requires_grad=True) for f in PARAMS}
+    scene = pf.build_scene(params, sigma_scale=sc.sigma_scale, tau=sc.tau)
+    imgs = pf.render_raster_diff(scene, cams)
+    sum((im.reshape(-1, 4) * g).sum() for im, g in zip(imgs, Gt)).backward()
+    g_all = {f: params[f].grad.detach().cpu().numpy().astype(np.float64) for f in PARAMS}
+    for f in PARAMS:
+        params[f].grad = None
+    one = []
+    for c, g in zip(cams, Gt):
+        im = pf.render_raster_diff(scene, [c])[0]
+        (im.reshape(-1, 4) * g).sum().backward()
+        one.append(im.detach())
+    torch.cuda.synchronize()
+    seen = sum(int((im.detach()[..., 3] > 0).sum()) for im in imgs)
+    _flush(f"  pixels with coverage: {seen} of {257 * 256}")
+    assert seen > 1000
+    for a, b in zip(imgs, one):
+        assert torch.equal(a.detach(), b)
+    for f in PARAMS:
+        b = params[f].grad.detach().cpu().numpy().astype(np.float64)
+        rel = _rel(g_all[f], b)
+        _flush(f"  grad {f:10s} all views vs one by one: rel {rel:.2e}")
+        assert np.abs(b).max() > 0 and rel <= 1e-5, f
