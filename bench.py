@@ -54,7 +54,7 @@ TRAFFIC = {
                    "sources": {"pf_backward.hip": "458b6967458821ba", "pf_shade.hpp": "a630fdb381c7dae7",
                                "pf_internal.hpp": "95396ae9bc7369b2"}},
     "k_raster_store": {"fetch_kib": 16565845.6, "write_kib": 11283653.3,
-                       "sources": {"pf_render.hip": "08c4b47e1d54f880", "pf_shade.hpp": "a630fdb381c7dae7",
+                       "sources": {"pf_render.hip": "e2ac3b958af638c9", "pf_shade.hpp": "a630fdb381c7dae7",
                                    "pf_internal.hpp": "95396ae9bc7369b2"}},
     "k_clip": {"fetch_kib": 409618.1, "write_kib": 180464.1,
                "sources": {"pf_build.hip": "60ddab952277c61e", "pf_internal.hpp": "95396ae9bc7369b2"}},

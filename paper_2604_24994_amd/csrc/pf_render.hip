@@ -607,7 +607,7 @@ __global__ void __launch_bounds__(256) k_start_final(const double* __restrict__ 
 
 // STORE: every contribution is also written as a record (as the store-mode
 // rasteriser does) with a one-record segment; rec_seg must be zeroed by the
-// caller (unused slots of the wave's segment blocks keep count 0).
+// caller (unused slots of the wave's segment blocks keep an empty mask).
 // Six waves per SIMD (at most 80 VGPRs): the walk is bound by the latency of
 // its per-step gathers, and occupancy hides it (100 Mrays/s at the three
 // waves that 136 unconstrained VGPRs allow, 125 at six).
