@@ -207,12 +207,12 @@ pf_status pf_render_trace(pf_scene* scene, const pf_camera* cams, int32_t ncam,
    over the rays, so its gradient is obtained by adding its weight to the A
    channel of d_rgba.  Statistics (device pointers, accumulated with +=):
    contribution [n] float, per cell sum over the rays of T a (the per-cell
-   sparsity term and the quantity the pruning schedule tracks, Sec. 3.7);
+   sparsity term and the quantity the pruning schedule tracks, Sec. 3.5);
    normal_loss [1] double, the value of L_normal over the rays;
    error [n] float, per cell sum over the rays of T a e, given the per-pixel
    photometric error pixel_error (device, one float per pixel in the image
    layout without the channel axis): the per-cell error that densification
-   averages (Sec. 3.7).  Both must be given for the error statistic. */
+   averages (Sec. 3.5).  Both must be given for the error statistic. */
 typedef struct {
   float lambda_normal;
   float* contribution;
@@ -292,13 +292,13 @@ pf_status pf_steiner(const pf_params* params, const float* z, const pf_steiner_o
                      float* out_p, float* out_power, float* out_radius, int32_t* out_near,
                      int64_t* round_counts, int64_t* n_out, void* stream);
 
-/* Exponential moving average for the densify/prune schedule (Sec. 3.7):
+/* Exponential moving average for the densify/prune schedule (Sec. 3.5):
    ema[i] = beta * ema[i] + (1 - beta) * value[i] for i < n (device arrays,
    formed in float64, rounded to float32).  Errors: INVALID (NULL, n < 0,
    beta outside [0, 1]), HIP. */
 pf_status pf_ema_update(float* ema, const float* value, int64_t n, float beta, void* stream);
 
-/* Densification and pruning (Sec. 3.7).  Cells whose contribution average
+/* Densification and pruning (Sec. 3.5).  Cells whose contribution average
    contrib_ema[i] is below prune_below are removed; the kept cells keep
    their order.  Then n_new cells are drawn, with replacement, from the
    multinomial distribution proportional to the kept cells' error averages

@@ -23,7 +23,7 @@ What it computes (all in float64, from the float32 inputs as given):
 * the Steiner cells of the supplementary material (Alg. 1) that fill empty
   space for the walk;
 * the per-cell error statistic, moving averages, pruning and multinomial
-  densification of Sec. 3.7.
+  densification of Sec. 3.5.
 
 Two independent forms are provided: the brute-force walk (start cell by
 argmin power distance over all sites, each exit by brute force over every

@@ -1,6 +1,6 @@
 """Densification and pruning (oracle; test infrastructure).
 
-Sec. 3.7, "Densification and Pruning", restated in float64:
+Sec. 3.5, "Densification and Pruning", restated in float64:
 
 * per-cell photometric error of a training view: the pixels' errors
   distributed over the cells by their contribution,

@@ -1,6 +1,6 @@
 """Training regularisers and per-cell statistics (oracle; test infrastructure).
 
-Supplementary material, "Loss functions", and Sec. 3.7 (densification and
+Supplementary material, "Loss functions", and Sec. 3.5 (densification and
 pruning), restated in float64:
 
 * contribution of cell i over a set of rays: ``sum_rays T a`` (the per-cell

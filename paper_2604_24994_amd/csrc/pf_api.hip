@@ -235,7 +235,8 @@ pf_status run_pass(pf_scene* scene, const std::vector<pf_camera>& cams, int kind
 pf_status new_state(pf_scene* scene, const pf_camera* cams, int32_t ncam, int kind, int mode, float t_min,
                     int max_steps, hipStream_t s, pf_fwd_state** out, const char* who) {
   *out = nullptr;
-  if (ncam >= 4096) return invalid(std::string(who) + ": at most 4095 cameras per call with a forward state");
+  // the records store the view in 12 bits (pf_record.hpp)
+  if (ncam > pf::REC_MAX_VIEWS) return invalid(std::string(who) + ": at most 4096 cameras per call with a forward state");
   pf_fwd_state* fs = new (std::nothrow) pf_fwd_state();
   if (!fs) {
     pf::set_error(std::string(who) + ": host allocation failed");

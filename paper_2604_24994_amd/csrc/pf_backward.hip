@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(256) k_suffix(const int32_t* __restrict__ head
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
     if (lambda_n != 0.0f || normal_loss) {
       const int4 r0 = ri[k];
-      const pf_camera& cam = cams[r0.w >> 20];
+      const pf_camera& cam = cams[rec_view(r0.w)];
       const RayD R = make_ray(cam, r0.y % cam.width + 0.5, r0.y / cam.width + 0.5);
       fx = R.fx;
       fy = R.fy;
@@ -392,8 +392,8 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
       gf = rf[ridx];
       ta = rta[ridx];
     }
-    const int view = rec.w >> 20;
-    const int b0 = ((rec.w >> 10) & 1023) - 2, b1 = (rec.w & 1023) - 2;
+    const int view = rec_view(rec.w);
+    const int b0 = rec_bind0(rec.w), b1 = rec_bind1(rec.w);
     const pf_camera& cam = cams[valid ? view : 0];
     const int pxl = rec.y % cam.width, pyl = rec.y / cam.width;
     const RayD R = make_ray(cam, pxl + 0.5, pyl + 0.5);

@@ -1,4 +1,4 @@
-// Densification and pruning (Sec. 3.7): moving averages of the per-cell
+// Densification and pruning (Sec. 3.5): moving averages of the per-cell
 // error and contribution, removal of cells whose contribution average is
 // below a threshold, and new cells drawn from the multinomial distribution
 // proportional to the error average of the remaining cells.

@@ -8,6 +8,9 @@
 
 #include "powerfoam.h"
 
+#define PF_HD __host__ __device__
+#include "pf_record.hpp"
+
 namespace pf {
 
 constexpr int KD = 8;              // detail sites per face (built variant)
@@ -67,7 +70,7 @@ struct Scene {
 // Contribution records written by the store-mode forward: one per (pixel,
 // cell) with alpha > 0, chained per pixel back to front through `prev`.
 //   ri = (cell, pixel within its view, prev record or -1,
-//         view << 20 | (bind0 + 2) << 10 | (bind1 + 2))
+//         pack_view_bind(view, bind0, bind1), see pf_record.hpp)
 //   rf = (alpha, c.r, c.g, c.b); after the per-pixel pass (dL/dalpha, dL/dc)
 //   rt = transmittance in front of the contribution
 // bind: -1 sphere, -2 ray start, f >= 0 raster face index of the cell.

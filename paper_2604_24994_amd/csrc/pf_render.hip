@@ -483,7 +483,7 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
           if (contrib) {
             const long long slot = base + __popcll(m & lt);
             if (slot < rec_cap) {
-              rec_ri[slot] = make_int4(ci, pix, head, (view << 20) | ((P.bind0 + 2) << 10) | (P.bind1 + 2));
+              rec_ri[slot] = make_int4(ci, pix, head, pack_view_bind(view, P.bind0, P.bind1));
               rec_rf[slot] = make_float4(P.alpha, r, gg, b);
               rec_rt[slot] = T;
               head = (int)slot;
@@ -677,7 +677,7 @@ k_trace(ViewArgs v, SceneDev S, const int32_t* __restrict__ start,
           if (contrib) {
             const long long slot = rblk + __popcll(m & lt), sg = sblk + __popcll(m & lt);
             if (slot < rec_cap) {
-              rec_ri[slot] = make_int4(cell, pix, head, (view << 20) | ((P.bind0 + 2) << 10) | (P.bind1 + 2));
+              rec_ri[slot] = make_int4(cell, pix, head, pack_view_bind(view, P.bind0, P.bind1));
               rec_rf[slot] = make_float4(P.alpha, r, gg, b);
               rec_rt[slot] = T;
               head = (int)slot;

@@ -1,4 +1,4 @@
-"""GPU parity of densification and pruning (Sec. 3.7) against the FP64
+"""GPU parity of densification and pruning (Sec. 3.5) against the FP64
 oracle (pinned in test_oracle_densify.py): the per-cell error statistic of
 the backward, the moving average, and the densify/prune update."""
 import numpy as np

@@ -1,4 +1,4 @@
-"""Pins of the densify/prune oracle (Sec. 3.7): the multinomial draw on a hand
+"""Pins of the densify/prune oracle (Sec. 3.5): the multinomial draw on a hand
 case and in distribution, the moving average's closed form, the pruning
 boundary, and the per-cell error against the telescoping of the segment sum
 (sum over cells of T a e = sum over rays of A e)."""
