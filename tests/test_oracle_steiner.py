@@ -1,7 +1,9 @@
 """Pins of the Steiner-cell oracle (supplementary material, Steiner points,
 Alg. 1): closed forms on one and two spheres, the power-nearest choice, the
-round structure, a pure-Python brute force, and the invariance of the image
-when empty cells are added outside the spheres of a scene with w = r^2."""
+in-loop insertion (a later point of a round is tested against the cells kept
+earlier in that round), the round structure, a pure-Python brute force, and
+the invariance of the image when empty cells are added outside the spheres
+of a scene with w = r^2."""
 import math
 
 import numpy as np
@@ -9,7 +11,7 @@ import pytest
 
 import workloads as W
 from oracle.cell import bisector
-from oracle.steiner import evaluate_candidates, steiner_points
+from oracle.steiner import evaluate_candidates, steiner_points, steiner_round
 from oracle.walk import render_walk
 
 
@@ -55,6 +57,58 @@ def test_new_weight_puts_the_bisector_on_the_nearest_sphere():
         m, h = bisector(np.asarray(P[i], float), float(Wt[i]), x[j], float(w_hat[j]))
         # plane (y - p_i).m <= h: its distance from p_i is h / |m| = r_i
         assert h / np.linalg.norm(m) == pytest.approx(R[i], rel=1e-12)
+
+
+def _round(P, R, X, Wt=None, lo=2.0, hi=6.0):
+    P = np.asarray(P, float)
+    R = np.asarray(R, float)
+    Wt = R * R if Wt is None else np.asarray(Wt, float)
+    X = np.asarray(X, float)
+    cap = len(P) + len(X)
+    PP, RR, WW = np.zeros((cap, 3)), np.zeros(cap), np.zeros(cap)
+    PP[:len(P)], RR[:len(P)], WW[:len(P)] = P, R, Wt
+    m, kept, near = steiner_round(PP, RR, WW, len(P), X, lo, hi)
+    return kept.tolist(), near.tolist(), PP[len(P):m], RR[len(P):m], WW[len(P):m]
+
+
+def test_later_point_is_tested_against_cells_kept_earlier_in_the_round():
+    # unit sphere at the origin; three points of one round, in this order:
+    #   (3, 0, 0): r_hat = 3 - 1 = 2, ratio 2: kept as a cell of radius 2
+    #   (3.5, 0, 0): outside the unit sphere (ratio 2.5 against it alone) but
+    #       0.5 from the centre of the cell just kept, inside its radius 2:
+    #       rejected
+    #   (3, 7, 0): power 49 - 4 = 45 w.r.t. the kept cell vs 58 - 1 = 57
+    #       w.r.t. the unit sphere, so the kept cell is its nearest:
+    #       r_hat = 7 - 2 = 5, ratio 2.5: kept.  Against the unit sphere alone
+    #       it would have r_hat = sqrt(58) - 1 = 6.62, ratio > 6: rejected.
+    kept, near, P, R, Wt = _round([[0, 0, 0]], [1.0], [[3, 0, 0], [3.5, 0, 0], [3, 7, 0]])
+    assert kept == [0, 2]
+    assert near == [0, 1]
+    assert P.tolist() == [[3, 0, 0], [3, 7, 0]]
+    assert R.tolist() == [2.0, 5.0]
+    # w = r^2 scene: the new weights are r_hat^2
+    assert Wt.tolist() == [4.0, 25.0]
+    # judged one by one against the unit sphere alone, the verdicts differ
+    keep_fixed, _, _, _ = _evaluate([[0, 0, 0]], [1.0], [[3, 0, 0], [3.5, 0, 0], [3, 7, 0]])
+    assert keep_fixed.tolist() == [True, True, False]
+
+
+def test_order_within_a_round_decides():
+    # the same two points in the other order: (3.5, 0, 0) first is kept with
+    # r_hat 2.5; then (3, 0, 0) lies inside its sphere (0.5 < 2.5) and is
+    # rejected
+    kept, near, _, R, _ = _round([[0, 0, 0]], [1.0], [[3.5, 0, 0], [3, 0, 0]])
+    assert kept == [0] and near == [0] and R.tolist() == [2.5]
+
+
+def test_tie_between_scene_cell_and_kept_cell_goes_to_the_scene_cell():
+    # after (3, 0, 0) is kept (radius 2), the points of equal power w.r.t.
+    # the unit sphere and the kept cell satisfy |x|^2 - 1 = |x - (3,0,0)|^2 - 4,
+    # i.e. x = 1; (1, 6, 0) has power 36 w.r.t. both
+    kept, near, _, R, _ = _round([[0, 0, 0]], [1.0], [[3, 0, 0], [1, 6, 0]], lo=0.0, hi=100.0)
+    assert kept == [0, 1]
+    assert near == [0, 0]                  # the scene cell (lower index) wins the tie
+    assert R[1] == float(np.float32(math.sqrt(37.0) - 1.0))   # stored as the float32 site radius
 
 
 def test_rounds_see_earlier_rounds_and_use_their_statistics():
@@ -111,21 +165,31 @@ def test_vectorised_test_matches_pure_python_brute_force():
 
 
 def test_kept_cells_lie_outside_every_earlier_sphere():
+    # every kept cell lies outside the spheres of the scene and of every cell
+    # kept before it, in its own round too, and its radius is 2..6 times its
+    # nearest cell's
     sc = W.scene_uniform(256, seed=3)
     z = W.steiner_draws(3, 512, seed=9)
     out = steiner_points(sc.p, sc.radius, sc.power, z)
     assert out["p"].shape[0] > 20
-    P = sc.p.astype(float)
-    R = sc.radius.astype(float)
-    for rnd in range(3):
-        sel = out["round"] == rnd
-        q = out["p"][sel].astype(float)
-        pw = ((q[:, None, :] - P[None]) ** 2).sum(-1) - R[None] ** 2
+    P = np.concatenate([sc.p, out["p"]]).astype(float)
+    R = np.concatenate([sc.radius, out["radius"]]).astype(float)
+    n = sc.n
+    for a in range(out["p"].shape[0]):
+        q = out["p"][a].astype(float)
+        pw = ((q[None, :] - P[:n + a]) ** 2).sum(-1) - R[:n + a] ** 2
         assert (pw > 0).all()
-        ratio = out["radius"][sel] / R[out["near"][sel]]
-        assert ((ratio >= 2 - 1e-6) & (ratio <= 6 + 1e-6)).all()
-        P = np.concatenate([P, q])
-        R = np.concatenate([R, out["radius"][sel].astype(float)])
+        assert int(np.argmin(pw)) == out["near"][a]
+        ratio = out["radius"][a] / R[out["near"][a]]
+        assert 2 - 1e-6 <= ratio <= 6 + 1e-6
+    # within a round, some later point was rejected or re-targeted because of
+    # an earlier one: the in-loop verdicts differ from judging the round's
+    # points against the round-start set alone
+    mean, std = sc.p.astype(float).mean(0), sc.p.astype(float).std(0)
+    X = (mean + std * z[0].astype(float)).astype(np.float32).astype(float)
+    keep0, _, _, _ = evaluate_candidates(sc.p.astype(float), sc.radius.astype(float), sc.power.astype(float), X)
+    kept0 = out["candidate"][out["round"] == 0]
+    assert set(kept0.tolist()) != set(np.nonzero(keep0)[0].tolist())
 
 
 def test_empty_cells_outside_the_spheres_leave_the_image_unchanged():
