@@ -3,13 +3,35 @@
 //
 // Per round: the per-axis mean and standard deviation of the current sites
 // (scene cells and the Steiner cells kept so far) turn the caller's standard
-// normal draws into candidate points; a candidate outside every sphere takes
-// the radius `|x - p_near| - r_near` to the sphere of its least-power cell
-// (power `|x - p|^2 - r^2`) and is kept when that radius lies within
-// [lo r_near, hi r_near].  Kept candidates join the site set at the end of
-// the round, in candidate order.  The new cell's power weight
+// normal draws into candidate points.  The candidates are then judged in
+// order, each against the scene, the cells of earlier rounds and the cells
+// kept earlier in the same round (the set grows inside the loop over the
+// sample): a candidate outside every sphere takes the radius
+// `|x - p_near| - r_near` to the sphere of its least-power cell (power
+// `|x - p|^2 - r^2`) and is kept when that radius lies within
+// [lo r_near, hi r_near].  The new cell's power weight
 // `r_hat^2 - r_near^2 + w_near` puts its bisector with the nearest cell on
 // that cell's sphere (`r_hat^2` when w = r^2).
+//
+// The in-order loop is made data-parallel in three steps:
+//   k_st_eval     every candidate against the sites present at the round's
+//                 start: least power and its cell.  A candidate inside a
+//                 sphere there stays invalid (the set only grows).
+//   k_st_conf     for each valid candidate, the earlier valid candidates
+//                 that could change its verdict if kept.  A kept cell k
+//                 changes candidate j only if its power at x_j is below j's
+//                 round-start least power b_j, i.e. |x_j - x_k|^2 < b_j + r_k^2,
+//                 and r_k <= sqrt(b_k) (the distance to the nearest sphere is
+//                 at most the square root of the power there), so the pairs
+//                 with |x_j - x_k|^2 < b_j + b_k (widened for rounding) are
+//                 listed; every other earlier cell leaves j's least power
+//                 and nearest cell as they are.
+//   k_st_resolve  launched until every valid candidate is decided: a
+//                 candidate is decided once all of its listed candidates were
+//                 decided in an earlier launch, by folding the kept ones into
+//                 its round-start least power in candidate order (strict
+//                 improvement: ties keep the lower index, scene cells first).
+// Every decision is the one the in-order loop takes.
 //
 // Layout: the sites of a round are Morton-sorted into an implicit 64-ary tree
 // (per node: box and largest radius); one wave per candidate walks it depth
@@ -19,6 +41,7 @@
 // so every decision is the one the float64 definition takes.
 #include "pf_internal.hpp"
 
+#include <algorithm>
 #include <climits>
 #include <vector>
 
@@ -179,16 +202,16 @@ __global__ void __launch_bounds__(64) k_st_level(const float4* __restrict__ sp, 
 
 __device__ inline double slack(double best) { return 1e-9 * (1.0 + fabs(best)); }
 
-// One wave per candidate: least power over the sites, then the test.
+// One wave per candidate: least power over the round-start sites and its
+// cell (ties: lower index).
 __global__ void __launch_bounds__(64) k_st_eval(const float* __restrict__ z, int64_t n_cand,
                                                  const double* __restrict__ stat, const float4* __restrict__ sp,
                                                  const int32_t* __restrict__ sidx, int64_t m,
                                                  const float4* __restrict__ nlo, const float4* __restrict__ nhi,
-                                                 Levels lv, const float* __restrict__ up,
-                                                 const float* __restrict__ ur, const float* __restrict__ uw,
-                                                 double lo_ratio, double hi_ratio, uint32_t* __restrict__ flag,
-                                                 float4* __restrict__ cx, float* __restrict__ cw,
-                                                 int32_t* __restrict__ cnear, unsigned int* __restrict__ overflow) {
+                                                 Levels lv,
+                                                 uint32_t* __restrict__ vflag, float4* __restrict__ cx,
+                                                 double* __restrict__ cbest, int32_t* __restrict__ cnear,
+                                                 unsigned int* __restrict__ overflow) {
 #pragma clang fp contract(off)
   __shared__ int stk[ST_STACK];
   __shared__ double skey[ST_STACK];
@@ -277,51 +300,168 @@ __global__ void __launch_bounds__(64) k_st_eval(const float* __restrict__ z, int
     __syncthreads();
   }
   if (lane != 0) return;
+  const bool valid = best > 0.0 && bi != INT_MAX;
+  vflag[j] = valid ? 1u : 0u;
+  cx[j] = make_float4(xf[0], xf[1], xf[2], 0.0f);
+  cbest[j] = best;
+  cnear[j] = valid ? bi : -1;
+}
+
+// Valid candidates, in candidate order, with their round-start least power,
+// its cell and the widened square of the largest radius they can take.
+__global__ void k_st_compact(const uint32_t* __restrict__ vflag, const uint32_t* __restrict__ vpos, int64_t n_cand,
+                             const float4* __restrict__ cx, const double* __restrict__ cbest,
+                             const int32_t* __restrict__ cnear, float4* __restrict__ vx, double* __restrict__ vb,
+                             double* __restrict__ vrho, int32_t* __restrict__ vnear) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_cand || !vflag[j]) return;
+  const uint32_t v = vpos[j];
+  const float4 x = cx[j];
+  const double b = cbest[j];
+  vx[v] = x;
+  vb[v] = b;
+  // r_hat = b / (|x - p| + r) <= sqrt(b); the float64 and float32 roundings
+  // of the kept radius are covered by the relative and absolute widening
+  const double ax = fmax(fabs((double)x.x), fmax(fabs((double)x.y), fabs((double)x.z)));
+  const double r = sqrt(b) * (1.0 + 1e-6) + 1e-7 * (1.0 + ax);
+  vrho[v] = r * r;
+  vnear[v] = cnear[j];
+}
+
+constexpr int CF_THREADS = 256;
+constexpr int RES_OPEN = 0x7F7F7F7F;   // k_st_resolve: not decided yet (the byte fill 0x7F)
+
+// Earlier valid candidates that can change candidate v's verdict (FILL =
+// false: their count; true: their indices, in increasing order).
+template <bool FILL>
+__global__ void __launch_bounds__(CF_THREADS) k_st_conf(const float4* __restrict__ vx, const double* __restrict__ vb,
+                                                         const double* __restrict__ vrho, int64_t nv,
+                                                         uint32_t* __restrict__ cnt, const uint32_t* __restrict__ off,
+                                                         int32_t* __restrict__ list,
+                                                         unsigned long long* __restrict__ total) {
+  __shared__ float4 sx[CF_THREADS];
+  __shared__ double sr[CF_THREADS];
+  const int64_t v = (int64_t)blockIdx.x * CF_THREADS + threadIdx.x;
+  const int64_t vmax = min(nv - 1, (int64_t)blockIdx.x * CF_THREADS + CF_THREADS - 1);
+  float4 x = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  double bj = 0.0;
+  if (v < nv) {
+    x = vx[v];
+    bj = vb[v];
+  }
+  uint32_t c = 0;
+  uint32_t o = (FILL && v < nv) ? off[v] : 0u;
+  for (int64_t t0 = 0; t0 < vmax; t0 += CF_THREADS) {
+    __syncthreads();
+    const int64_t k = t0 + threadIdx.x;
+    if (k < nv) {
+      sx[threadIdx.x] = vx[k];
+      sr[threadIdx.x] = vrho[k];
+    }
+    __syncthreads();
+    if (v < nv) {
+      const int kend = (int)min((int64_t)CF_THREADS, v - t0);
+      for (int q = 0; q < kend; ++q) {
+        const float4 y = sx[q];
+        const double dx = (double)x.x - (double)y.x, dy = (double)x.y - (double)y.y, dz = (double)x.z - (double)y.z;
+        const double d2 = (dx * dx + dy * dy) + dz * dz;
+        if (d2 < (bj + sr[q]) * (1.0 + 1e-12)) {
+          if (FILL) list[o + c] = (int32_t)(t0 + q);
+          ++c;
+        }
+      }
+    }
+  }
+  if (!FILL) {
+    if (v < nv) cnt[v] = c;
+    unsigned long long t = c;
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if ((threadIdx.x & 63) == 0 && t) atomicAdd(total, t);
+  }
+}
+
+// One launch of the in-order resolution (see the file header).  it: the
+// launch's number; res[v] the launch that decided v (RES_OPEN: not yet).
+// tag[v] >= 0: the nearest cell is site tag[v] of the round-start set;
+// tag[v] < 0: it is the valid candidate -1 - tag[v] of this round.
+__global__ void k_st_resolve(const float4* __restrict__ vx, const double* __restrict__ vb,
+                             const int32_t* __restrict__ vnear, int64_t nv, const uint32_t* __restrict__ off,
+                             const int32_t* __restrict__ list, const float* __restrict__ up,
+                             const float* __restrict__ ur, const float* __restrict__ uw, double lo_ratio,
+                             double hi_ratio, int it, int32_t* __restrict__ res, uint32_t* __restrict__ kept,
+                             float* __restrict__ vr, float* __restrict__ vw, int32_t* __restrict__ tag,
+                             unsigned int* __restrict__ done) {
+#pragma clang fp contract(off)
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv || res[v] != RES_OPEN) return;
+  const uint32_t c0 = off[v], c1 = off[v + 1];
+  for (uint32_t c = c0; c < c1; ++c)
+    if (res[list[c]] >= it) return;   // an earlier candidate is still open
+  const float4 x = vx[v];
+  const double xx = x.x, xy = x.y, xz = x.z;
+  double best = vb[v];
+  int t = vnear[v];
+  double npx = up[3 * (int64_t)t], npy = up[3 * (int64_t)t + 1], npz = up[3 * (int64_t)t + 2];
+  double nr = ur[t], nw = uw[t];
+  for (uint32_t c = c0; c < c1; ++c) {
+    const int k = list[c];
+    if (!kept[k]) continue;
+    const float4 y = vx[k];
+    const double rk = vr[k];
+    const double dx = xx - (double)y.x, dy = xy - (double)y.y, dz = xz - (double)y.z;
+    const double pw = ((dx * dx + dy * dy) + dz * dz) - rk * rk;
+    if (pw < best) {
+      best = pw;
+      t = -1 - k;
+      npx = y.x; npy = y.y; npz = y.z;
+      nr = rk;
+      nw = vw[k];
+    }
+  }
   uint32_t ok = 0;
   float rh_f = 0.0f, wh_f = 0.0f;
-  int near = -1;
-  if (best > 0.0 && bi != INT_MAX) {
-    near = bi;
-    const double px = up[3 * (int64_t)bi], py = up[3 * (int64_t)bi + 1], pz = up[3 * (int64_t)bi + 2];
-    const double rn = ur[bi], wn = uw[bi];
-    const double dx = x - px, dy = y - py, dz = zc - pz;
+  if (best > 0.0) {
+    const double dx = xx - npx, dy = xy - npy, dz = xz - npz;
     const double d = sqrt((dx * dx + dy * dy) + dz * dz);
-    const double rh = d - rn;
-    ok = (lo_ratio * rn <= rh && rh <= hi_ratio * rn) ? 1u : 0u;
+    const double rh = d - nr;
+    ok = (lo_ratio * nr <= rh && rh <= hi_ratio * nr) ? 1u : 0u;
     rh_f = __double2float_rn(rh);
-    wh_f = __double2float_rn((rh * rh - rn * rn) + wn);
+    wh_f = __double2float_rn((rh * rh - nr * nr) + nw);
   }
-  flag[j] = ok;
-  cx[j] = make_float4(xf[0], xf[1], xf[2], rh_f);
-  cw[j] = wh_f;
-  cnear[j] = near;
+  kept[v] = ok;
+  vr[v] = rh_f;
+  vw[v] = wh_f;
+  tag[v] = t;
+  res[v] = it;
+  atomicAdd(done, 1u);
 }
 
 // Kept candidates, in candidate order, to the caller's outputs (from `a`)
 // and to the site set (from `m`).
-__global__ void k_st_emit(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ pos, int64_t n_cand,
-                          const float4* __restrict__ cx, const float* __restrict__ cw,
-                          const int32_t* __restrict__ cnear, int64_t a, int64_t m, int64_t cap,
+__global__ void k_st_emit(const uint32_t* __restrict__ kept, const uint32_t* __restrict__ kpos, int64_t nv,
+                          const float4* __restrict__ vx, const float* __restrict__ vr, const float* __restrict__ vw,
+                          const int32_t* __restrict__ tag, int64_t a, int64_t m, int64_t cap,
                           float* __restrict__ out_p, float* __restrict__ out_w, float* __restrict__ out_r,
                           int32_t* __restrict__ out_near, float* __restrict__ up, float* __restrict__ ur,
                           float* __restrict__ uw) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n_cand || !flag[j]) return;
-  const int64_t k = pos[j];
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv || !kept[v]) return;
+  const int64_t k = kpos[v];
   if (a + k >= cap) return;
-  const float4 c = cx[j];
+  const float4 c = vx[v];
   const int64_t o = a + k, u = m + k;
   out_p[3 * o] = c.x;
   out_p[3 * o + 1] = c.y;
   out_p[3 * o + 2] = c.z;
-  out_r[o] = c.w;
-  out_w[o] = cw[j];
-  if (out_near) out_near[o] = cnear[j];
+  out_r[o] = vr[v];
+  out_w[o] = vw[v];
+  const int t = tag[v];
+  if (out_near) out_near[o] = t >= 0 ? t : (int32_t)(m + kpos[-1 - t]);
   up[3 * u] = c.x;
   up[3 * u + 1] = c.y;
   up[3 * u + 2] = c.z;
-  ur[u] = c.w;
-  uw[u] = cw[j];
+  ur[u] = vr[v];
+  uw[u] = vw[v];
 }
 
 Levels levels_for(int64_t count, long long* total_nodes) {
@@ -359,12 +499,14 @@ pf_status steiner_impl(const pf_params& prm, const float* z, const pf_steiner_op
     set_error("pf_steiner: too many sites for the search tree");
     return PF_ERR_UNSUPPORTED;
   }
-  Tmp<double> stat(s), part(s);
-  Tmp<uint32_t> keys(s), order(s), flag(s), pos(s), tot(s);
-  Tmp<float4> sp(s), nlo(s), nhi(s), cx(s);
-  Tmp<int32_t> sidx(s), cnear(s);
-  Tmp<float> cw(s);
-  Tmp<unsigned int> ovf(s);
+  const int64_t nc = opt.n_cand;
+  Tmp<double> stat(s), part(s), cbest(s), vb(s), vrho(s);
+  Tmp<uint32_t> keys(s), order(s), vflag(s), vpos(s), tot(s), ccnt(s), coff(s), kept(s), kpos(s);
+  Tmp<float4> sp(s), nlo(s), nhi(s), cx(s), vx(s);
+  Tmp<int32_t> sidx(s), cnear(s), vnear(s), res(s), tag(s);
+  Tmp<float> vr(s), vw(s);
+  Tmp<unsigned int> ovf(s), done(s);
+  Tmp<unsigned long long> ctot(s);
   PF_HIP_TRY(stat.alloc(12));
   PF_HIP_TRY(part.alloc(9 * ST_BLOCKS));
   PF_HIP_TRY(keys.alloc(total));
@@ -373,13 +515,27 @@ pf_status steiner_impl(const pf_params& prm, const float* z, const pf_steiner_op
   PF_HIP_TRY(sidx.alloc(total));
   PF_HIP_TRY(nlo.alloc(max_nodes));
   PF_HIP_TRY(nhi.alloc(max_nodes));
-  PF_HIP_TRY(flag.alloc(opt.n_cand));
-  PF_HIP_TRY(pos.alloc(opt.n_cand));
-  PF_HIP_TRY(tot.alloc(1));
-  PF_HIP_TRY(cx.alloc(opt.n_cand));
-  PF_HIP_TRY(cw.alloc(opt.n_cand));
-  PF_HIP_TRY(cnear.alloc(opt.n_cand));
+  PF_HIP_TRY(vflag.alloc(nc));
+  PF_HIP_TRY(vpos.alloc(nc));
+  PF_HIP_TRY(tot.alloc(2));
+  PF_HIP_TRY(cx.alloc(nc));
+  PF_HIP_TRY(cbest.alloc(nc));
+  PF_HIP_TRY(cnear.alloc(nc));
+  PF_HIP_TRY(vx.alloc(nc));
+  PF_HIP_TRY(vb.alloc(nc));
+  PF_HIP_TRY(vrho.alloc(nc));
+  PF_HIP_TRY(vnear.alloc(nc));
+  PF_HIP_TRY(ccnt.alloc(nc + 1));
+  PF_HIP_TRY(coff.alloc(nc + 1));
+  PF_HIP_TRY(res.alloc(nc));
+  PF_HIP_TRY(kept.alloc(nc));
+  PF_HIP_TRY(kpos.alloc(nc));
+  PF_HIP_TRY(tag.alloc(nc));
+  PF_HIP_TRY(vr.alloc(nc));
+  PF_HIP_TRY(vw.alloc(nc));
   PF_HIP_TRY(ovf.alloc(1));
+  PF_HIP_TRY(done.alloc(1));
+  PF_HIP_TRY(ctot.alloc(1));
   PF_HIP_TRY(hipMemsetAsync(ovf.p, 0, sizeof(unsigned int), s));
 
   int64_t a = 0;
@@ -410,33 +566,93 @@ pf_status steiner_impl(const pf_params& prm, const float* z, const pf_steiner_op
     }
     {
       ProfScope ps("k_st_eval", s);
-      k_st_eval<<<(unsigned)opt.n_cand, 64, 0, s>>>(z + 3 * opt.n_cand * (int64_t)r, opt.n_cand, stat.p, sp.p,
-                                                     sidx.p, m, nlo.p, nhi.p, lv, up.p, ur.p, uw.p,
-                                                     (double)opt.lo_ratio, (double)opt.hi_ratio, flag.p, cx.p, cw.p,
-                                                     cnear.p, ovf.p);
+      k_st_eval<<<(unsigned)nc, 64, 0, s>>>(z + 3 * nc * (int64_t)r, nc, stat.p, sp.p, sidx.p, m, nlo.p, nhi.p, lv,
+                                            vflag.p, cx.p, cbest.p, cnear.p, ovf.p);
     }
     PF_HIP_TRY(hipGetLastError());
-    PF_HIP_TRY(exclusive_scan_u32(flag.p, pos.p, opt.n_cand, tot.p, s));
-    k_st_emit<<<(unsigned)((opt.n_cand + 255) / 256), 256, 0, s>>>(flag.p, pos.p, opt.n_cand, cx.p, cw.p, cnear.p, a,
-                                                                   m, cap, out_p, out_power, out_radius, out_near,
-                                                                   up.p, ur.p, uw.p);
+    // valid candidates, in candidate order
+    PF_HIP_TRY(exclusive_scan_u32(vflag.p, vpos.p, nc, tot.p, s));
+    const unsigned gc = (unsigned)((nc + 255) / 256);
+    k_st_compact<<<gc, 256, 0, s>>>(vflag.p, vpos.p, nc, cx.p, cbest.p, cnear.p, vx.p, vb.p, vrho.p, vnear.p);
     PF_HIP_TRY(hipGetLastError());
-    uint32_t kept = 0;
+    uint32_t nv = 0;
     unsigned int over = 0;
-    PF_HIP_TRY(hipMemcpyAsync(&kept, tot.p, sizeof(kept), hipMemcpyDeviceToHost, s));
+    PF_HIP_TRY(hipMemcpyAsync(&nv, tot.p, sizeof(nv), hipMemcpyDeviceToHost, s));
     PF_HIP_TRY(hipMemcpyAsync(&over, ovf.p, sizeof(over), hipMemcpyDeviceToHost, s));
     PF_HIP_TRY(hipStreamSynchronize(s));
     if (over) {
       set_error("pf_steiner: search stack exceeded");
       return PF_ERR_OVERFLOW;
     }
-    if (round_counts) round_counts[r] = kept;
-    if (a + (int64_t)kept > cap) {
+    uint32_t nkept = 0;
+    if (nv > 0) {
+      // the earlier candidates each valid one must wait for
+      const unsigned gv = (unsigned)((nv + CF_THREADS - 1) / CF_THREADS);
+      PF_HIP_TRY(hipMemsetAsync(ctot.p, 0, sizeof(unsigned long long), s));
+      {
+        ProfScope ps("k_st_conf", s);
+        k_st_conf<false><<<gv, CF_THREADS, 0, s>>>(vx.p, vb.p, vrho.p, nv, ccnt.p, nullptr, nullptr, ctot.p);
+      }
+      PF_HIP_TRY(hipGetLastError());
+      unsigned long long nconf64 = 0;
+      PF_HIP_TRY(hipMemcpyAsync(&nconf64, ctot.p, sizeof(nconf64), hipMemcpyDeviceToHost, s));
+      PF_HIP_TRY(hipStreamSynchronize(s));
+      if (nconf64 >= (1ull << 31)) {
+        set_error("pf_steiner: more than 2^31 candidate pairs to resolve in one round; draw fewer candidates");
+        return PF_ERR_OVERFLOW;
+      }
+      PF_HIP_TRY(hipMemsetAsync(ccnt.p + nv, 0, sizeof(uint32_t), s));
+      PF_HIP_TRY(exclusive_scan_u32(ccnt.p, coff.p, (int64_t)nv + 1, tot.p + 1, s));
+      uint32_t nconf = 0;
+      PF_HIP_TRY(hipMemcpyAsync(&nconf, tot.p + 1, sizeof(nconf), hipMemcpyDeviceToHost, s));
+      PF_HIP_TRY(hipStreamSynchronize(s));
+      Tmp<int32_t> clist(s);
+      PF_HIP_TRY(clist.alloc(nconf));
+      {
+        ProfScope ps("k_st_conf", s);
+        k_st_conf<true><<<gv, CF_THREADS, 0, s>>>(vx.p, vb.p, vrho.p, nv, nullptr, coff.p, clist.p, nullptr);
+      }
+      PF_HIP_TRY(hipGetLastError());
+      // in-order decisions: every launch decides at least the earliest open
+      // candidate, so at most nv launches
+      PF_HIP_TRY(hipMemsetAsync(res.p, 0x7F, sizeof(int32_t) * nv, s));   // RES_OPEN, above any launch number
+      PF_HIP_TRY(hipMemsetAsync(done.p, 0, sizeof(unsigned int), s));
+      const unsigned gr = (unsigned)((nv + 255) / 256);
+      int it = 0, batch = 4;   // launches between checks, doubled up to 64 (extra launches find nothing open)
+      for (;;) {
+        {
+          ProfScope ps("k_st_resolve", s);
+          for (int q = 0; q < batch; ++q, ++it)
+            k_st_resolve<<<gr, 256, 0, s>>>(vx.p, vb.p, vnear.p, nv, coff.p, clist.p, up.p, ur.p, uw.p,
+                                            (double)opt.lo_ratio, (double)opt.hi_ratio, it, res.p, kept.p, vr.p,
+                                            vw.p, tag.p, done.p);
+        }
+        PF_HIP_TRY(hipGetLastError());
+        unsigned int nd = 0;
+        PF_HIP_TRY(hipMemcpyAsync(&nd, done.p, sizeof(nd), hipMemcpyDeviceToHost, s));
+        PF_HIP_TRY(hipStreamSynchronize(s));
+        if (nd >= nv) break;
+        batch = std::min(2 * batch, 64);
+        if (it > (int)nv + 4) {
+          set_error("pf_steiner: in-order resolution did not finish");
+          return PF_ERR_HIP;
+        }
+      }
+      PF_HIP_TRY(exclusive_scan_u32(kept.p, kpos.p, nv, tot.p, s));
+      k_st_emit<<<gr, 256, 0, s>>>(kept.p, kpos.p, nv, vx.p, vr.p, vw.p, tag.p, a, m, cap, out_p, out_power,
+                                   out_radius, out_near, up.p, ur.p, uw.p);
+      PF_HIP_TRY(hipGetLastError());
+      PF_HIP_TRY(hipMemcpyAsync(&nkept, tot.p, sizeof(nkept), hipMemcpyDeviceToHost, s));
+      PF_HIP_TRY(hipStreamSynchronize(s));
+    }
+    const int64_t kept_r = nkept;
+    if (round_counts) round_counts[r] = kept_r;
+    if (a + kept_r > cap) {
       a = cap;
       full = true;
       break;
     }
-    a += kept;
+    a += kept_r;
   }
   *n_out = a;
   if (full) {

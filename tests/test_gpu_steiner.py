@@ -56,9 +56,11 @@ def test_steiner_capacity_and_arguments():
 
 
 def test_steiner_full_size_first_round_sampled():
-    # 1,048,576 cells: the kept set of the first round equals the oracle's
-    # decisions on a sample of candidates, and every sampled kept cell is one
-    # the oracle keeps with the same radius
+    # 1,048,576 cells, one round of 262,144 candidates: the in-order loop
+    # cannot be replayed on the host at this size, so the output is checked
+    # as a fixed point of it on sampled candidates: a sampled candidate is
+    # kept, with the GPU's nearest cell and radius, exactly when the oracle's
+    # test keeps it against the scene plus the cells the GPU kept before it
     _flush("case steiner 1M cells, 1 round of 262144 candidates, 48 sampled")
     sc = W.c3_scene()
     z = W.steiner_draws(1, 262144, seed=5)
@@ -67,19 +69,31 @@ def test_steiner_full_size_first_round_sampled():
     R = sc.radius.astype(np.float64)
     Wt = sc.power.astype(np.float64)
     x = (P.mean(0) + P.std(0) * z[0].astype(np.float64)).astype(np.float32).astype(np.float64)
-    kept = {tuple(v) for v in got["p"].astype(np.float64)}
-    _flush(f"  kept {len(kept)} of {z.shape[1]}")
-    assert len(kept) > 100
+    index = {tuple(v): j for j, v in enumerate(x)}
+    assert len(index) == x.shape[0]                    # candidate points are distinct
+    kept_cand = np.array([index[tuple(v)] for v in got["p"].astype(np.float64)], dtype=np.int64)
+    assert (np.diff(kept_cand) > 0).all()              # kept in candidate order
+    _flush(f"  kept {len(kept_cand)} of {z.shape[1]}")
+    assert len(kept_cand) > 100
+    n = sc.n
     rng = np.random.default_rng(0)
-    sample = rng.choice(z.shape[1], 32, replace=False)
-    keep, r_hat, _, near = oracle.evaluate_candidates(P, R, Wt, x[sample], chunk=4)
-    for j, kj in zip(sample, keep):
-        assert (tuple(x[j]) in kept) == bool(kj), j
-    ks = rng.choice(len(got["p"]), 16, replace=False)
-    keep2, r2, _, near2 = oracle.evaluate_candidates(P, R, Wt, got["p"][ks].astype(np.float64), chunk=4)
-    assert keep2.all()
-    assert np.array_equal(near2, got["near"][ks].astype(np.int64))
-    assert np.array_equal(r2.astype(np.float32), got["radius"][ks])
+    sample = np.concatenate([rng.choice(z.shape[1], 32, replace=False),
+                             kept_cand[rng.choice(len(kept_cand), 16, replace=False)]])
+    for j in sample:
+        before = np.searchsorted(kept_cand, j)           # kept cells ahead of candidate j
+        PP = np.concatenate([P, got["p"][:before].astype(np.float64)])
+        RR = np.concatenate([R, got["radius"][:before].astype(np.float64)])
+        WW = np.concatenate([Wt, got["power"][:before].astype(np.float64)])
+        keep, r_hat, _, near = oracle.evaluate_candidates(PP, RR, WW, x[j:j + 1], chunk=1)
+        is_kept = before < len(kept_cand) and kept_cand[before] == j
+        assert is_kept == bool(keep[0]), j
+        if is_kept:
+            assert int(near[0]) == int(got["near"][before]), j
+            assert np.float32(r_hat[0]) == got["radius"][before], j
+    # the round-start reading would keep a different set on this workload
+    keep0, _, _, _ = oracle.evaluate_candidates(P, R, Wt, x[:4096], chunk=256)
+    first = set(kept_cand[kept_cand < 4096].tolist())
+    _flush(f"  first 4096 candidates: kept in order {len(first)}, judged alone {int(keep0.sum())}")
 
 
 def _augmented(sc, cells):

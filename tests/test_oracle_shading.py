@@ -13,7 +13,13 @@
 * pinhole: the image edge sits at half the vertical field of view;
 * equidistant fisheye: the polar angle equals image radius / f, pixels past
   the image circle are masked;
-* compositing invariants: alpha in [0,1], |C| <= max|c| * A.
+* compositing invariants: alpha in [0,1], |C| <= max|c| * A;
+* distinct detail sites: with a hard soft-Voronoi, the displacement is the
+  site owning the undisplaced hit and the radiance the site owning the
+  displaced hit (hand-computed closed form, Sec. 3.4 Eq. svdisp then
+  Eq. svrad); with a moderate temperature, the displacement blended at the
+  undisplaced hit (computed by hand) gives the dense length that dense point
+  sampling measures.
 """
 import math
 
@@ -148,3 +154,89 @@ def test_composite_invariants():
     assert (rgba[:, 3] >= 0).all() and (rgba[:, 3] <= 1).all()
     cmax = np.abs(sc.rgb).max() + np.abs(sc.tex[:, :, 27:]).max()
     assert (np.abs(rgba[:, :3]).max(axis=1) <= cmax * rgba[:, 3] + 1e-12).all()
+
+
+def _sites_scene(pos, disp, tau, radius=2.0, lam=0.3, seed=5):
+    # one cell at the origin, normal +z (face frame t1 = x, t2 = y), detail
+    # sites at the given face positions with the given displacements, all
+    # Spherical-Voronoi axes zero (each site's colour is the mean of its M
+    # colours) and distinct colours per site
+    rng = np.random.default_rng(seed)
+    tex = np.zeros((1, 8, 51))
+    tex[0, :, 0:2] = pos
+    tex[0, :, 2] = disp
+    tex[0, :, 27:51] = rng.uniform(-1, 1, size=(8, 24))
+    return make_scene([[0, 0, 0]], power=0.0, radius=radius, normal=[[0, 0, 1]], occ_logit=lam,
+                      rgb=[[0.2, 0.5, 0.7]], tex=tex, tau=tau)
+
+
+def test_texture_point_is_the_hit_with_the_displaced_face():
+    # Hard soft-Voronoi (tau = 1e4): the ray o = (5.2, 0, 5), d = (-1, 0, -1)/sqrt(2)
+    # meets the undisplaced face z = 0 at xbar = (0.2, 0, 0), on detail site 0
+    # (d_0 = 0.3), so delta = 0.3 (Eq. svdisp at xbar); the displaced face
+    # z = 0.3 is met at x = (0.5, 0, 0.3), on detail site 1, so the radiance is
+    # site 1's (Eq. svrad at x): rgb + mean_m c_1m.  Evaluating the radiance at
+    # xbar (site 0), or the displacement at x (d_1 = -0.1), changes the result.
+    pos = [[0.2, 0.0], [0.5, 0.0]] + [[-3.0, -3.0]] * 6
+    disp = [0.3, -0.1] + [0.05] * 6
+    sc = _sites_scene(pos, disp, tau=1e4, lam=-3.0)
+    rgba = oracle.render_walk(sc, _cam_line([5.2, 0.0, 5.0], [-1.0, 0.0, -1.0]))[0]
+    # with s the distance along (-1, 0, -1) per unit of x: the sphere |x| <= 2
+    # is crossed for s in [s0, s1], 2 s^2 - 20.4 s + 48.04 = 0; the dense side
+    # z < delta is s > 5 - delta
+    delta = float(np.float32(0.3))
+    s1 = (20.4 + math.sqrt(20.4 ** 2 - 8 * 48.04)) / 4.0
+    ell = math.sqrt(2.0) * (s1 - (5.0 - delta))
+    sigma = 10.0 * math.log1p(math.exp(float(sc.occ_logit[0])))
+    alpha = 1.0 - math.exp(-sigma * ell)
+    cols = sc.tex[0, :, 27:51].astype(np.float64).reshape(8, 8, 3).mean(axis=1)   # per-site colour
+    colour = sc.rgb[0].astype(np.float64) + cols[1]
+    np.testing.assert_allclose(rgba[3], alpha, rtol=0, atol=2e-6)
+    np.testing.assert_allclose(rgba[:3], alpha * colour, rtol=0, atol=2e-6)
+    # the alternatives a plausible slip would give are far away
+    assert np.abs(rgba[:3] - alpha * (sc.rgb[0] + cols[0])).max() > 0.05
+    ell_wrong = math.sqrt(2.0) * (s1 - (5.0 + 0.1))
+    assert abs(rgba[3] - (1.0 - math.exp(-sigma * ell_wrong))) > 0.05
+
+
+def test_displacement_at_the_undisplaced_hit_by_dense_sampling():
+    # Moderate tau = 20, three distinct detail-site positions (site 0, site 1,
+    # and six coincident sites): delta is computed here by hand from the
+    # soft-Voronoi weights at the undisplaced hit xbar (Eq. svdisp), the cell's
+    # dense length is then measured by dense point sampling of
+    # (x - p).n < delta along the ray (no interval formula), and compared with
+    # the opacity the walk gives.
+    pos = [[0.1, 0.0], [-0.1, 0.05]] + [[0.0, -0.2]] * 6
+    disp = [0.25, -0.15] + [0.05] * 6
+    tau = 20.0
+    sc = _sites_scene(pos, disp, tau=tau, lam=-2.0)
+    o = np.array([0.7, 0.3, 4.0])
+    d = np.array([-0.1, 0.05, -1.0])
+    cam = _cam_line(o, d)
+    R0, D0, _ = oracle.generate_rays(cam)
+    o64, d64 = R0.numpy(), D0.numpy()[0]
+    # hand evaluation: xbar on z = 0, weights exp(-tau |ubar - s_k|) / sum
+    tbar = -o64[2] / d64[2]
+    ubar = (o64 + tbar * d64)[:2]
+    s = sc.tex[0, :, 0:2].astype(np.float64)
+    dk = sc.tex[0, :, 2].astype(np.float64)
+    e = np.exp(-tau * np.linalg.norm(ubar[None, :] - s, axis=1))
+    delta = float((e * dk).sum() / e.sum())
+    assert min(abs(delta - v) for v in (0.25, -0.15, 0.05)) > 0.02   # a blend, not one site's value
+    S = scene_tensors(sc)
+    segs = oracle.dense_sample_ray(S, torch.tensor(o64), torch.tensor(d64), 8.0, 2e-5, delta={0: delta})
+    (cell, inside, dense), = segs
+    sigma = 10.0 * math.log1p(math.exp(float(sc.occ_logit[0])))
+    alpha = oracle.render_walk(sc, cam)[0][3]
+    ell_walk = -math.log1p(-alpha) / sigma
+    assert cell == 0
+    assert abs(ell_walk - dense) <= 1e-4
+    # the displacement taken at the displaced hit instead, or none at all,
+    # gives a dense length far outside the sampling error
+    tx = (delta - o64[2]) / d64[2]
+    ux = (o64 + tx * d64)[:2]
+    ex = np.exp(-tau * np.linalg.norm(ux[None, :] - s, axis=1))
+    delta_x = float((ex * dk).sum() / ex.sum())
+    for wrong in (delta_x, 0.0):
+        segw = oracle.dense_sample_ray(S, torch.tensor(o64), torch.tensor(d64), 8.0, 2e-5, delta={0: wrong})
+        assert abs(segw[0][2] - dense) > 2e-3, wrong
