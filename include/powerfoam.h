@@ -33,11 +33,15 @@
  *    pointers to the parameter arrays inside a scene, so they must stay
  *    allocated and unchanged until pf_scene_destroy (re-build after changing
  *    them).  Library-owned memory (adjacency, per-view lists, forward state)
- *    is released by pf_scene_destroy / pf_state_release.  The library keeps
+ *    is released by pf_scene_destroy / pf_state_release.
+ *  - Device memory of the library comes from the caller's allocator when one
+ *    is set (pf_set_allocator), e.g. the framework's caching allocator, so
+ *    that one allocator owns all memory.  Without one, the library keeps
  *    released device blocks in a cache of its own and reuses them
- *    stream-ordered (a reuse waits for an event recorded where the block
- *    was released); blocks go back to the runtime when the cache passes
- *    48 GiB or a device allocation fails.
+ *    stream-ordered (a reuse waits for an event recorded where the block was
+ *    released); blocks go back to the runtime when the cache passes its
+ *    limit (48 GiB, pf_set_cache_limit) or a device allocation fails.
+ *    pf_query_workspace bounds what a call will request.
  *  - Images: a call with ncam cameras writes ncam images back to back into
  *    rgba, image c at float offset 4*sum_{c'<c} W_c'*H_c', each [H][W][4]
  *    (R, G, B, A), pixel (x, y) at row y, column x, sampled at its centre.
@@ -111,7 +115,26 @@ typedef struct {
   int32_t state_mode;        /* forward state: 0 store the contribution
                                 records (default), 1 keep only the cameras and
                                 replay the forward inside pf_backward         */
+  int64_t workspace_limit;   /* bytes the contribution records may occupy at
+                                once (0: no limit).  Store mode: a forward
+                                whose records exceed it keeps only the cameras
+                                (the state becomes a recompute-mode state).
+                                Recompute mode: the backward's replay window
+                                (0: 1 GiB).                                   */
 } pf_render_opts;
+
+/* Caller allocator.  alloc returns a device block of at least `bytes` bytes
+   usable in stream order on `stream` (a hipStream_t), or NULL on failure;
+   free takes back a block from alloc (with the size asked for), after all
+   work the library queued on `stream` so far that uses it: an allocator
+   that reuses blocks in stream order (as a caching allocator does per
+   stream) may hand it out at once on that stream.  Both are called from the
+   thread that makes the library call. */
+typedef struct {
+  void* (*alloc)(void* ctx, size_t bytes, void* stream);
+  void (*free)(void* ctx, void* ptr, size_t bytes, void* stream);
+  void* ctx;
+} pf_allocator;
 
 typedef struct {
   int64_t n;
@@ -173,12 +196,14 @@ void pf_scene_destroy(pf_scene* scene);
    cull each cell's bound into 16x16 tiles, sort each tile's cells by power
    distance from the camera centre (ties: lower index), composite front to
    back.  cams (host) [ncam]; opts (host) may be NULL; rgba as in the
-   conventions.  If state is non-NULL, *state receives a forward state for
-   pf_backward: with opts->state_mode 0 it stores the per-pixel contribution
-   records (about 36 B per contribution), with 1 only the cameras (the
-   records are rebuilt inside pf_backward).  Synchronises the stream (pair
-   list and record pool sizing).
-   Errors: INVALID (ncam < 1, bad camera, state_mode not 0/1), OOM, HIP. */
+   conventions.  If state is non-NULL (at most 4096 cameras), *state
+   receives a forward state for pf_backward: with opts->state_mode 0 it
+   stores the per-pixel contribution records (about 36 B per contribution),
+   unless they exceed opts->workspace_limit; with 1 (or past the limit) only
+   the cameras, and pf_backward replays the forward.  Synchronises the
+   stream (pair list and record pool sizing).
+   Errors: INVALID (ncam < 1, bad camera, state_mode not 0/1, negative
+   workspace_limit, more than 4096 cameras with a state), OOM, HIP. */
 pf_status pf_render_raster(pf_scene* scene, const pf_camera* cams, int32_t ncam,
                            const pf_render_opts* opts, float* rgba,
                            pf_fwd_state** state, void* stream);
@@ -227,10 +252,16 @@ typedef struct {
    grads (host struct of device pointers).  opts (host) may be NULL.  A
    store-mode state is consumed (its records are overwritten): a second
    pf_backward on it fails with INVALID.  A recompute-mode state replays its
-   forward with records (temporary memory as for store mode), synchronises
-   the stream, and may be used again.
+   forward in windows of consecutive 16x16 tiles: each window's records are
+   written into one pool of at most the state's workspace_limit bytes (1 GiB
+   without a limit), differentiated, and dropped before the next window is
+   replayed, so the memory does not grow with the number of contributions
+   (a window whose records do not fit is halved and replayed).  It
+   synchronises the stream once per window and may be used again.  The
+   gradients equal the store-mode ones up to the order of float atomic adds.
    Errors: INVALID (NULL argument, state/scene mismatch, consumed state,
-   non-finite lambda_normal), OOM, HIP. */
+   non-finite lambda_normal), OOM (also: one tile's records exceed the
+   limit), HIP. */
 pf_status pf_backward(pf_scene* scene, pf_fwd_state* state, const float* d_rgba,
                       const pf_grads* grads, const pf_backward_opts* opts, void* stream);
 
@@ -333,17 +364,45 @@ pf_status pf_densify_prune(const pf_params* params, const float* err_ema, const 
                            const pf_cell_arrays* out, float* out_err, float* out_contrib, int32_t* out_parent,
                            int64_t* n_kept, int64_t* n_drawn, void* stream);
 
-/* Device memory estimate (bytes, host output) of a render of cams (what 0),
-   of a render with a store-mode forward state (what 1), or of that plus the
-   backward's workspace (what 2), from the scene's sizing hints (pair and
-   record counts of its last renders; defaults before the first).  An
-   estimate for admission control, not a bound.  Errors: INVALID. */
-pf_status pf_query_workspace(const pf_scene* scene, const pf_camera* cams, int32_t ncam,
-                             int32_t what, int64_t* bytes);
+/* Upper bound on the device bytes the library requests for a raster call
+   sequence on `scene` with cameras cams (host) [ncam] and options opts
+   (host, may be NULL): what 0, pf_render_raster without a state; what 1,
+   pf_render_raster with a state in opts->state_mode; what 2, that state's
+   pf_render_raster followed by pf_backward.  The bound counts the bytes the
+   library asks its allocator for (the caller's allocator, or its cache,
+   which rounds a block up by at most 1/16) that are in use at once during
+   the calls, beyond the scene itself.  It is exact in the pair lists: the
+   call runs the per-view cull-and-count pass of the rasteriser (one launch
+   per group of views, its own temporary memory at most the bound of what 0)
+   and synchronises the stream.  For a store-mode state without a
+   workspace_limit the records are sized from the scene's last renders, so
+   the value is an estimate, not a bound; with a limit, or in recompute mode,
+   it is a bound.  Errors: INVALID (NULL argument, ncam < 1, bad camera,
+   bad what or options), OOM, HIP. */
+pf_status pf_query_workspace(pf_scene* scene, const pf_camera* cams, int32_t ncam, int32_t what,
+                             const pf_render_opts* opts, void* stream, int64_t* bytes);
+
+/* Sets the caller's allocator for all later device allocations of the
+   library (process-wide; NULL restores the library's own cache).  Blocks
+   already handed out go back to the allocator that gave them.  Setting an
+   allocator returns the cache's free blocks to the runtime.
+   Errors: INVALID (alloc or free missing). */
+pf_status pf_set_allocator(const pf_allocator* alloc);
+
+/* Limit of the library's own block cache in bytes (default 48 GiB; blocks
+   past it go back to the runtime at once).  Errors: INVALID (bytes < 0). */
+pf_status pf_set_cache_limit(int64_t bytes);
+
+/* Requested bytes of the library's device blocks in use now (*live), their
+   high-water mark since the last reset (*peak), and the bytes held free in
+   the library's cache (*cached); any pointer may be NULL.  reset_peak != 0
+   sets the high-water mark to the bytes in use. */
+pf_status pf_memory_stats(int64_t* live, int64_t* peak, int64_t* cached, int32_t reset_peak);
 
 /* Number of contribution records (pixel-cell pairs with alpha > 0) and of
-   pixels in a forward state (host outputs). */
-pf_status pf_state_info(const pf_fwd_state* state, int64_t* n_records, int64_t* n_pixels);
+   pixels in a forward state, and its mode (0 store, 1 recompute; may be
+   NULL) (host outputs).  A recompute-mode state holds no records (0). */
+pf_status pf_state_info(const pf_fwd_state* state, int64_t* n_records, int64_t* n_pixels, int32_t* mode);
 
 /* Kernel timing for measurement.  While enabled (on != 0), every kernel the
    library launches is bracketed by HIP events on its stream; pf_profile_read

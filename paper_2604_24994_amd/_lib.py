@@ -13,7 +13,8 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "OOM", 3: "HIP", 4: "UNSUPPORTED", 5: 
 EXPORTS = ("pf_build_scene", "pf_scene_info_get", "pf_scene_adjacency", "pf_scene_destroy",
            "pf_render_raster", "pf_render_trace", "pf_backward", "pf_state_release", "pf_last_error",
            "pf_profile_enable", "pf_profile_read", "pf_state_info", "pf_update_scene", "pf_query_workspace",
-           "pf_connect_loss", "pf_steiner", "pf_ema_update", "pf_densify_prune")
+           "pf_connect_loss", "pf_steiner", "pf_ema_update", "pf_densify_prune", "pf_set_allocator",
+           "pf_set_cache_limit", "pf_memory_stats")
 
 
 class PfParams(C.Structure):
@@ -35,7 +36,16 @@ class PfBuildOpts(C.Structure):
 
 
 class PfRenderOpts(C.Structure):
-    _fields_ = [("t_min", C.c_float), ("max_steps", C.c_int32), ("state_mode", C.c_int32)]
+    _fields_ = [("t_min", C.c_float), ("max_steps", C.c_int32), ("state_mode", C.c_int32),
+                ("workspace_limit", C.c_int64)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+
+
+class PfAllocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
 
 
 class PfSceneInfo(C.Structure):
@@ -98,7 +108,11 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.pf_render_trace.argtypes = [vp, C.POINTER(PfCamera), i32, C.POINTER(PfRenderOpts), vp,
                                     C.POINTER(i64), C.POINTER(vp), vp]
     lib.pf_update_scene.argtypes = [vp, C.POINTER(PfParams), vp]
-    lib.pf_query_workspace.argtypes = [vp, C.POINTER(PfCamera), i32, i32, C.POINTER(i64)]
+    lib.pf_query_workspace.argtypes = [vp, C.POINTER(PfCamera), i32, i32, C.POINTER(PfRenderOpts), vp,
+                                       C.POINTER(i64)]
+    lib.pf_set_allocator.argtypes = [C.POINTER(PfAllocator)]
+    lib.pf_set_cache_limit.argtypes = [i64]
+    lib.pf_memory_stats.argtypes = [C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), i32]
     lib.pf_connect_loss.argtypes = [vp, C.c_float, C.POINTER(PfGrads), vp, vp]
     lib.pf_steiner.argtypes = [C.POINTER(PfParams), vp, C.POINTER(PfSteinerOpts), i64, vp, vp, vp, vp,
                                C.POINTER(i64), C.POINTER(i64), vp]
@@ -108,7 +122,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.pf_backward.argtypes = [vp, vp, vp, C.POINTER(PfGrads), C.POINTER(PfBackwardOpts), vp]
     lib.pf_state_release.argtypes = [vp]
     lib.pf_state_release.restype = None
-    lib.pf_state_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
+    lib.pf_state_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)]
     lib.pf_profile_enable.argtypes = [i32]
     lib.pf_profile_read.argtypes = [C.POINTER(PfProfileEntry), i32, C.POINTER(i32)]
     lib.pf_last_error.argtypes = []

@@ -157,10 +157,11 @@ def update_scene(scene: Scene, params, stream=None) -> Scene:
 STORE, RECOMPUTE = 0, 1
 
 
-def _opts(t_min: float, max_steps: int, state_mode: int = STORE) -> L.PfRenderOpts:
+def _opts(t_min: float, max_steps: int, state_mode: int = STORE, workspace_limit: int = 0) -> L.PfRenderOpts:
     if state_mode not in (STORE, RECOMPUTE):
         raise ValueError("state_mode must be STORE (0) or RECOMPUTE (1)")
-    return L.PfRenderOpts(t_min=float(t_min), max_steps=int(max_steps), state_mode=int(state_mode))
+    return L.PfRenderOpts(t_min=float(t_min), max_steps=int(max_steps), state_mode=int(state_mode),
+                          workspace_limit=int(workspace_limit))
 
 
 def _alloc_images(shapes, device):
@@ -217,9 +218,10 @@ class ForwardState:
         return self._h
 
     def info(self) -> dict:
-        nr, npx = C.c_int64(0), C.c_int64(0)
-        L.check(L.load().pf_state_info(self.handle, C.byref(nr), C.byref(npx)))
-        return {"records": int(nr.value), "pixels": int(npx.value)}
+        nr, npx, mode = C.c_int64(0), C.c_int64(0), C.c_int32(0)
+        L.check(L.load().pf_state_info(self.handle, C.byref(nr), C.byref(npx), C.byref(mode)))
+        return {"records": int(nr.value), "pixels": int(npx.value),
+                "mode": "store" if mode.value == STORE else "recompute"}
 
     def release(self):
         if self._h:
@@ -234,11 +236,14 @@ class ForwardState:
 
 
 def render_raster_state(scene: Scene, cams, t_min: float = 1e-6, stream=None, out: Optional[torch.Tensor] = None,
-                        state_mode: int = STORE):
-    """pf_render_raster with a forward state: (flat RGBA buffer, ForwardState)."""
+                        state_mode: int = STORE, workspace_limit: int = 0):
+    """pf_render_raster with a forward state: (flat RGBA buffer, ForwardState).
+    ``workspace_limit``: bytes the records may occupy (store mode: past it
+    the state keeps only the cameras; recompute mode: the backward's replay
+    window)."""
     arr, nc, shapes = _cams(cams)
     buf = out if out is not None else _alloc_images(shapes, scene.params["p"].device)
-    opts = _opts(t_min, 0, state_mode)
+    opts = _opts(t_min, 0, state_mode, workspace_limit)
     h = C.c_void_p()
     L.check(L.load().pf_render_raster(scene.handle, arr, nc, C.byref(opts), C.c_void_p(buf.data_ptr()),
                                       C.byref(h), C.c_void_p(_stream_ptr(stream))))
@@ -246,11 +251,11 @@ def render_raster_state(scene: Scene, cams, t_min: float = 1e-6, stream=None, ou
 
 
 def render_trace_state(scene: Scene, cams, t_min: float = 1e-6, max_steps: int = 4096, stream=None,
-                       out: Optional[torch.Tensor] = None, state_mode: int = STORE):
+                       out: Optional[torch.Tensor] = None, state_mode: int = STORE, workspace_limit: int = 0):
     """pf_render_trace with a forward state: (flat RGBA buffer, ForwardState)."""
     arr, nc, shapes = _cams(cams)
     buf = out if out is not None else _alloc_images(shapes, scene.params["p"].device)
-    opts = _opts(t_min, max_steps, state_mode)
+    opts = _opts(t_min, max_steps, state_mode, workspace_limit)
     h = C.c_void_p()
     L.check(L.load().pf_render_trace(scene.handle, arr, nc, C.byref(opts), C.c_void_p(buf.data_ptr()), None,
                                      C.byref(h), C.c_void_p(_stream_ptr(stream))))
@@ -274,13 +279,67 @@ def connect_loss(scene: Scene, lam: float, grads: Optional[Dict[str, torch.Tenso
     return val
 
 
-def query_workspace(scene: Scene, cams, what: int = 0) -> int:
-    """pf_query_workspace: estimated device bytes of a render (0), a render
-    with a store-mode state (1), or that plus the backward (2)."""
+def query_workspace(scene: Scene, cams, what: int = 0, state_mode: int = STORE, workspace_limit: int = 0,
+                    stream=None) -> int:
+    """pf_query_workspace: upper bound on the device bytes the library asks
+    for during a raster render (what 0), a render with a state of
+    ``state_mode`` (1), or that render and its backward (2).  Runs the
+    rasteriser's cull-and-count pass on ``stream`` and waits for it."""
     arr, nc, _ = _cams(cams)
     b = C.c_int64(0)
-    L.check(L.load().pf_query_workspace(scene.handle, arr, nc, int(what), C.byref(b)))
+    opts = _opts(1e-6, 0, state_mode, workspace_limit)
+    L.check(L.load().pf_query_workspace(scene.handle, arr, nc, int(what), C.byref(opts),
+                                        C.c_void_p(_stream_ptr(stream)), C.byref(b)))
     return int(b.value)
+
+
+_ALLOCATOR = {}   # the installed callbacks (kept alive while installed)
+
+
+def use_torch_allocator(device=None) -> None:
+    """Routes every device allocation of the library through PyTorch's
+    caching allocator (pf_set_allocator), on the stream of each library call,
+    so that one allocator owns all device memory.  A failed allocation makes
+    the library call return OOM."""
+    _require_cuda()
+    dev = torch.cuda.current_device() if device is None else torch.device(device).index
+
+    def _alloc(ctx, nbytes, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream or 0))
+        except Exception:   # noqa: BLE001 - out of memory: the library reports OOM
+            return None
+
+    def _free(ctx, ptr, nbytes, stream):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    a = L.PfAllocator(L.ALLOC_FN(_alloc), L.FREE_FN(_free), None)
+    L.check(L.load().pf_set_allocator(C.byref(a)))
+    _ALLOCATOR["active"] = a
+
+
+def set_allocator(alloc_fn, free_fn) -> None:
+    """Installs Python callables as the library's allocator:
+    ``alloc_fn(nbytes, stream) -> int`` (device pointer, 0 on failure) and
+    ``free_fn(ptr, nbytes, stream)``."""
+    a = L.PfAllocator(L.ALLOC_FN(lambda ctx, n, st: alloc_fn(int(n), int(st or 0)) or None),
+                      L.FREE_FN(lambda ctx, p, n, st: free_fn(int(p), int(n), int(st or 0))), None)
+    L.check(L.load().pf_set_allocator(C.byref(a)))
+    _ALLOCATOR["active"] = a
+
+
+def use_library_allocator() -> None:
+    """Restores the library's own block cache (pf_set_allocator(NULL))."""
+    L.check(L.load().pf_set_allocator(None))
+    _ALLOCATOR.pop("active", None)
+
+
+def memory_stats(reset_peak: bool = False) -> dict:
+    """pf_memory_stats: requested bytes of the library's device blocks in
+    use, their high-water mark, and the bytes its cache holds."""
+    live, peak, cached = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+    L.check(L.load().pf_memory_stats(C.byref(live), C.byref(peak), C.byref(cached), 1 if reset_peak else 0))
+    return {"live": int(live.value), "peak": int(peak.value), "cached": int(cached.value)}
 
 
 def backward(scene: Scene, state: ForwardState, d_rgba: torch.Tensor, grads: Dict[str, torch.Tensor],

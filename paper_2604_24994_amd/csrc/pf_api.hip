@@ -1,6 +1,7 @@
 // C ABI entry points: argument checks, error text, handle lifetime.
 #include <algorithm>
 #include <atomic>
+#include <functional>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -33,18 +34,56 @@ struct pf_fwd_state {
   bool consumed = false; // store mode: pf_backward has overwritten the records
   float t_min = 1e-6f;
   int max_steps = 4096;
+  int64_t limit = 0;     // workspace limit of the render options (0: none)
   hipStream_t stream = nullptr;   // the stream it was rendered on: its memory is freed there
 };
 
 namespace {
-void free_state_mem(pf_fwd_state* s) {
-  void* ptrs[] = {s->st.rec.ri,      s->st.rec.rf,  s->st.rec.rt,    s->st.rec.head,
-                  s->st.rec.counter, s->st.rec.seg, s->st.rec.wtail, s->st.cams_dev};
+void free_records(pf::RecBuf& r, hipStream_t s) {
+  void* ptrs[] = {r.ri, r.rf, r.rt, r.head, r.counter, r.seg, r.wtail};
   for (void* q : ptrs)
-    if (q) pf::pool_free(q, s->stream);
-  s->st.rec = pf::RecBuf{};
+    if (q) pf::pool_free(q, s);
+  r = pf::RecBuf{};
+}
+
+void free_state_mem(pf_fwd_state* s) {
+  free_records(s->st.rec, s->stream);
+  if (s->st.cams_dev) pf::pool_free(s->st.cams_dev, s->stream);
   s->st.cams_dev = nullptr;
 }
+
+// Device bytes of a record pool of cap record slots and seg_cap segment slots.
+constexpr int64_t REC_BYTES = sizeof(int4) + sizeof(float4) + sizeof(float);   // 36
+constexpr int64_t SEG_BYTES = sizeof(int4);                                    // 16
+constexpr int64_t DEFAULT_WINDOW = int64_t(1) << 30;   // recompute window without a limit
+
+struct Caps {
+  int64_t cap = 0, seg_cap = 0;
+};
+
+// Segment slots per record slot: one per record for the walk, else the
+// scene's ratio of its last raster (at least 1/16).
+double seg_ratio(const pf::Scene& sc, int kind) {
+  if (kind == 1) return 1.0;
+  const double rpp = sc.rec_per_pixel > 0.0 ? sc.rec_per_pixel : g_rec_hint.load();
+  const double spp = sc.rec_per_pixel > 0.0 ? sc.seg_per_pixel : g_seg_hint.load();
+  return std::min(1.0, std::max(1.0 / 16.0, spp / std::max(rpp, 1e-9)));
+}
+
+// The largest pool of at most `bytes`.
+Caps caps_within(int64_t bytes, double ratio) {
+  Caps c;
+  c.cap = std::max<int64_t>(1, (int64_t)((double)bytes / ((double)REC_BYTES + SEG_BYTES * ratio)));
+  c.cap = std::min<int64_t>(c.cap, INT32_MAX - 1);
+  c.seg_cap = std::max<int64_t>(1, std::min<int64_t>((int64_t)(ratio * (double)c.cap), INT32_MAX - 1));
+  while (c.cap * REC_BYTES + c.seg_cap * SEG_BYTES > bytes && c.cap > 1) {
+    c.cap -= 1 + c.cap / 64;
+    c.seg_cap = std::max<int64_t>(1, (int64_t)(ratio * (double)c.cap));
+  }
+  return c;
+}
+
+int64_t pool_bytes(const Caps& c) { return c.cap * REC_BYTES + c.seg_cap * SEG_BYTES; }
 }  // namespace
 
 namespace pf {
@@ -233,7 +272,7 @@ pf_status run_pass(pf_scene* scene, const std::vector<pf_camera>& cams, int kind
 
 // New state with the cameras on the device (no records yet).
 pf_status new_state(pf_scene* scene, const pf_camera* cams, int32_t ncam, int kind, int mode, float t_min,
-                    int max_steps, hipStream_t s, pf_fwd_state** out, const char* who) {
+                    int max_steps, int64_t limit, hipStream_t s, pf_fwd_state** out, const char* who) {
   *out = nullptr;
   // the records store the view in 12 bits (pf_record.hpp)
   if (ncam > pf::REC_MAX_VIEWS) return invalid(std::string(who) + ": at most 4096 cameras per call with a forward state");
@@ -248,11 +287,12 @@ pf_status new_state(pf_scene* scene, const pf_camera* cams, int32_t ncam, int ki
   fs->mode = mode;
   fs->t_min = t_min;
   fs->max_steps = max_steps;
+  fs->limit = limit;
   fs->stream = s;
   int64_t npix = 0, ntiles = 0;
   for (int c = 0; c < ncam; ++c) {
     npix += (int64_t)cams[c].width * cams[c].height;
-    ntiles += (int64_t)((cams[c].width + pf::TILE - 1) / pf::TILE) * ((cams[c].height + pf::TILE - 1) / pf::TILE);
+    ntiles += pf::view_tiles(cams[c]);
   }
   fs->st.npix = npix;
   fs->st.ncam = ncam;
@@ -269,88 +309,246 @@ pf_status new_state(pf_scene* scene, const pf_camera* cams, int32_t ncam, int ki
   return PF_OK;
 }
 
-// Runs the state's pass with records.  The record pool and segment list are
-// sized from the last store-mode forward of this scene (else of any scene in
-// the process); a pass that runs out of room is repeated once with the
-// exact sizes.  rgba receives the image; trunc_dev (walk only) is zeroed
-// before each attempt.
+pf_status hip_status(hipError_t e, const char* who) {
+  pf::set_error(std::string(who) + ": " + hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? PF_ERR_OOM : PF_ERR_HIP;
+}
+
+// Per-pixel heads and counters of a record buffer; wtail_tiles raster tiles
+// of segment tails (0: none, the walk).
+pf_status alloc_record_meta(pf::RecBuf& r, int64_t npix, int64_t wtail_tiles, hipStream_t s, const char* who) {
+  hipError_t e = pf::pool_alloc((void**)&r.head, sizeof(int32_t) * npix, s);
+  if (e == hipSuccess) e = pf::pool_alloc((void**)&r.counter, 3 * sizeof(unsigned long long), s);
+  if (e == hipSuccess && wtail_tiles > 0) e = pf::pool_alloc((void**)&r.wtail, sizeof(int2) * 4 * wtail_tiles, s);
+  return e == hipSuccess ? PF_OK : hip_status(e, who);
+}
+
+pf_status alloc_pool(pf::RecBuf& r, const Caps& c, hipStream_t s, const char* who) {
+  r.cap = c.cap;
+  r.seg_cap = c.seg_cap;
+  hipError_t e = pf::pool_alloc((void**)&r.ri, sizeof(int4) * c.cap, s);
+  if (e == hipSuccess) e = pf::pool_alloc((void**)&r.rf, sizeof(float4) * c.cap, s);
+  if (e == hipSuccess) e = pf::pool_alloc((void**)&r.rt, sizeof(float) * c.cap, s);
+  if (e == hipSuccess) e = pf::pool_alloc((void**)&r.seg, sizeof(int4) * c.seg_cap, s);
+  return e == hipSuccess ? PF_OK : hip_status(e, who);
+}
+
+void free_pool(pf::RecBuf& r, hipStream_t s) {
+  void* pool[] = {r.ri, r.rf, r.rt, r.seg};
+  for (void* q : pool)
+    if (q) pf::pool_free(q, s);
+  r.ri = nullptr;
+  r.rf = nullptr;
+  r.rt = nullptr;
+  r.seg = nullptr;
+}
+
+// Clears the pool's counters (and, for the walk, its segment slots: unused
+// slots of a wave's blocks must read as empty) before a pass.
+pf_status reset_pool(pf::RecBuf& r, bool walk, hipStream_t s, const char* who) {
+  hipError_t e = hipMemsetAsync(r.counter, 0, 3 * sizeof(unsigned long long), s);
+  if (e == hipSuccess && walk) e = hipMemsetAsync(r.seg, 0, sizeof(int4) * r.seg_cap, s);
+  return e == hipSuccess ? PF_OK : hip_status(e, who);
+}
+
+// After a pass: slots reserved (records, segments) and, if they fit, the
+// records the segments list.  Synchronises the stream.
+pf_status pool_usage(pf::RecBuf& r, hipStream_t s, unsigned long long used[3], const char* who) {
+  used[0] = used[1] = used[2] = 0;
+  hipError_t e = hipMemcpyAsync(used, r.counter, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_status(e, who);
+  if ((int64_t)used[0] <= r.cap && (int64_t)used[1] <= r.seg_cap) {
+    const pf_status st = pf::seg_record_total(r.seg, (int64_t)used[1], r.counter + 2, s);
+    if (st != PF_OK) return st;
+    e = hipMemcpyAsync(used + 2, r.counter + 2, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_status(e, who);
+  }
+  return PF_OK;
+}
+
+// Record and segment slots for a store-mode pass, from the scene's last
+// raster (else any scene's), in coarse steps so that steps of similar size
+// ask for the same block sizes; within `limit` bytes when one is set.
+Caps store_caps(const pf_fwd_state* fs, int64_t need_rec, int64_t need_seg) {
+  const pf::Scene& sc = fs->scene->s;
+  const double npix = (double)fs->st.npix;
+  const bool seen = sc.rec_per_pixel > 0.0;
+  const double rpp = seen ? sc.rec_per_pixel : g_rec_hint.load();
+  const double spp = seen ? sc.seg_per_pixel : g_seg_hint.load();
+  auto coarse = [](int64_t x, int64_t step) { return (x + step - 1) / step * step; };
+  Caps c;
+  c.cap = coarse(std::max<int64_t>((int64_t)(rpp * npix), need_rec) + 4096, 1 << 22);
+  c.seg_cap = coarse(std::max<int64_t>((int64_t)(spp * npix), need_seg) + 4096, 1 << 20);
+  if (fs->kind == 1) c.seg_cap = std::max(c.seg_cap, c.cap);   // one segment per record on the walk
+  // record and segment indices are stored as 32-bit integers
+  c.cap = std::min<int64_t>(c.cap, INT32_MAX - 1);
+  c.seg_cap = std::min<int64_t>(c.seg_cap, INT32_MAX - 1);
+  if (fs->limit > 0 && pool_bytes(c) > fs->limit) c = caps_within(fs->limit, seg_ratio(sc, fs->kind));
+  return c;
+}
+
+// Runs the state's pass with records (store mode).  A pass that runs out of
+// room is repeated once with the exact sizes; when the records do not fit
+// the state's workspace limit, the state becomes a recompute-mode state
+// (*demoted = true; the image of the pass is complete either way).  rgba
+// receives the image; trunc_dev (walk only) is zeroed before each attempt.
 pf_status fill_records(pf_fwd_state* fs, float* rgba, unsigned long long* trunc_dev, hipStream_t s,
-                       const char* who) {
+                       const char* who, bool* demoted) {
+  *demoted = false;
   pf_scene* scene = fs->scene;
   const int64_t npix = fs->st.npix;
-  hipError_t e = pf::pool_alloc((void**)&fs->st.rec.head, sizeof(int32_t) * npix, s);
-  if (e == hipSuccess) e = pf::pool_alloc((void**)&fs->st.rec.counter, 3 * sizeof(unsigned long long), s);
-  // the raster lists each wave's last segment block (4 waves per tile)
-  if (e == hipSuccess && fs->kind == 0) e = pf::pool_alloc((void**)&fs->st.rec.wtail, sizeof(int2) * 4 * fs->st.ntiles, s);
-  if (e != hipSuccess) {
-    pf::set_error(std::string(who) + ": " + hipGetErrorString(e));
-    return e == hipErrorOutOfMemory ? PF_ERR_OOM : PF_ERR_HIP;
-  }
-  const bool seen = scene->s.rec_per_pixel > 0.0;
-  const double rpp = seen ? scene->s.rec_per_pixel : g_rec_hint.load();
-  const double spp = seen ? scene->s.seg_per_pixel : g_seg_hint.load();
-  // capacities in coarse steps, so that steps of similar size ask the
-  // memory pool for the same block sizes and reuse them
-  auto coarse = [](int64_t x, int64_t step) { return (x + step - 1) / step * step; };
-  int64_t cap = coarse((int64_t)(rpp * (double)npix) + 4096, 1 << 22);
-  int64_t seg_cap = coarse((int64_t)(spp * (double)npix) + 4096, 1 << 20);
-  if (fs->kind == 1) seg_cap = std::max(seg_cap, cap);   // one segment per record on the walk
+  pf_status st = alloc_record_meta(fs->st.rec, npix, fs->kind == 0 ? fs->st.ntiles : 0, s, who);
+  if (st != PF_OK) return st;
+  Caps c = store_caps(fs, 0, 0);
   for (int attempt = 0; attempt < 2; ++attempt) {
-    // record and segment indices are stored as 32-bit integers
-    cap = std::min<int64_t>(cap, INT32_MAX - 1);
-    seg_cap = std::min<int64_t>(seg_cap, INT32_MAX - 1);
-    fs->st.rec.cap = cap;
-    fs->st.rec.seg_cap = seg_cap;
-    e = pf::pool_alloc((void**)&fs->st.rec.ri, sizeof(int4) * cap, s);
-    if (e == hipSuccess) e = pf::pool_alloc((void**)&fs->st.rec.rf, sizeof(float4) * cap, s);
-    if (e == hipSuccess) e = pf::pool_alloc((void**)&fs->st.rec.rt, sizeof(float) * cap, s);
-    if (e == hipSuccess) e = pf::pool_alloc((void**)&fs->st.rec.seg, sizeof(int4) * seg_cap, s);
-    if (e == hipSuccess) e = hipMemsetAsync(fs->st.rec.counter, 0, 3 * sizeof(unsigned long long), s);
-    if (e == hipSuccess && fs->kind == 1) e = hipMemsetAsync(fs->st.rec.seg, 0, sizeof(int4) * seg_cap, s);
-    if (e == hipSuccess && trunc_dev) e = hipMemsetAsync(trunc_dev, 0, sizeof(unsigned long long), s);
-    if (e != hipSuccess) {
-      pf::set_error(std::string(who) + ": record pool: " + hipGetErrorString(e));
-      return e == hipErrorOutOfMemory ? PF_ERR_OOM : PF_ERR_HIP;
+    st = alloc_pool(fs->st.rec, c, s, who);
+    if (st == PF_OK) st = reset_pool(fs->st.rec, fs->kind == 1, s, who);
+    if (st == PF_OK && trunc_dev) {
+      const hipError_t e = hipMemsetAsync(trunc_dev, 0, sizeof(unsigned long long), s);
+      if (e != hipSuccess) st = hip_status(e, who);
     }
-    pf_status st = run_pass(scene, fs->cams, fs->kind, fs->t_min, fs->max_steps, rgba, trunc_dev, s, &fs->st.rec);
+    if (st == PF_OK) st = run_pass(scene, fs->cams, fs->kind, fs->t_min, fs->max_steps, rgba, trunc_dev, s, &fs->st.rec);
+    unsigned long long used[3];
+    if (st == PF_OK) st = pool_usage(fs->st.rec, s, used, who);
     if (st != PF_OK) return st;
-    unsigned long long used[3] = {0, 0, 0};
-    e = hipMemcpyAsync(used, fs->st.rec.counter, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e == hipSuccess && (int64_t)used[0] <= cap && (int64_t)used[1] <= seg_cap) {
-      st = pf::seg_record_total(fs->st.rec.seg, (int64_t)used[1], fs->st.rec.counter + 2, s);
-      if (st != PF_OK) return st;
-      e = hipMemcpyAsync(used + 2, fs->st.rec.counter + 2, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+    if (used[0] >= (unsigned long long)INT32_MAX || used[1] >= (unsigned long long)INT32_MAX) {
+      if (fs->limit > 0) break;   // recompute in windows instead
+      return invalid(std::string(who) + ": more than 2^31 - 2 contributions or segments in one call; render fewer "
+                                        "views or set a workspace limit");
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
-      pf::set_error(std::string(who) + ": " + hipGetErrorString(e));
-      return PF_ERR_HIP;
-    }
-    if (used[0] >= (unsigned long long)INT32_MAX || used[1] >= (unsigned long long)INT32_MAX)
-      return invalid(std::string(who) + ": more than 2^31 - 2 contributions or segments in one call; render fewer views");
     if (fs->kind == 0) {
       scene->s.rec_per_pixel = 1.05 * (double)used[0] / (double)npix;
       scene->s.seg_per_pixel = 1.05 * (double)used[1] / (double)npix;
       g_rec_hint.store(scene->s.rec_per_pixel);
       g_seg_hint.store(scene->s.seg_per_pixel);
     }
-    if ((int64_t)used[0] <= cap && (int64_t)used[1] <= seg_cap) {
+    if ((int64_t)used[0] <= c.cap && (int64_t)used[1] <= c.seg_cap) {
       fs->st.nrec = (int64_t)used[2];
       fs->st.nseg = (int64_t)used[1];
       return PF_OK;
     }
-    void* pool[] = {fs->st.rec.ri, fs->st.rec.rf, fs->st.rec.rt, fs->st.rec.seg};
-    for (void* q : pool) pf::pool_free(q, s);
-    fs->st.rec.ri = nullptr;
-    fs->st.rec.rf = nullptr;
-    fs->st.rec.rt = nullptr;
-    fs->st.rec.seg = nullptr;
-    cap = std::max(cap, coarse((int64_t)used[0] + 4096, 1 << 22));
-    seg_cap = std::max(seg_cap, coarse((int64_t)used[1] + 4096, 1 << 20));
+    free_pool(fs->st.rec, s);
+    const Caps exact = store_caps(fs, (int64_t)used[0], (int64_t)used[1]);
+    if (exact.cap < (int64_t)used[0] || exact.seg_cap < (int64_t)used[1]) break;   // over the limit
+    c = exact;
+  }
+  if (fs->limit > 0) {
+    // the records do not fit the limit: keep the cameras only and replay
+    // the pass in windows inside pf_backward
+    free_records(fs->st.rec, s);
+    fs->mode = 1;
+    fs->st.nrec = fs->st.nseg = 0;
+    *demoted = true;
+    return PF_OK;
   }
   pf::set_error(std::string(who) + ": record pool sizing failed");
   return PF_ERR_HIP;
+}
+
+// Record window of a recompute-mode backward: the state's workspace limit,
+// else DEFAULT_WINDOW.
+Caps window_caps(const pf_fwd_state* fs) {
+  return caps_within(fs->limit > 0 ? fs->limit : DEFAULT_WINDOW, seg_ratio(fs->scene->s, fs->kind));
+}
+
+// Recompute-mode backward: the state's pass is replayed over windows of
+// consecutive tiles whose records fit one bounded pool, and each window's
+// records are differentiated and released before the next window is
+// replayed.  A window whose records overflow the pool is split in two and
+// replayed.  Peak memory: the binned lists of one group of views, the
+// window's pool and the backward's workspace for it, one scratch image and
+// the per-pixel heads.
+pf_status backward_windows(pf_fwd_state* fs, const float* d_rgba, const pf_grads& g, const pf::BwdOpts& bo,
+                           hipStream_t s) {
+  const char* who = "pf_backward";
+  pf::Scene& sc = fs->scene->s;
+  const int64_t npix = fs->st.npix;
+  const Caps c = window_caps(fs);
+  // a window's tiles from the expected records per tile
+  const double rpp = sc.rec_per_pixel > 0.0 ? sc.rec_per_pixel : g_rec_hint.load();
+  const int64_t est_tiles = std::max<int64_t>(1, (int64_t)((double)c.cap / (1.25 * rpp * pf::TILE * pf::TILE)));
+  const bool walk = fs->kind == 1;
+  int64_t max_tiles = 0;   // tiles of the largest launch (wave segment tails)
+  for (const pf_camera& cam : fs->cams) max_tiles = std::max(max_tiles, pf::view_tiles(cam));
+  max_tiles = std::min<int64_t>(walk ? max_tiles : fs->st.ntiles, 4 * est_tiles);
+
+  pf::BwdState w;
+  w.npix = npix;
+  w.ncam = fs->st.ncam;
+  w.cams_dev = fs->st.cams_dev;
+  float* scratch = nullptr;
+  unsigned long long* trunc = nullptr;
+  hipError_t e = pf::pool_alloc((void**)&scratch, sizeof(float) * 4 * npix, s);
+  if (e == hipSuccess && walk) e = pf::pool_alloc((void**)&trunc, sizeof(unsigned long long), s);
+  pf_status st = e == hipSuccess ? PF_OK : hip_status(e, who);
+  if (st == PF_OK) st = alloc_record_meta(w.rec, npix, walk ? 0 : max_tiles, s, who);
+  if (st == PF_OK) st = alloc_pool(w.rec, c, s, who);
+
+  // one window [first, first + count) of a launch over a group's (or a
+  // view's) tiles; global_first: its first tile among all views' tiles
+  using Launch = std::function<pf_status(int64_t first, int64_t count)>;
+  // windows are sized from the records per tile seen so far (first: the
+  // scene's records per pixel); a window that overflows is halved
+  double per_window = (double)std::min(max_tiles, est_tiles);
+  auto windows = [&](int64_t ntiles, int64_t global_first, const Launch& launch) -> pf_status {
+    int64_t first = 0;
+    while (first < ntiles) {
+      const int64_t count = std::min<int64_t>(ntiles - first, std::max<int64_t>(1, (int64_t)per_window));
+      pf_status r = reset_pool(w.rec, walk, s, who);
+      if (r == PF_OK) r = launch(first, count);
+      unsigned long long used[3];
+      if (r == PF_OK) r = pool_usage(w.rec, s, used, who);
+      if (r != PF_OK) return r;
+      if ((int64_t)used[0] > w.rec.cap || (int64_t)used[1] > w.rec.seg_cap) {
+        if (count == 1) {
+          pf::set_error(std::string(who) + ": the records of one 16x16 tile exceed the workspace limit");
+          return PF_ERR_OOM;
+        }
+        per_window = (double)(count / 2);
+        continue;
+      }
+      w.nrec = (int64_t)used[2];
+      w.nseg = (int64_t)used[1];
+      w.ntiles = count;
+      w.tile0 = global_first + first;
+      r = pf::backward_impl(sc, w, d_rgba, g, bo, s);
+      if (r != PF_OK) return r;
+      first += count;
+      // the next window from this one's fill (slots of records and segments)
+      const double fill = std::max((double)used[0] / (double)w.rec.cap, (double)used[1] / (double)w.rec.seg_cap);
+      per_window = std::min((double)max_tiles, std::max(1.0, (double)count / std::max(fill, 1e-3) / 1.15));
+    }
+    return PF_OK;
+  };
+
+  if (st == PF_OK && !walk) {
+    const pf::GroupFn fn = [&](int64_t tiles_before, int64_t ntiles, const pf::GroupComposite& run) {
+      return windows(ntiles, tiles_before, [&](int64_t first, int64_t count) { return run(first, count, &w.rec); });
+    };
+    st = pf::raster_views(sc, fs->cams.data(), (int)fs->cams.size(), fs->t_min, scratch, s, nullptr, &fn);
+  } else if (st == PF_OK) {
+    int64_t pix = 0, tiles = 0;
+    for (int v = 0; v < (int)fs->cams.size() && st == PF_OK; ++v) {
+      const pf_camera& cam = fs->cams[v];
+      const int64_t nt = pf::view_tiles(cam);
+      st = windows(nt, tiles, [&](int64_t first, int64_t count) {
+        return pf::trace_view(sc, cam, fs->t_min, fs->max_steps, scratch + 4 * pix, trunc, s, &w.rec, v, pix, first,
+                              count);
+      });
+      pix += (int64_t)cam.width * cam.height;
+      tiles += nt;
+    }
+  }
+  if (st == PF_OK) {
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = hip_status(e, who);
+  }
+  free_records(w.rec, s);
+  if (scratch) pf::pool_free(scratch, s);
+  if (trunc) pf::pool_free(trunc, s);
+  return st;
 }
 
 }  // namespace
@@ -362,17 +560,20 @@ pf_status pf_render_raster(pf_scene* scene, const pf_camera* cams, int32_t ncam,
   if (st != PF_OK) return st;
   const float t_min = (opts && opts->t_min > 0) ? opts->t_min : 1e-6f;
   const int mode = opts ? opts->state_mode : 0;
+  const int64_t limit = opts ? opts->workspace_limit : 0;
   if (mode != 0 && mode != 1) return invalid("pf_render_raster: state_mode must be 0 (store) or 1 (recompute)");
+  if (limit < 0) return invalid("pf_render_raster: workspace_limit must be >= 0");
   hipStream_t s = (hipStream_t)stream;
   if (!state || mode == 1) {
     st = pf::raster_views(scene->s, cams, ncam, t_min, rgba, s);
     if (st != PF_OK || !state) return st;
-    return new_state(scene, cams, ncam, 0, 1, t_min, 0, s, state, "pf_render_raster");
+    return new_state(scene, cams, ncam, 0, 1, t_min, 0, limit, s, state, "pf_render_raster");
   }
   pf_fwd_state* fs = nullptr;
-  st = new_state(scene, cams, ncam, 0, 0, t_min, 0, s, &fs, "pf_render_raster");
+  st = new_state(scene, cams, ncam, 0, 0, t_min, 0, limit, s, &fs, "pf_render_raster");
   if (st != PF_OK) return st;
-  st = fill_records(fs, rgba, nullptr, s, "pf_render_raster");
+  bool demoted = false;
+  st = fill_records(fs, rgba, nullptr, s, "pf_render_raster", &demoted);
   if (st != PF_OK) {
     free_state_mem(fs);
     delete fs;
@@ -398,7 +599,9 @@ pf_status pf_render_trace(pf_scene* scene, const pf_camera* cams, int32_t ncam, 
   const float t_min = (opts && opts->t_min > 0) ? opts->t_min : 1e-6f;
   const int max_steps = (opts && opts->max_steps > 0) ? opts->max_steps : 4096;
   const int mode = opts ? opts->state_mode : 0;
+  const int64_t limit = opts ? opts->workspace_limit : 0;
   if (mode != 0 && mode != 1) return invalid("pf_render_trace: state_mode must be 0 (store) or 1 (recompute)");
+  if (limit < 0) return invalid("pf_render_trace: workspace_limit must be >= 0");
   hipStream_t s = (hipStream_t)stream;
   unsigned long long* trunc = nullptr;
   PF_HIP_TRY(pf::pool_alloc((void**)&trunc, sizeof(unsigned long long), s));
@@ -411,10 +614,12 @@ pf_status pf_render_trace(pf_scene* scene, const pf_camera* cams, int32_t ncam, 
   const std::vector<pf_camera> cv(cams, cams + ncam);
   if (!state || mode == 1) {
     st = run_pass(scene, cv, 1, t_min, max_steps, rgba, trunc, s, nullptr);
-    if (st == PF_OK && state) st = new_state(scene, cams, ncam, 1, 1, t_min, max_steps, s, &fs, "pf_render_trace");
+    if (st == PF_OK && state)
+      st = new_state(scene, cams, ncam, 1, 1, t_min, max_steps, limit, s, &fs, "pf_render_trace");
   } else {
-    st = new_state(scene, cams, ncam, 1, 0, t_min, max_steps, s, &fs, "pf_render_trace");
-    if (st == PF_OK) st = fill_records(fs, rgba, trunc, s, "pf_render_trace");
+    st = new_state(scene, cams, ncam, 1, 0, t_min, max_steps, limit, s, &fs, "pf_render_trace");
+    bool demoted = false;
+    if (st == PF_OK) st = fill_records(fs, rgba, trunc, s, "pf_render_trace", &demoted);
   }
   if (st == PF_OK && truncated) {
     unsigned long long h = 0;
@@ -460,33 +665,7 @@ pf_status pf_backward(pf_scene* scene, pf_fwd_state* state, const float* d_rgba,
     state->consumed = true;
     return pf::backward_impl(scene->s, state->st, d_rgba, *grads, bo, s);
   }
-  // recompute mode: replay the forward with records into a temporary state
-  pf_fwd_state* tmp = nullptr;
-  pf_status st = new_state(scene, state->cams.data(), (int32_t)state->cams.size(), state->kind, 0, state->t_min,
-                           state->max_steps, s, &tmp, "pf_backward");
-  if (st != PF_OK) return st;
-  float* scratch = nullptr;
-  unsigned long long* trunc = nullptr;
-  hipError_t e = pf::pool_alloc((void**)&scratch, sizeof(float) * 4 * tmp->st.npix, s);
-  if (e == hipSuccess && state->kind == 1) e = pf::pool_alloc((void**)&trunc, sizeof(unsigned long long), s);
-  if (e != hipSuccess) {
-    pf::set_error(std::string("pf_backward: ") + hipGetErrorString(e));
-    st = e == hipErrorOutOfMemory ? PF_ERR_OOM : PF_ERR_HIP;
-  }
-  if (st == PF_OK) st = fill_records(tmp, scratch, trunc, s, "pf_backward");
-  if (st == PF_OK) st = pf::backward_impl(scene->s, tmp->st, d_rgba, *grads, bo, s);
-  if (st == PF_OK) {
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
-      pf::set_error(std::string("pf_backward: ") + hipGetErrorString(e));
-      st = PF_ERR_HIP;
-    }
-  }
-  if (scratch) pf::pool_free(scratch, s);
-  if (trunc) pf::pool_free(trunc, s);
-  free_state_mem(tmp);
-  delete tmp;
-  return st;
+  return backward_windows(state, d_rgba, *grads, bo, s);
 }
 
 pf_status pf_connect_loss(const pf_scene* scene, float lambda, const pf_grads* grads, double* loss, void* stream) {
@@ -544,29 +723,81 @@ pf_status pf_densify_prune(const pf_params* params, const float* err_ema, const 
                           n_drawn, (hipStream_t)stream);
 }
 
-pf_status pf_query_workspace(const pf_scene* scene, const pf_camera* cams, int32_t ncam, int32_t what,
-                             int64_t* bytes) {
+pf_status pf_query_workspace(pf_scene* scene, const pf_camera* cams, int32_t ncam, int32_t what,
+                             const pf_render_opts* opts, void* stream, int64_t* bytes) {
   if (!scene || !cams || ncam < 1 || !bytes) return invalid("pf_query_workspace: NULL argument or ncam < 1");
   if (what < 0 || what > 2) return invalid("pf_query_workspace: what must be 0, 1 or 2");
-  const pf::Scene& sc = scene->s;
-  const double n = (double)sc.n;
-  double npix = 0.0, ntiles = 0.0;
   for (int c = 0; c < ncam; ++c) {
-    npix += (double)cams[c].width * cams[c].height;
-    ntiles += (double)((cams[c].width + pf::TILE - 1) / pf::TILE) * ((cams[c].height + pf::TILE - 1) / pf::TILE);
+    std::string why;
+    if (!pf::camera_ok(cams[c], &why)) return invalid("pf_query_workspace: camera " + std::to_string(c) + ": " + why);
   }
-  double ppc = 0.0;
-  __atomic_load(&sc.pairs_per_cell, &ppc, __ATOMIC_RELAXED);
-  if (!(ppc > 0.0)) ppc = 4.0;
-  const double rpp = sc.rec_per_pixel > 0.0 ? sc.rec_per_pixel : g_rec_hint.load();
-  const double spp = sc.seg_per_pixel > 0.0 ? sc.seg_per_pixel : g_seg_hint.load();
-  // render: per (view, cell) key, count, offset; pairs (tile, value, sorted
-  // value); per tile counts and offsets; the image
-  double b = 12.0 * n * ncam + 20.0 * ppc * n * ncam + 12.0 * ntiles + 16.0 * npix;
-  // store-mode state: records, segments, per-pixel heads, per-wave segment tails
-  if (what >= 1) b += 36.0 * rpp * npix + 16.0 * spp * npix + 4.0 * npix + 32.0 * ntiles;
-  if (what == 2) b += 20.0 * n + 4.0 * rpp * npix + 16.0 * (n / 2.0);      // backward workspace
-  *bytes = (int64_t)(b * 1.1) + (1 << 20);
+  const int mode = opts ? opts->state_mode : 0;
+  const int64_t limit = opts ? opts->workspace_limit : 0;
+  if (mode != 0 && mode != 1) return invalid("pf_query_workspace: state_mode must be 0 or 1");
+  if (limit < 0) return invalid("pf_query_workspace: workspace_limit must be >= 0");
+  if (what > 0 && ncam > pf::REC_MAX_VIEWS) return invalid("pf_query_workspace: at most 4096 cameras with a state");
+  const pf::Scene& sc = scene->s;
+  const int64_t n = sc.n;
+  int64_t group = 0;   // binned lists of the largest group of views
+  {
+    const pf_status st = pf::raster_workspace(scene->s, cams, ncam, (hipStream_t)stream, &group);
+    if (st != PF_OK) return st;
+  }
+  if (what == 0) {
+    *bytes = group;
+    return PF_OK;
+  }
+  int64_t npix = 0, ntiles = 0;
+  for (int c = 0; c < ncam; ++c) {
+    npix += (int64_t)cams[c].width * cams[c].height;
+    ntiles += pf::view_tiles(cams[c]);
+  }
+  const int64_t state = (int64_t)sizeof(pf_camera) * ncam;
+  const int64_t meta = 4 * npix + 3 * 8 + 8 * 4 * ntiles;   // heads, counters, wave segment tails
+  // recompute: the render keeps the cameras; the backward replays windows
+  pf_fwd_state probe;
+  probe.scene = scene;
+  probe.kind = 0;
+  probe.limit = limit;
+  probe.st.npix = npix;
+  const Caps wc = window_caps(&probe);
+  const int64_t recompute_render = group + state;
+  const int64_t recompute_bwd = state + 16 * npix + meta + pool_bytes(wc) + group + pf::backward_bytes(n, wc.cap, true);
+  if (mode == 1) {
+    *bytes = what == 1 ? recompute_render : std::max(recompute_render, recompute_bwd);
+    return PF_OK;
+  }
+  // store: records for the whole call (within the limit, else demoted to
+  // recompute, whose backward is then the bound)
+  // (with a limit every pool the render asks for, the first one sized from
+  // the hints or the exact one of a repeated pass, is within it)
+  const Caps c = store_caps(&probe, 0, 0);
+  const int64_t pool = limit > 0 ? limit : pool_bytes(c);
+  const int64_t cap = limit > 0 ? limit / REC_BYTES : c.cap;
+  const int64_t render = state + meta + pool + group;
+  int64_t b = render;
+  if (what == 2) {
+    b = std::max(b, state + meta + pool + pf::backward_bytes(n, cap, true));
+    if (limit > 0) b = std::max(b, recompute_bwd);
+  }
+  *bytes = b;
+  return PF_OK;
+}
+
+pf_status pf_set_allocator(const pf_allocator* alloc) {
+  if (alloc && (!alloc->alloc || !alloc->free)) return invalid("pf_set_allocator: alloc and free must both be set");
+  pf::set_allocator(alloc);
+  return PF_OK;
+}
+
+pf_status pf_set_cache_limit(int64_t bytes) {
+  if (bytes < 0) return invalid("pf_set_cache_limit: bytes must be >= 0");
+  pf::set_cache_limit((size_t)bytes);
+  return PF_OK;
+}
+
+pf_status pf_memory_stats(int64_t* live, int64_t* peak, int64_t* cached, int32_t reset_peak) {
+  pf::memory_stats(live, peak, cached, reset_peak != 0);
   return PF_OK;
 }
 
@@ -576,10 +807,11 @@ void pf_state_release(pf_fwd_state* state) {
   delete state;
 }
 
-pf_status pf_state_info(const pf_fwd_state* state, int64_t* n_records, int64_t* n_pixels) {
+pf_status pf_state_info(const pf_fwd_state* state, int64_t* n_records, int64_t* n_pixels, int32_t* mode) {
   if (!state || !n_records || !n_pixels) return invalid("pf_state_info: NULL argument");
   *n_records = state->st.nrec;
   *n_pixels = state->st.npix;
+  if (mode) *mode = state->mode;
   return PF_OK;
 }
 

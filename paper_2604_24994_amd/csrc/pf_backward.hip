@@ -30,6 +30,7 @@
 #include "pf_backward.hpp"
 #include "pf_shade.hpp"
 
+#include <algorithm>
 #include <vector>
 
 namespace pf {
@@ -46,13 +47,13 @@ constexpr int KPAD = 65;            // row pitch of the per-site LDS table (bank
 // One workgroup per 16x16 tile of a view, one wave per 8x8 quadrant, lanes
 // row-major in the quadrant: the pixel layout of the store-mode raster, so
 // that the lanes of a wave walk records its raster wave appended side by side.
-__global__ void __launch_bounds__(256) k_suffix(const int32_t* __restrict__ head, int ncam,
+__global__ void __launch_bounds__(256) k_suffix(const int32_t* __restrict__ head, int ncam, int64_t tile0,
                                                 const float* __restrict__ d_rgba, const int4* __restrict__ ri,
                                                 float4* __restrict__ rf, float* __restrict__ rt,
                                                 const pf_camera* __restrict__ cams, const float4* __restrict__ nrm,
                                                 float lambda_n, double* __restrict__ normal_loss,
                                                 const float* __restrict__ pix_err, float* __restrict__ rte) {
-  int64_t tile = blockIdx.x, base = 0;
+  int64_t tile = tile0 + blockIdx.x, base = 0;
   int v = 0;
   for (; v < ncam - 1; ++v) {
     const int nt = ((cams[v].width + TILE - 1) / TILE) * ((cams[v].height + TILE - 1) / TILE);
@@ -120,12 +121,12 @@ __global__ void __launch_bounds__(256) k_suffix(const int32_t* __restrict__ head
 // order).  A segment's records are contiguous and its cell is uniform: the
 // loads and stores are coalesced and no record waits for the one behind it.
 __global__ void __launch_bounds__(256) k_suffix_seg(const int4* __restrict__ seg, const int2* __restrict__ wtail,
-                                                    int ncam, const float* __restrict__ d_rgba,
+                                                    int ncam, int64_t tile0, const float* __restrict__ d_rgba,
                                                     float4* __restrict__ rf, float* __restrict__ rt,
                                                     const pf_camera* __restrict__ cams, const float4* __restrict__ nrm,
                                                     float lambda_n, double* __restrict__ normal_loss,
                                                     const float* __restrict__ pix_err, float* __restrict__ rte) {
-  int64_t tile = blockIdx.x, base = 0;
+  int64_t tile = tile0 + blockIdx.x, base = 0;
   int v = 0;
   for (; v < ncam - 1; ++v) {
     const int nt = ((cams[v].width + TILE - 1) / TILE) * ((cams[v].height + TILE - 1) / TILE);
@@ -743,6 +744,14 @@ struct Buf {
 
 }  // namespace
 
+int64_t backward_bytes(int64_t n, int64_t cap, bool want_err) {
+  auto b = [](int64_t count, int64_t size) { return std::max<int64_t>(count, 1) * size; };
+  // chunks: sum over cells of ceil(records / CHUNK) <= records / CHUNK + cells with records
+  const int64_t nchunks = cap / CHUNK + std::min(n, cap) + 1;
+  return (want_err ? b(cap, 4) : 0) + b(n + 1, 4) * 4 + b(n, 4) + b(cap, 4) + 2 * scan_scratch_bytes(n + 1) +
+         b(nchunks, 16);
+}
+
 pf_status backward_impl(const Scene& sc, const BwdState& st, const float* d_rgba, const pf_grads& g,
                         const BwdOpts& opt, hipStream_t s) {
   const int64_t n = sc.n;
@@ -757,11 +766,13 @@ pf_status backward_impl(const Scene& sc, const BwdState& st, const float* d_rgba
   {
     ProfScope ps("k_suffix", s);
     if (st.rec.wtail)   // raster records: walk the waves' segments
-      k_suffix_seg<<<gp, 256, 0, s>>>(st.rec.seg, st.rec.wtail, st.ncam, d_rgba, st.rec.rf, st.rec.rt, st.cams_dev,
+      k_suffix_seg<<<gp, 256, 0, s>>>(st.rec.seg, st.rec.wtail, st.ncam, st.tile0, d_rgba, st.rec.rf, st.rec.rt,
+                                      st.cams_dev,
                                       sc.nrm, opt.lambda_normal, opt.normal_loss,
                                       want_err ? opt.pixel_error : nullptr, want_err ? rte.p : nullptr);
     else                // ray-walk records: follow the per-pixel chains
-      k_suffix<<<gp, 256, 0, s>>>(st.rec.head, st.ncam, d_rgba, st.rec.ri, st.rec.rf, st.rec.rt, st.cams_dev, sc.nrm,
+      k_suffix<<<gp, 256, 0, s>>>(st.rec.head, st.ncam, st.tile0, d_rgba, st.rec.ri, st.rec.rf, st.rec.rt, st.cams_dev,
+                                  sc.nrm,
                                   opt.lambda_normal, opt.normal_loss, want_err ? opt.pixel_error : nullptr,
                                   want_err ? rte.p : nullptr);
   }

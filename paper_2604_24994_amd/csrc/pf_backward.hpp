@@ -11,7 +11,8 @@ struct BwdState {
   int64_t nseg = 0;           // segments written
   int64_t npix = 0;           // pixels of all views
   int32_t ncam = 0;           // views
-  int64_t ntiles = 0;         // 16x16 tiles of all views
+  int64_t ntiles = 0;         // 16x16 tiles the records cover (grid of the per-pixel pass)
+  int64_t tile0 = 0;          // global index of the first of them (over the tiles of all views)
   pf_camera* cams_dev = nullptr;
 };
 
@@ -27,5 +28,8 @@ struct BwdOpts {
 
 pf_status backward_impl(const Scene& sc, const BwdState& st, const float* d_rgba, const pf_grads& g,
                         const BwdOpts& o, hipStream_t s);
+// Bytes backward_impl allocates at most for a state of record capacity cap
+// (every buffer, all live at once at most).
+int64_t backward_bytes(int64_t n, int64_t cap, bool want_err);
 
 }  // namespace pf

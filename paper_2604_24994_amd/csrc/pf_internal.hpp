@@ -115,11 +115,17 @@ void dfree(void* p, hipStream_t s);
 // gives it back once the work queued on s so far has finished with it.
 hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s);
 void pool_free(void* p, hipStream_t s);
+// The caller's allocator (NULL: the library's cache); the cache's limit;
+// requested bytes in use, their high-water mark and the cached bytes.
+void set_allocator(const pf_allocator* a);
+void set_cache_limit(size_t bytes);
+void memory_stats(int64_t* live, int64_t* peak, int64_t* cached, bool reset_peak);
 
 // --- scan / sort utilities (pf_util.hip) ---------------------------------
 // Exclusive prefix sum of n uint32 values; out may alias in.  Returns the
 // total through *total_dev (device, may be null).  Scratch is allocated on
-// the stream.
+// the stream: scan_scratch_bytes(n) bytes at most, all live at once.
+int64_t scan_scratch_bytes(int64_t n);
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n,
                               uint32_t* total_dev, hipStream_t s);
 // Stable LSD radix sort of (key, value) pairs on the low `bits` bits of key.

@@ -382,7 +382,9 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
                                                 int32_t* __restrict__ rec_head,
                                                 unsigned long long* __restrict__ rec_counter,
                                                 int4* __restrict__ rec_seg, int2* __restrict__ rec_wtail,
-                                                int64_t tile0, int64_t rec_cap, int64_t seg_cap) {
+                                                int64_t tile_first, int64_t wtail_base, int64_t rec_cap,
+                                                int64_t seg_cap, int64_t count,
+                                                unsigned long long* __restrict__ work) {
   // the tile's sorted cells are staged RB at a time: list entry and the cell
   // record fields every lane needs, loaded by the whole workgroup at once
   __shared__ int s_ci[RB];
@@ -392,12 +394,24 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
   __shared__ int s_row[RB];
   __shared__ int s_nr[RB];
   __shared__ int s_more[4];
+  __shared__ long long s_item;
 
-  // view of this tile: the last one whose tiles start at or before it
+  // work items = the launch's tiles: one per workgroup, or (work != null, a
+  // persistent launch) taken in turn from the counter until none is left
+  for (int64_t item = blockIdx.x;;) {
+  if (work) {
+    if (threadIdx.x == 0) s_item = (long long)atomicAdd(work, 1ull);
+    __syncthreads();
+    item = s_item;
+    __syncthreads();
+  }
+  if (item >= count) break;
+  // tile of the view group; its view: the last one whose tiles start at or before it
+  const int64_t gtile = tile_first + item;
   int lo = 0, hi = nview - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (views[mid].tile_base <= (long long)blockIdx.x) lo = mid; else hi = mid - 1;
+    if (views[mid].tile_base <= (long long)gtile) lo = mid; else hi = mid - 1;
   }
   const ViewDev& vd = views[lo];
   const int view = vd.view_id;
@@ -405,7 +419,7 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
   const int64_t pix_base = vd.pix_base;
   float* rgba = rgba_all + 4 * pix_base;
   int px, py;
-  tile_pixel(v.tiles_x, px, py, (int)(blockIdx.x - vd.tile_base));
+  tile_pixel(v.tiles_x, px, py, (int)(gtile - vd.tile_base));
   const bool inside = px < v.cam.width && py < v.cam.height;
   const RayD R = make_ray(v.cam, px + 0.5, py + 0.5);
   bool live = inside && R.valid;
@@ -414,7 +428,7 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int pix = py * v.cam.width + px;
-  const uint32_t e0 = tile_off[blockIdx.x], e1 = tile_off[blockIdx.x + 1];
+  const uint32_t e0 = tile_off[gtile], e1 = tile_off[gtile + 1];
   long long rblk = 0, sblk = 0;   // the wave's current record / segment block
   long long cblk = -1;            // first slot (header) of the wave's current segment block
   int rleft = 0, sleft = 0;
@@ -519,7 +533,9 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
     // unused slots of the last segment block are marked empty (mask 0)
     for (int j = lane; j < sleft; j += 64)
       if (sblk + j < seg_cap) rec_seg[sblk + j] = make_int4(0, 0, 0, 0);
-    if (lane == 0) rec_wtail[(tile0 + blockIdx.x) * 4 + wave] = make_int2((int)cblk, SBLK - sleft);
+    if (lane == 0) rec_wtail[(wtail_base + item) * 4 + wave] = make_int2((int)cblk, SBLK - sleft);
+  }
+  if (!work) break;
   }
 }
 
@@ -613,7 +629,7 @@ __global__ void __launch_bounds__(256) k_start_final(const double* __restrict__ 
 // waves that 136 unconstrained VGPRs allow, 125 at six).
 template <bool STORE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6)))
-k_trace(ViewArgs v, SceneDev S, const int32_t* __restrict__ start,
+k_trace(ViewArgs v, int64_t tile_first, SceneDev S, const int32_t* __restrict__ start,
                                                float t_min, int max_steps, float* __restrict__ rgba,
                                                unsigned long long* __restrict__ truncated, int view,
                                                int4* __restrict__ rec_ri, float4* __restrict__ rec_rf,
@@ -621,7 +637,7 @@ k_trace(ViewArgs v, SceneDev S, const int32_t* __restrict__ start,
                                                unsigned long long* __restrict__ rec_counter,
                                                int4* __restrict__ rec_seg, int64_t rec_cap, int64_t seg_cap) {
   int px, py;
-  tile_pixel(v.tiles_x, px, py);
+  tile_pixel(v.tiles_x, px, py, (int)(tile_first + blockIdx.x));
   const bool inside = px < v.cam.width && py < v.cam.height;
   const RayD R = make_ray(v.cam, px + 0.5, py + 0.5);
   bool live = inside && R.valid;
@@ -777,102 +793,189 @@ bool camera_ok(const pf_camera& c, std::string* why) {
   return true;
 }
 
-pf_status raster_views(Scene& sc, const pf_camera* cams, int ncam, float t_min, float* rgba, hipStream_t s,
-                       const RecBuf* rec) {
-  const int64_t n = sc.n;
+int raster_group_size(int64_t n, int ncam) {
   // views are processed in groups so that the per-(view, cell) scan fits 32 bits
-  const int group = (int)std::max<int64_t>(1, std::min<int64_t>(ncam, ((int64_t)1 << 28) / n));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(ncam, ((int64_t)1 << 28) / n));
+}
+
+int64_t view_tiles(const pf_camera& c) {
+  return (int64_t)((c.width + TILE - 1) / TILE) * ((c.height + TILE - 1) / TILE);
+}
+
+int64_t raster_group_bytes(int64_t n, int nv, int64_t ntiles, int64_t np) {
+  auto b = [](int64_t count, int64_t size) { return std::max<int64_t>(count, 1) * size; };
+  const int64_t nvc = (int64_t)nv * n;
+  return b(nv, sizeof(ViewDev)) + b(nvc + 1, 4) * 2 + b(nvc, 4) * 2 + b(ntiles + 1, 4) * 2 + b(ntiles, 4) +
+         b(1, 4) + b(1, 8) + scan_scratch_bytes(nvc + 1) + scan_scratch_bytes(ntiles + 1) + b(np, 4) + b(np, 8) * 2;
+}
+
+namespace {
+
+// The binned tile lists of one group of views (every buffer lives until
+// the group is done).
+struct Group {
+  int c0 = 0, nv = 0;
+  int64_t ntiles = 0, tiles_before = 0, pix_before = 0;
+  uint32_t np = 0;
+  Buf<ViewDev> views;
+  Buf<uint32_t> cnt, key, off, tcnt, toff, fill, cone_list, cone_n, ptile;
+  Buf<unsigned long long> pval, sorted, work;
+  explicit Group(hipStream_t s)
+      : views(s), cnt(s), key(s), off(s), tcnt(s), toff(s), fill(s), cone_list(s), cone_n(s), ptile(s), pval(s),
+        sorted(s), work(s) {}
+};
+
+// Cull and count (count_only: stops after the pair count), then emit,
+// bucket by tile and sort each tile's list.
+pf_status bin_group(Scene& sc, const pf_camera* cams, Group& G, hipStream_t s, bool count_only) {
+  const int64_t n = sc.n;
+  const int nv = G.nv;
+  std::vector<ViewDev> hv(nv);
+  int64_t ntiles = 0, pix = G.pix_before;
+  for (int v = 0; v < nv; ++v) {
+    const pf_camera& cam = cams[G.c0 + v];
+    hv[v].v.cam = cam;
+    hv[v].v.tiles_x = (cam.width + TILE - 1) / TILE;
+    hv[v].v.tiles_y = (cam.height + TILE - 1) / TILE;
+    hv[v].tile_base = ntiles;
+    hv[v].pix_base = pix;
+    hv[v].view_id = G.c0 + v;
+    ntiles += (int64_t)hv[v].v.tiles_x * hv[v].v.tiles_y;
+    pix += (int64_t)cam.width * cam.height;
+  }
+  G.ntiles = ntiles;
+  const int64_t nvc = (int64_t)nv * n;
+  PF_HIP_TRY(G.views.alloc(nv));
+  PF_HIP_TRY(hipMemcpyAsync(G.views.p, hv.data(), sizeof(ViewDev) * nv, hipMemcpyHostToDevice, s));
+  PF_HIP_TRY(G.cnt.alloc(nvc + 1));
+  PF_HIP_TRY(G.key.alloc(nvc));
+  PF_HIP_TRY(G.off.alloc(nvc + 1));
+  PF_HIP_TRY(G.tcnt.alloc(ntiles + 1));
+  PF_HIP_TRY(G.toff.alloc(ntiles + 1));
+  PF_HIP_TRY(G.fill.alloc(ntiles));
+  PF_HIP_TRY(G.cone_list.alloc(nvc));
+  PF_HIP_TRY(G.cone_n.alloc(1));
+  PF_HIP_TRY(G.work.alloc(1));
+  PF_HIP_TRY(hipMemsetAsync(G.cone_n.p, 0, sizeof(uint32_t), s));
+  const dim3 g((unsigned)((n + 255) / 256), (unsigned)nv);
+  {
+    ProfScope ps("k_view_count", s);
+    k_view_count<<<g, 256, 0, s>>>(G.views.p, sc.geo, sc.cull, sc.prm.power, n, G.cnt.p, G.key.p, G.cone_list.p,
+                                   G.cone_n.p);
+  }
+  PF_HIP_TRY(hipGetLastError());
+  uint32_t ncone = 0;
+  PF_HIP_TRY(hipMemcpyAsync(&ncone, G.cone_n.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  PF_HIP_TRY(hipStreamSynchronize(s));
+  if (ncone) {
+    k_cone_count<<<ncone, 256, 0, s>>>(G.views.p, sc.geo, sc.cull, n, G.cone_list.p, G.cnt.p);
+    PF_HIP_TRY(hipGetLastError());
+  }
+  PF_HIP_TRY(hipMemsetAsync(G.cnt.p + nvc, 0, sizeof(uint32_t), s));
+  PF_HIP_TRY(exclusive_scan_u32(G.cnt.p, G.off.p, nvc + 1, nullptr, s));
+  uint32_t np = 0;
+  PF_HIP_TRY(hipMemcpyAsync(&np, G.off.p + nvc, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  PF_HIP_TRY(hipStreamSynchronize(s));
+  G.np = np;
+  double ppc = (double)np / (double)nvc;   // sizing hint (renders may run on several threads)
+  __atomic_store(&sc.pairs_per_cell, &ppc, __ATOMIC_RELAXED);
+  if (count_only) return PF_OK;
+  PF_HIP_TRY(G.ptile.alloc(np));
+  PF_HIP_TRY(G.pval.alloc(np));
+  PF_HIP_TRY(G.sorted.alloc(np));
+  PF_HIP_TRY(hipMemsetAsync(G.tcnt.p, 0, sizeof(uint32_t) * (ntiles + 1), s));
+  PF_HIP_TRY(hipMemsetAsync(G.fill.p, 0, sizeof(uint32_t) * ntiles, s));
+  {
+    ProfScope ps("k_view_emit", s);
+    k_view_emit<<<g, 256, 0, s>>>(G.views.p, sc.geo, sc.cull, n, G.off.p, G.key.p, G.ptile.p, G.pval.p, G.tcnt.p);
+    if (ncone)
+      k_cone_emit<<<ncone, 256, 0, s>>>(G.views.p, sc.geo, sc.cull, n, G.off.p, G.key.p, G.cone_list.p, G.ptile.p,
+                                        G.pval.p, G.tcnt.p);
+  }
+  PF_HIP_TRY(hipGetLastError());
+  PF_HIP_TRY(exclusive_scan_u32(G.tcnt.p, G.toff.p, ntiles + 1, nullptr, s));
+  if (np) {
+    k_tile_scatter<<<(unsigned)((np + 255) / 256), 256, 0, s>>>(G.ptile.p, G.pval.p, np, G.toff.p, G.fill.p,
+                                                               G.sorted.p);
+    PF_HIP_TRY(hipGetLastError());
+    ProfScope ps("k_tile_sort", s);
+    k_tile_sort<<<(unsigned)ntiles, SORT_THREADS, 0, s>>>(G.sorted.p, G.toff.p);
+    PF_HIP_TRY(hipGetLastError());
+  }
+  return PF_OK;
+}
+
+// Composite of the group's tiles [first, first + count); with records, the
+// wave segment tails go to rec->wtail from index wtail_base.
+// The plain composite is one persistent launch: PERSIST_GROUPS workgroups
+// take the (view, tile) work items in turn from a counter, so that tiles of
+// all the call's views (the requests of a serving batch) share the CUs and
+// long tile lists do not leave CUs idle at the end of the launch.
+constexpr unsigned PERSIST_GROUPS = 256 * 8;
+
+pf_status composite(Scene& sc, Group& G, float t_min, float* rgba, hipStream_t s, const RecBuf* rec,
+                    int64_t first, int64_t count, int64_t wtail_base) {
+  if (count <= 0) return PF_OK;
+  ProfScope ps(rec ? "k_raster_store" : "k_raster", s);
+  if (rec) {
+    const RecBuf& rb = *rec;
+    k_raster<true><<<(unsigned)count, 256, 0, s>>>(G.views.p, G.nv, scene_dev(sc), G.sorted.p, G.toff.p, t_min, rgba,
+                                                   rb.ri, rb.rf, rb.rt, rb.head, rb.counter, rb.seg, rb.wtail, first,
+                                                   wtail_base, rb.cap, rb.seg_cap, count, nullptr);
+  } else {
+    PF_HIP_TRY(hipMemsetAsync(G.work.p, 0, sizeof(unsigned long long), s));
+    const unsigned grid = (unsigned)std::min<int64_t>(count, PERSIST_GROUPS);
+    k_raster<false><<<grid, 256, 0, s>>>(G.views.p, G.nv, scene_dev(sc), G.sorted.p, G.toff.p, t_min, rgba, nullptr,
+                                         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, first, 0, 0, 0, count,
+                                         G.work.p);
+  }
+  PF_HIP_TRY(hipGetLastError());
+  return PF_OK;
+}
+
+}  // namespace
+
+pf_status raster_views(Scene& sc, const pf_camera* cams, int ncam, float t_min, float* rgba, hipStream_t s,
+                       const RecBuf* rec, const GroupFn* fn) {
+  const int group = raster_group_size(sc.n, ncam);
   int64_t pix_done = 0, tiles_done = 0;
   for (int c0 = 0; c0 < ncam; c0 += group) {
-    const int nv = std::min(group, ncam - c0);
-    std::vector<ViewDev> hv(nv);
-    int64_t ntiles = 0;
-    for (int v = 0; v < nv; ++v) {
-      const pf_camera& cam = cams[c0 + v];
-      hv[v].v.cam = cam;
-      hv[v].v.tiles_x = (cam.width + TILE - 1) / TILE;
-      hv[v].v.tiles_y = (cam.height + TILE - 1) / TILE;
-      hv[v].tile_base = ntiles;
-      hv[v].pix_base = pix_done;
-      hv[v].view_id = c0 + v;
-      ntiles += (int64_t)hv[v].v.tiles_x * hv[v].v.tiles_y;
-      pix_done += (int64_t)cam.width * cam.height;
+    Group G(s);
+    G.c0 = c0;
+    G.nv = std::min(group, ncam - c0);
+    G.tiles_before = tiles_done;
+    G.pix_before = pix_done;
+    pf_status st = bin_group(sc, cams, G, s, false);
+    if (st != PF_OK) return st;
+    if (fn) {
+      const GroupComposite run = [&](int64_t first, int64_t count, const RecBuf* r) {
+        return composite(sc, G, t_min, rgba, s, r, first, count, 0);
+      };
+      st = (*fn)(tiles_done, G.ntiles, run);
+    } else {
+      st = composite(sc, G, t_min, rgba, s, rec, 0, G.ntiles, tiles_done);
     }
-    const int64_t nvc = (int64_t)nv * n;
-    Buf<ViewDev> views(s);
-    Buf<uint32_t> cnt(s), key(s), off(s), tcnt(s), toff(s), fill(s);
-    PF_HIP_TRY(views.alloc(nv));
-    PF_HIP_TRY(hipMemcpyAsync(views.p, hv.data(), sizeof(ViewDev) * nv, hipMemcpyHostToDevice, s));
-    PF_HIP_TRY(cnt.alloc(nvc + 1));
-    PF_HIP_TRY(key.alloc(nvc));
-    PF_HIP_TRY(off.alloc(nvc + 1));
-    PF_HIP_TRY(tcnt.alloc(ntiles + 1));
-    PF_HIP_TRY(toff.alloc(ntiles + 1));
-    PF_HIP_TRY(fill.alloc(ntiles));
-    Buf<uint32_t> cone_list(s), cone_n(s);
-    PF_HIP_TRY(cone_list.alloc(nvc));
-    PF_HIP_TRY(cone_n.alloc(1));
-    PF_HIP_TRY(hipMemsetAsync(cone_n.p, 0, sizeof(uint32_t), s));
-    const dim3 g((unsigned)((n + 255) / 256), (unsigned)nv);
-    {
-      ProfScope ps("k_view_count", s);
-      k_view_count<<<g, 256, 0, s>>>(views.p, sc.geo, sc.cull, sc.prm.power, n, cnt.p, key.p, cone_list.p,
-                                     cone_n.p);
-    }
-    PF_HIP_TRY(hipGetLastError());
-    uint32_t ncone = 0;
-    PF_HIP_TRY(hipMemcpyAsync(&ncone, cone_n.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    PF_HIP_TRY(hipStreamSynchronize(s));
-    if (ncone) {
-      k_cone_count<<<ncone, 256, 0, s>>>(views.p, sc.geo, sc.cull, n, cone_list.p, cnt.p);
-      PF_HIP_TRY(hipGetLastError());
-    }
-    PF_HIP_TRY(hipMemsetAsync(cnt.p + nvc, 0, sizeof(uint32_t), s));
-    PF_HIP_TRY(exclusive_scan_u32(cnt.p, off.p, nvc + 1, nullptr, s));
-    uint32_t np = 0;
-    PF_HIP_TRY(hipMemcpyAsync(&np, off.p + nvc, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    PF_HIP_TRY(hipStreamSynchronize(s));
-    double ppc = (double)np / (double)nvc;   // sizing hint (renders may run on several threads)
-    __atomic_store(&sc.pairs_per_cell, &ppc, __ATOMIC_RELAXED);
-    Buf<uint32_t> ptile(s);
-    Buf<unsigned long long> pval(s), sorted(s);
-    PF_HIP_TRY(ptile.alloc(np));
-    PF_HIP_TRY(pval.alloc(np));
-    PF_HIP_TRY(sorted.alloc(np));
-    PF_HIP_TRY(hipMemsetAsync(tcnt.p, 0, sizeof(uint32_t) * (ntiles + 1), s));
-    PF_HIP_TRY(hipMemsetAsync(fill.p, 0, sizeof(uint32_t) * ntiles, s));
-    {
-      ProfScope ps("k_view_emit", s);
-      k_view_emit<<<g, 256, 0, s>>>(views.p, sc.geo, sc.cull, n, off.p, key.p, ptile.p, pval.p, tcnt.p);
-      if (ncone)
-        k_cone_emit<<<ncone, 256, 0, s>>>(views.p, sc.geo, sc.cull, n, off.p, key.p, cone_list.p, ptile.p, pval.p,
-                                          tcnt.p);
-    }
-    PF_HIP_TRY(hipGetLastError());
-    PF_HIP_TRY(exclusive_scan_u32(tcnt.p, toff.p, ntiles + 1, nullptr, s));
-    if (np) {
-      k_tile_scatter<<<(unsigned)((np + 255) / 256), 256, 0, s>>>(ptile.p, pval.p, np, toff.p, fill.p, sorted.p);
-      PF_HIP_TRY(hipGetLastError());
-      ProfScope ps("k_tile_sort", s);
-      k_tile_sort<<<(unsigned)ntiles, SORT_THREADS, 0, s>>>(sorted.p, toff.p);
-      PF_HIP_TRY(hipGetLastError());
-    }
-    {
-      ProfScope ps(rec ? "k_raster_store" : "k_raster", s);
-      if (rec) {
-        const RecBuf& rb = *rec;
-        k_raster<true><<<(unsigned)ntiles, 256, 0, s>>>(views.p, nv, scene_dev(sc), sorted.p, toff.p, t_min, rgba,
-                                                        rb.ri, rb.rf, rb.rt, rb.head, rb.counter, rb.seg, rb.wtail,
-                                                        tiles_done, rb.cap, rb.seg_cap);
-      } else {
-        k_raster<false><<<(unsigned)ntiles, 256, 0, s>>>(views.p, nv, scene_dev(sc), sorted.p, toff.p, t_min, rgba,
-                                                         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                                         nullptr, 0, 0, 0);
-      }
-    }
-    PF_HIP_TRY(hipGetLastError());
-    tiles_done += ntiles;
+    if (st != PF_OK) return st;
+    tiles_done += G.ntiles;
+    for (int v = 0; v < G.nv; ++v) pix_done += (int64_t)cams[c0 + v].width * cams[c0 + v].height;
   }
+  return PF_OK;
+}
+
+pf_status raster_workspace(Scene& sc, const pf_camera* cams, int ncam, hipStream_t s, int64_t* bytes) {
+  const int group = raster_group_size(sc.n, ncam);
+  int64_t worst = 0, pix_done = 0;
+  for (int c0 = 0; c0 < ncam; c0 += group) {
+    Group G(s);
+    G.c0 = c0;
+    G.nv = std::min(group, ncam - c0);
+    G.pix_before = pix_done;
+    const pf_status st = bin_group(sc, cams, G, s, true);
+    if (st != PF_OK) return st;
+    worst = std::max(worst, raster_group_bytes(sc.n, G.nv, G.ntiles, G.np));
+    for (int v = 0; v < G.nv; ++v) pix_done += (int64_t)cams[c0 + v].width * cams[c0 + v].height;
+  }
+  *bytes = worst;
   return PF_OK;
 }
 
@@ -887,13 +990,15 @@ pf_status seg_record_total(const int4* seg, int64_t nseg, unsigned long long* to
 }
 
 pf_status trace_view(const Scene& sc, const pf_camera& cam, float t_min, int max_steps, float* rgba,
-                     unsigned long long* trunc_dev, hipStream_t s, const RecBuf* rec, int view, int64_t pix_base) {
+                     unsigned long long* trunc_dev, hipStream_t s, const RecBuf* rec, int view, int64_t pix_base,
+                     int64_t tile_first, int64_t tile_count) {
   const int64_t n = sc.n;
   ViewArgs v;
   v.cam = cam;
   v.tiles_x = (cam.width + TILE - 1) / TILE;
   v.tiles_y = (cam.height + TILE - 1) / TILE;
-  const int64_t ntiles = (int64_t)v.tiles_x * v.tiles_y;
+  const int64_t ntiles = tile_count >= 0 ? tile_count : (int64_t)v.tiles_x * v.tiles_y - tile_first;
+  if (ntiles <= 0) return PF_OK;
   const int nb = (int)std::min<int64_t>(1024, (n + 255) / 256);
   Buf<double> pk(s);
   Buf<long long> pi(s);
@@ -909,11 +1014,13 @@ pf_status trace_view(const Scene& sc, const pf_camera& cam, float t_min, int max
   ProfScope ps(rec ? "k_trace_store" : "k_trace", s);
   if (rec) {
     const RecBuf& rb = *rec;
-    k_trace<true><<<(unsigned)ntiles, 256, 0, s>>>(v, scene_dev(sc), start.p, t_min, max_steps, rgba, trunc_dev,
+    k_trace<true><<<(unsigned)ntiles, 256, 0, s>>>(v, tile_first, scene_dev(sc), start.p, t_min, max_steps, rgba,
+                                                   trunc_dev,
                                                    view, rb.ri, rb.rf, rb.rt, rb.head + pix_base, rb.counter,
                                                    rb.seg, rb.cap, rb.seg_cap);
   } else {
-    k_trace<false><<<(unsigned)ntiles, 256, 0, s>>>(v, scene_dev(sc), start.p, t_min, max_steps, rgba, trunc_dev,
+    k_trace<false><<<(unsigned)ntiles, 256, 0, s>>>(v, tile_first, scene_dev(sc), start.p, t_min, max_steps, rgba,
+                                                    trunc_dev,
                                                     0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0);
   }
   PF_HIP_TRY(hipGetLastError());

@@ -14,13 +14,16 @@
 
 namespace pf {
 
-// Device blocks are cached by the library: a freed block is kept, with an
-// event recorded on the stream that freed it, and handed out again to an
-// allocation of at most twice its size on that stream (stream order makes
-// it safe), or on another stream once the event has completed (no stream
-// waits on another, so concurrent streams stay independent).
-// The runtime is asked for memory only on a miss; blocks go back to it when
-// the cache exceeds its limit or an allocation fails.
+// Device blocks come from the caller's allocator when one is set
+// (pf_set_allocator), else from a cache of the library's own: a freed block
+// is kept, with an event recorded on the stream that freed it, and handed
+// out again to an allocation of at most twice its size on that stream
+// (stream order makes it safe), or on another stream once the event has
+// completed (no stream waits on another, so concurrent streams stay
+// independent).  The runtime is asked for memory only on a miss; blocks go
+// back to it when the cache exceeds its limit or an allocation fails.
+// Either way the requested bytes of the blocks in use, and their high-water
+// mark, are counted (pf_memory_stats).
 namespace {
 struct CachedBlock {
   void* p;
@@ -29,11 +32,25 @@ struct CachedBlock {
   hipEvent_t ev;
   hipStream_t freed_on;
 };
+struct LiveBlock {
+  size_t bytes;          // block size (the cache's rounding), or the request for a caller block
+  size_t req;            // requested bytes
+  int dev;
+  bool caller;           // from the caller's allocator
+  pf_allocator a;        // that allocator
+};
 std::mutex g_cache_mu;
 std::multimap<size_t, CachedBlock> g_cache;                  // free blocks by size
-std::unordered_map<void*, std::pair<size_t, int>> g_live;    // handed-out blocks: size, device
+std::unordered_map<void*, LiveBlock> g_live;                 // handed-out blocks
 size_t g_cached_bytes = 0;
-constexpr size_t CACHE_LIMIT = size_t(48) << 30;
+size_t g_cache_limit = size_t(48) << 30;
+pf_allocator g_alloc{};                                      // caller's allocator (alloc == NULL: none)
+int64_t g_live_req = 0, g_peak_req = 0;                      // requested bytes in use, high-water mark
+
+void account(int64_t delta) {
+  g_live_req += delta;
+  if (g_live_req > g_peak_req) g_peak_req = g_live_req;
+}
 
 size_t round_bytes(size_t bytes) {
   // above 1 MiB in steps of 1/16 of the power of two (at most 6.25% more)
@@ -70,27 +87,41 @@ void flush_device(int dev) {
 }  // namespace
 
 hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s) {
-  bytes = round_bytes(bytes);
+  const size_t req = bytes;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
+  pf_allocator a{};
   {
     std::unique_lock<std::mutex> lk(g_cache_mu);
-    for (auto it = g_cache.lower_bound(bytes); it != g_cache.end() && it->first <= 2 * bytes; ++it) {
-      if (it->second.dev != dev) continue;
-      if (it->second.freed_on != s && hipEventQuery(it->second.ev) != hipSuccess) {
-        (void)hipGetLastError();   // "not ready" is not an error of the caller's
-        continue;
+    a = g_alloc;
+    if (!a.alloc) {
+      bytes = round_bytes(bytes);
+      for (auto it = g_cache.lower_bound(bytes); it != g_cache.end() && it->first <= 2 * bytes; ++it) {
+        if (it->second.dev != dev) continue;
+        if (it->second.freed_on != s && hipEventQuery(it->second.ev) != hipSuccess) {
+          (void)hipGetLastError();   // "not ready" is not an error of the caller's
+          continue;
+        }
+        const CachedBlock b = it->second;
+        g_cache.erase(it);
+        g_cached_bytes -= b.bytes;
+        g_live[b.p] = LiveBlock{b.bytes, req, dev, false, {}};
+        account((int64_t)req);
+        lk.unlock();
+        (void)hipEventDestroy(b.ev);
+        *p = b.p;
+        return hipSuccess;
       }
-      const CachedBlock b = it->second;
-      g_cache.erase(it);
-      g_cached_bytes -= b.bytes;
-      g_live[b.p] = {b.bytes, dev};
-      lk.unlock();
-      (void)hipEventDestroy(b.ev);
-      *p = b.p;
-      return hipSuccess;
     }
+  }
+  if (a.alloc) {
+    *p = a.alloc(a.ctx, req, (void*)s);
+    if (!*p) return hipErrorOutOfMemory;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_live[*p] = LiveBlock{req, req, dev, true, a};
+    account((int64_t)req);
+    return hipSuccess;
   }
   e = hipMalloc(p, bytes);
   if (e == hipErrorOutOfMemory) {
@@ -100,7 +131,8 @@ hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s) {
   }
   if (e == hipSuccess) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
-    g_live[*p] = {bytes, dev};
+    g_live[*p] = LiveBlock{bytes, req, dev, false, {}};
+    account((int64_t)req);
   }
   return e;
 }
@@ -108,13 +140,20 @@ hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s) {
 void pool_free(void* p, hipStream_t s) {
   if (!p) return;
   CachedBlock b{p, 0, 0, nullptr, s};
+  LiveBlock lb{};
   {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto it = g_live.find(p);
     if (it == g_live.end()) return;   // not from pool_alloc: nothing to do
-    b.bytes = it->second.first;
-    b.dev = it->second.second;
+    lb = it->second;
+    b.bytes = lb.bytes;
+    b.dev = lb.dev;
     g_live.erase(it);
+    account(-(int64_t)lb.req);
+  }
+  if (lb.caller) {
+    lb.a.free(lb.a.ctx, p, lb.req, (void*)s);
+    return;
   }
   if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess ||
       hipEventRecord(b.ev, s) != hipSuccess) {
@@ -128,7 +167,7 @@ void pool_free(void* p, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     g_cache.insert({b.bytes, b});
     g_cached_bytes += b.bytes;
-    while (g_cached_bytes > CACHE_LIMIT && !g_cache.empty()) {
+    while (g_cached_bytes > g_cache_limit && !g_cache.empty()) {
       auto last = std::prev(g_cache.end());
       out.push_back(last->second);
       g_cached_bytes -= last->second.bytes;
@@ -136,6 +175,38 @@ void pool_free(void* p, hipStream_t s) {
     }
   }
   for (const CachedBlock& v : out) release_block(v);
+}
+
+void set_allocator(const pf_allocator* a) {
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_alloc = a ? *a : pf_allocator{};
+  }
+  int dev = 0;
+  if (a && hipGetDevice(&dev) == hipSuccess) flush_device(dev);   // the caller's allocator gets the memory
+}
+
+void set_cache_limit(size_t bytes) {
+  std::vector<CachedBlock> out;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_cache_limit = bytes;
+    while (g_cached_bytes > g_cache_limit && !g_cache.empty()) {
+      auto last = std::prev(g_cache.end());
+      out.push_back(last->second);
+      g_cached_bytes -= last->second.bytes;
+      g_cache.erase(last);
+    }
+  }
+  for (const CachedBlock& v : out) release_block(v);
+}
+
+void memory_stats(int64_t* live, int64_t* peak, int64_t* cached, bool reset_peak) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  if (live) *live = g_live_req;
+  if (peak) *peak = g_peak_req;
+  if (cached) *cached = (int64_t)g_cached_bytes;
+  if (reset_peak) g_peak_req = g_live_req;
 }
 
 namespace {
@@ -207,6 +278,17 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_block_apply(const uint32_t* in
 }
 
 }  // namespace
+
+int64_t scan_scratch_bytes(int64_t n) {
+  int64_t b = 0;
+  while (n > 0) {
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb == 1) break;
+    b += (int64_t)sizeof(uint32_t) * nb;
+    n = nb;
+  }
+  return b;
+}
 
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total_dev,
                               hipStream_t s) {

@@ -1,13 +1,17 @@
 """Continuous-batching render server over resident scenes.
 
-Scenes stay built in HBM.  Requests (scene id, camera) queue on arrival; a
-pool of worker threads, each with its own HIP stream, repeatedly takes the
-oldest waiting requests of one scene that fit the free HBM budget and a ray
-cap, and renders them as ONE batched pf_render_raster call (all of the
-batch's tiles in one composite launch).  Requests arriving while batches run
-join the next batch as soon as a worker and budget free up, so device work
-of consecutive batches overlaps.  Each request's image is the same as a
-render of that camera alone (views never interact).
+Scenes stay built in HBM.  Requests (scene id, camera) queue on arrival,
+each sized by the library's bound on the device memory its render requests
+(pf_query_workspace, exact in the scene's tile-pair lists for that camera)
+plus its RGBA output.  A pool of worker threads, each with its own HIP
+stream, repeatedly takes the oldest waiting requests of one scene whose
+bounds fit the free part of the HBM budget (and a ray cap), and renders
+them as ONE batched pf_render_raster call: one persistent composite launch
+over the (request, tile) work items of the whole batch.  Requests arriving
+while batches run join the next batch as soon as a worker and budget free
+up, so device work of consecutive batches overlaps; a request that does not
+fit waits until enough in-flight work completes.  Each request's image is
+the same as a render of that camera alone (views never interact).
 
 ``PlainServer`` is the per-request baseline: one pf_render_raster call per
 request, in arrival order, one stream.
@@ -18,20 +22,19 @@ import collections
 import threading
 import time
 from concurrent.futures import Future
-from typing import Dict, List, Optional
+from typing import Callable, Dict, List, Optional
 
 import numpy as np
 import torch
 
-from .api import Scene, render_raster
+from .api import Scene, query_workspace, render_raster
 
 
-def request_bytes(scene: Scene, cam) -> int:
-    """Device memory a request holds while in flight: its RGBA output, the
-    per-(view, cell) key/count/offset arrays and the tile pair lists (an
-    estimate of 24 B per cell)."""
-    n = int(scene.params["p"].shape[0])
-    return 16 * int(cam.width) * int(cam.height) + 24 * n
+def request_bytes(scene: Scene, cam, stream=None) -> int:
+    """Device memory a request holds while in flight: the library's upper
+    bound for rendering it (pf_query_workspace, which runs the cull-and-count
+    pass of this camera on ``stream``) plus its RGBA output (16 B/pixel)."""
+    return query_workspace(scene, [cam], 0, stream=stream) + 16 * int(cam.width) * int(cam.height)
 
 
 class _Req:
@@ -81,13 +84,33 @@ def take_batch(queue: "collections.deque", inflight: int, budget: int, max_batch
 
 
 class Server:
-    def __init__(self, scenes: Dict[int, Scene], hbm_budget_bytes: int = 8 << 30, max_batch_rays: int = 8 << 20,
-                 max_batch: int = 64, n_workers: int = 2, t_min: float = 1e-6):
+    """``hbm_budget_bytes``: device bytes the requests in flight may hold
+    together (None: 80% of the free device memory when the server starts).
+    ``render_fn(scene, cams, stream) -> images`` and ``sizer(scene, cam) ->
+    bytes`` replace the library calls (host tests of the policy); ``streams``
+    False runs the workers without device streams."""
+
+    def __init__(self, scenes: Dict[int, Scene], hbm_budget_bytes: Optional[int] = None,
+                 max_batch_rays: int = 8 << 20, max_batch: int = 64, n_workers: int = 2, t_min: float = 1e-6,
+                 render_fn: Optional[Callable] = None, sizer: Optional[Callable] = None, streams: bool = True):
         self.scenes = scenes
+        if hbm_budget_bytes is None:
+            hbm_budget_bytes = int(0.8 * torch.cuda.mem_get_info()[0])
         self.budget = int(hbm_budget_bytes)
         self.max_batch_rays = int(max_batch_rays)
         self.max_batch = int(max_batch)
         self.t_min = t_min
+        self._streams = streams
+        self._render = render_fn or (lambda scene, cams, stream: render_raster(scene, cams, t_min=self.t_min,
+                                                                               stream=stream))
+        if sizer is None:
+            self._qstream = torch.cuda.Stream()
+            self._qlock = threading.Lock()
+
+            def sizer(scene, cam):
+                with self._qlock:
+                    return request_bytes(scene, cam, stream=self._qstream)
+        self._sizer = sizer
         self._queue: collections.deque = collections.deque()
         self._cv = threading.Condition()
         self._inflight = 0
@@ -95,6 +118,7 @@ class Server:
         self._stop = False
         self.latencies: List[float] = []
         self.batches: List[int] = []
+        self.admitted: List[tuple] = []     # (time, in-flight bytes after admission)
         self.rays_done = 0
         self._workers = [threading.Thread(target=self._run, daemon=True, name=f"pf-serve-{i}")
                          for i in range(n_workers)]
@@ -105,8 +129,8 @@ class Server:
         """Queues a request; the future resolves to its [H,W,4] image."""
         if scene_id not in self.scenes:
             raise KeyError(f"unknown scene {scene_id}")
-        req = _Req(scene_id, cam, time.perf_counter() if arrival is None else arrival,
-                   request_bytes(self.scenes[scene_id], cam))
+        arrival = time.perf_counter() if arrival is None else arrival
+        req = _Req(scene_id, cam, arrival, int(self._sizer(self.scenes[scene_id], cam)))
         if req.nbytes > self.budget:
             raise ValueError("request needs more than the whole HBM budget")
         with self._cv:
@@ -118,10 +142,12 @@ class Server:
         batch = take_batch(self._queue, self._inflight, self.budget, self.max_batch_rays, self.max_batch)
         self._inflight += sum(r.nbytes for r in batch)
         self.peak_inflight = max(self.peak_inflight, self._inflight)
+        if batch:
+            self.admitted.append((time.perf_counter(), self._inflight))
         return batch
 
     def _run(self):
-        stream = torch.cuda.Stream()
+        stream = torch.cuda.Stream() if self._streams else None
         while True:
             with self._cv:
                 batch: List[_Req] = []
@@ -135,12 +161,14 @@ class Server:
                     return
             nbytes = sum(r.nbytes for r in batch)
             try:
-                with torch.cuda.stream(stream):
-                    imgs = render_raster(self.scenes[batch[0].scene_id], [r.cam for r in batch],
-                                         t_min=self.t_min, stream=stream)
-                    ev = torch.cuda.Event()
-                    ev.record(stream)
-                ev.synchronize()
+                if stream is not None:
+                    with torch.cuda.stream(stream):
+                        imgs = self._render(self.scenes[batch[0].scene_id], [r.cam for r in batch], stream)
+                        ev = torch.cuda.Event()
+                        ev.record(stream)
+                    ev.synchronize()
+                else:
+                    imgs = self._render(self.scenes[batch[0].scene_id], [r.cam for r in batch], None)
                 done = time.perf_counter()
                 with self._cv:
                     for r in batch:

@@ -24,7 +24,8 @@ def test_header_declares_boundary():
     names = _declared()
     for n in ("pf_build_scene", "pf_update_scene", "pf_render_raster", "pf_render_trace", "pf_backward",
               "pf_query_workspace", "pf_connect_loss", "pf_steiner", "pf_ema_update", "pf_densify_prune",
-              "pf_state_release", "pf_scene_destroy", "pf_last_error"):
+              "pf_state_release", "pf_scene_destroy", "pf_last_error", "pf_set_allocator", "pf_set_cache_limit",
+              "pf_memory_stats"):
         assert n in names
 
 
@@ -40,7 +41,8 @@ def test_binding_struct_sizes_match_header_layout():
     from paper_2604_24994_amd import _lib as L
     assert ctypes.sizeof(L.PfCamera) == 4 * (3 + 12 + 6)
     assert ctypes.sizeof(L.PfParams) == 8 + 4 + 4 + 7 * 8 + 8
-    assert ctypes.sizeof(L.PfRenderOpts) == 12
+    assert ctypes.sizeof(L.PfRenderOpts) == 24       # float, int32, int32, int64
+    assert ctypes.sizeof(L.PfAllocator) == 3 * 8
     assert ctypes.sizeof(L.PfSceneInfo) == 6 * 8 + 6 * 4
     assert ctypes.sizeof(L.PfSteinerOpts) == 8 + 4 * 4
     assert ctypes.sizeof(L.PfBackwardOpts) == 8 * 5
@@ -54,7 +56,7 @@ def test_binding_struct_sizes_match_header_layout():
     st = lib.pf_update_scene(None, None, None)
     assert st == L.PF_ERR_INVALID and b"pf_update_scene" in lib.pf_last_error()
     b = ctypes.c_int64(0)
-    st = lib.pf_query_workspace(None, None, 0, 0, ctypes.byref(b))
+    st = lib.pf_query_workspace(None, None, 0, 0, None, None, ctypes.byref(b))
     assert st == L.PF_ERR_INVALID and b"pf_query_workspace" in lib.pf_last_error()
     n_out = ctypes.c_int64(-1)
     o = L.PfSteinerOpts(n_cand=16, rounds=0, lo_ratio=2.0, hi_ratio=6.0)

@@ -102,8 +102,16 @@ def test_render_null_and_count_checks(lib):
     _expect(lib, lib.pf_render_raster(FAKE, cams, 1, C.byref(bad), FAKE, None, None), PF_ERR_INVALID,
             "state_mode must be 0 (store) or 1 (recompute)")
     n = C.c_int64()
-    _expect(lib, lib.pf_query_workspace(FAKE, cams, 0, 0, C.byref(n)), PF_ERR_INVALID, "ncam < 1")
-    _expect(lib, lib.pf_query_workspace(FAKE, cams, 1, 3, C.byref(n)), PF_ERR_INVALID, "what must be 0, 1 or 2")
+    _expect(lib, lib.pf_query_workspace(FAKE, cams, 0, 0, None, None, C.byref(n)), PF_ERR_INVALID, "ncam < 1")
+    _expect(lib, lib.pf_query_workspace(FAKE, cams, 1, 3, None, None, C.byref(n)), PF_ERR_INVALID,
+            "what must be 0, 1 or 2")
+    _expect(lib, lib.pf_query_workspace(FAKE, cams, 1, 1, C.byref(bad), None, C.byref(n)), PF_ERR_INVALID,
+            "state_mode must be 0 or 1")
+    neg = L.PfRenderOpts(t_min=1e-6, max_steps=0, state_mode=0, workspace_limit=-1)
+    _expect(lib, lib.pf_query_workspace(FAKE, cams, 1, 1, C.byref(neg), None, C.byref(n)), PF_ERR_INVALID,
+            "workspace_limit must be >= 0")
+    _expect(lib, lib.pf_render_raster(FAKE, cams, 1, C.byref(neg), FAKE, None, None), PF_ERR_INVALID,
+            "workspace_limit must be >= 0")
 
 
 def test_backward_and_regulariser_checks(lib):
@@ -114,7 +122,7 @@ def test_backward_and_regulariser_checks(lib):
     _expect(lib, lib.pf_connect_loss(FAKE, math.nan, C.byref(g), C.byref(loss), None), PF_ERR_INVALID,
             "lambda must be finite")
     n1, n2 = C.c_int64(), C.c_int64()
-    _expect(lib, lib.pf_state_info(None, C.byref(n1), C.byref(n2)), PF_ERR_INVALID, "NULL argument")
+    _expect(lib, lib.pf_state_info(None, C.byref(n1), C.byref(n2), None), PF_ERR_INVALID, "NULL argument")
 
 
 def _steiner(lib, p=None, rounds=6, n_cand=100, lo=2.0, hi=6.0, cap=10, outs=True, z=FAKE):
@@ -182,3 +190,13 @@ def test_profile_read_checks(lib):
     n = C.c_int32()
     _expect(lib, lib.pf_profile_read(None, 4, C.byref(n)), PF_ERR_INVALID, "NULL argument")
     _expect(lib, lib.pf_profile_read(None, 0, None), PF_ERR_INVALID, "NULL argument")
+
+
+def test_allocator_and_memory_checks(lib):
+    a = L.PfAllocator()
+    _expect(lib, lib.pf_set_allocator(C.byref(a)), PF_ERR_INVALID, "alloc and free must both be set")
+    _expect(lib, lib.pf_set_cache_limit(-1), PF_ERR_INVALID, "bytes must be >= 0")
+    live, peak, cached = C.c_int64(-1), C.c_int64(-1), C.c_int64(-1)
+    assert lib.pf_memory_stats(C.byref(live), C.byref(peak), C.byref(cached), 0) == PF_OK
+    assert live.value >= 0 and peak.value >= live.value and cached.value >= 0
+    assert lib.pf_set_allocator(None) == PF_OK

@@ -3,8 +3,8 @@
     FP64 oracle adjoint and against the raster's backward;
   * recompute mode (no records kept; pf_backward replays the forward)
     against store mode;
-  * pf_update_scene against a fresh build of the moved parameters;
-  * pf_query_workspace estimates."""
+  * pf_update_scene against a fresh build of the moved parameters.
+(pf_query_workspace and the bounded recompute windows: test_gpu_memory.py.)"""
 import numpy as np
 import pytest
 import torch
@@ -112,22 +112,6 @@ def test_update_scene_equals_fresh_build(kind, n, move):
         bad = dict(moved)
         bad["p"] = moved["p"][:10].contiguous()
         pf.update_scene(scene, bad)
-
-
-def test_query_workspace_estimates():
-    import paper_2604_24994_amd as pf
-    _flush("case query_workspace: 20,000 sites, one 256x192 view")
-    sc = W.scene_mixture(20000, seed=4)
-    cam = W.pinhole(W.random_eyes(1, 4.0, 8)[0], 256, 192, 60.0)
-    scene = pf.build_scene(pf.to_device_params(sc), sigma_scale=sc.sigma_scale, tau=sc.tau)
-    q0, q1, q2 = (pf.query_workspace(scene, cam, w) for w in (0, 1, 2))
-    assert 0 < q0 < q1 < q2
-    _, state = pf.render_raster_state(scene, cam)
-    nrec = state.info()["records"]
-    q1b = pf.query_workspace(scene, cam, 1)     # now sized from this render's counts
-    _flush(f"  estimates {q0} {q1} {q2}; after a render {q1b}, records {nrec} ({36 * nrec} B)")
-    assert q1b >= 36 * nrec
-    state.release()
 
 
 def test_raster_over_view_groups_equals_views_one_by_one():

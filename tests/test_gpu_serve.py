@@ -42,12 +42,22 @@ def test_results_equal_alone_and_in_mix(budget_mb, expect_batching):
     if budget < max(serve.request_bytes(scene, r.camera) for r in reqs):
         budget = max(serve.request_bytes(scene, r.camera) for r in reqs)   # one request at a time
     srv = serve.Server({0: scene}, hbm_budget_bytes=budget, n_workers=2)
+    base = pf.memory_stats(reset_peak=True)
     try:
         futs = [srv.submit(0, r.camera) for r in reqs]
         imgs = [f.result(timeout=120) for f in futs]
     finally:
         srv.close()
     torch.cuda.synchronize()
+    lib_peak = pf.memory_stats()["peak"] - base["live"]
+    sizing = max(serve.request_bytes(scene, r.camera) for r in reqs)
+    _flush(f"  library device memory in flight at most {lib_peak} B; budget {budget} B, "
+           f"admitted at most {srv.peak_inflight} B")
+    # the library's own device requests never exceeded the admitted bounds
+    # (the images are the caller's tensors, also inside the bounds), plus the
+    # sizing query of the one request being admitted (bounded like it)
+    assert lib_peak <= srv.peak_inflight + sizing
+    assert srv.peak_inflight <= budget
     for a, b in zip(alone, imgs):
         assert torch.equal(a, b)
     _flush(f"  batches {srv.batches}")

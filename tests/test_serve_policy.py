@@ -47,3 +47,48 @@ def test_single_large_request_is_admitted_alone():
 def test_max_batch():
     q = _q([(i, 0, 1, 1) for i in range(10)])
     assert len(take_batch(q, 0, 100, 10 ** 6, 4)) == 4 and len(q) == 6
+
+
+def test_server_waits_for_budget_and_admits_when_memory_frees():
+    # the threaded server with a stand-in renderer (no GPU): three requests
+    # of 60, 60 and 30 bytes under a 100-byte budget.  The second does not
+    # fit beside the first and must wait until the first completes; the
+    # third may not overtake it (same scene).  In-flight bytes never exceed
+    # the budget.
+    import threading
+    import time
+    from types import SimpleNamespace
+
+    from paper_2604_24994_amd.serve import Server
+
+    release = {0: threading.Event(), 1: threading.Event(), 2: threading.Event()}
+    started = []
+
+    def render(scene, cams, stream):
+        for c in cams:
+            started.append(c.i)
+        for c in cams:
+            release[c.i].wait(5)
+        return [c.i for c in cams]
+
+    sizes = {0: 60, 1: 60, 2: 30}
+    srv = Server({0: object()}, hbm_budget_bytes=100, render_fn=render, sizer=lambda sc, cam: sizes[cam.i],
+                 streams=False, n_workers=2)
+    try:
+        cams = [SimpleNamespace(i=i, width=4, height=4) for i in range(3)]
+        futs = [srv.submit(0, c) for c in cams]
+        time.sleep(0.3)
+        assert started == [0]                 # 1 (60 B) waits beside 0 (60 B); 2 may not overtake 1
+        release[0].set()
+        assert futs[0].result(timeout=5) == 0
+        time.sleep(0.3)
+        assert sorted(started) == [0, 1, 2]   # memory freed: 1 and 2 (90 B) admitted together
+        release[1].set()
+        release[2].set()
+        assert [f.result(timeout=5) for f in futs] == [0, 1, 2]
+    finally:
+        for e in release.values():
+            e.set()
+        srv.close()
+    assert srv.peak_inflight <= 100
+    assert max(b for _, b in srv.admitted) <= 100
