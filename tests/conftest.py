@@ -39,3 +39,27 @@ def make_scene(p, power, radius, normal=None, occ_logit=None, rgb=None, tex=None
 @pytest.fixture
 def scene_factory():
     return make_scene
+
+
+def grad_errors(g, ref):
+    """Gradient errors against a reference (oracle) gradient, by the bar of
+    the parity tests: per tensor ``|g - ref|_inf / |ref|_inf`` and per
+    component ``max_c |g_c - ref_c| / max(|ref_c|, 1e-2 |ref|_inf)``.  Both
+    must stay <= 1e-3."""
+    g = np.asarray(g, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64).reshape(g.shape)
+    scale = np.abs(ref).max()
+    if scale == 0:
+        return 0.0 if np.abs(g).max() == 0 else np.inf, 0.0 if np.abs(g).max() == 0 else np.inf
+    err = np.abs(g - ref)
+    per_tensor = err.max() / scale
+    per_comp = (err / np.maximum(np.abs(ref), 1e-2 * scale)).max()
+    return float(per_tensor), float(per_comp)
+
+
+def assert_grad_close(g, ref, name, tol=1e-3, log=print):
+    t, c = grad_errors(g, ref)
+    log(f"  {name:10s} |ref|max {np.abs(np.asarray(ref)).max():.4e}  rel {t:.3e}  per-component {c:.3e}")
+    assert np.abs(np.asarray(ref)).max() > 0, name
+    assert t <= tol, (name, t)
+    assert c <= tol, (name, c)

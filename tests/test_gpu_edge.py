@@ -8,6 +8,7 @@ import torch
 
 import oracle
 import workloads as W
+from conftest import assert_grad_close
 
 pytestmark = pytest.mark.gpu
 
@@ -57,10 +58,7 @@ def test_single_cell_forward_and_backward():
     ref, _ = oracle.adjoint_gradients(sc, cam, G)
     for f in FIELDS:
         g = params[f].grad.cpu().numpy().astype(np.float64)
-        r = np.asarray(ref[f]).reshape(g.shape)
-        err = np.abs(g - r).max() / max(np.abs(r).max(), 1e-30)
-        _flush(f"  grad {f:10s} rel {err:.2e}")
-        assert err <= 1e-3, f
+        assert_grad_close(g, np.asarray(ref[f]).reshape(g.shape), f, log=_flush)
 
 
 def test_coincident_sites():

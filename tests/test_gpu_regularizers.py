@@ -11,6 +11,7 @@ import torch
 
 import oracle
 import workloads as W
+from conftest import assert_grad_close
 
 pytestmark = pytest.mark.gpu
 
@@ -54,9 +55,7 @@ def test_normal_and_sparsity_losses_match_oracle(lam_n, lam_s):
         contrib_ref += vals["contribution"]
         normal_ref += vals["normal"]
     for f in PARAMS:
-        r = _rel(g_gpu[f], g_ref[f])
-        _flush(f"  {f:10s} rel {r:.3e}")
-        assert r <= 1e-3, f
+        assert_grad_close(g_gpu[f], g_ref[f], f, log=_flush)
     c = stats["contribution"].cpu().numpy().astype(np.float64)
     nl = float(stats["normal_loss"].cpu()[0])
     _flush(f"  contribution max err {np.abs(c - contrib_ref).max():.3e} (max {contrib_ref.max():.3f}); "

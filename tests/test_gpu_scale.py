@@ -12,6 +12,7 @@ import torch
 
 import oracle
 import workloads as W
+from conftest import assert_grad_close
 
 pytestmark = pytest.mark.gpu
 PARAMS = ("p", "power", "radius", "normal", "occ_logit", "rgb", "tex")
@@ -70,8 +71,5 @@ def test_c3_training_step_forward_and_gradients_on_sampled_pixels():
         for f in PARAMS:
             g_ref[f] += gr[f].reshape(g_ref[f].shape)
     for f in PARAMS:
-        scale = np.abs(g_ref[f]).max()
-        e = np.abs(g_gpu[f] - g_ref[f]).max()
-        _flush(f"  {f:10s} |g_ref|max {scale:.4e} err {e:.3e} rel {e / max(scale, 1e-30):.3e}")
-        assert scale > 0 and e <= 1e-3 * scale, f
+        assert_grad_close(g_gpu[f], g_ref[f], f, log=_flush)
     scene.destroy()
