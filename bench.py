@@ -86,9 +86,13 @@ def parse():
     ap.add_argument("--width", type=int, default=1600)
     ap.add_argument("--height", type=int, default=1066)
     ap.add_argument("--mode", choices=["train", "fwd"], default="train")
-    ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--serve-seconds", type=float, default=30.0, help="measured serving window (after the warm-up)")
+    ap.add_argument("--serve-warmup", type=float, default=2.0, help="serving warm-up excluded from the statistics")
     ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--cpu-rays", type=int, default=8, help="oracle sample size for the CPU baseline (about 2 s per ray)")
+    ap.add_argument("--recompute-steps", type=int, default=2,
+                    help="recompute-mode training steps timed beside the store-mode ones (0: skip)")
+    ap.add_argument("--cpu-rays", type=int, default=32,
+                    help="oracle sample size for the CPU baseline (about 16 s per ray and core)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-densify", action="store_true", help="skip the densify/prune side measurement")
     ap.add_argument("--steiner-cand", type=int, default=-1,
@@ -103,22 +107,66 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(sc, cam, n_rays: int):
-    """The FP64 oracle (walk form) on ``n_rays`` seeded central pixels of one
-    view, timed on this host's cores."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_ORACLE = {}   # scene tensors and cameras shared with forked oracle workers
+
+
+def _oracle_rays(item):
     import oracle
+    torch.set_num_threads(1)
+    v, pix = item
+    oracle.render_walk(_ORACLE["scene"], _ORACLE["cams"][v], pix=pix, S=_ORACLE["S"], chunk_elems=1 << 22)
+    return len(pix)
+
+
+def _oracle_timed(sc, cams, items, procs: int) -> float:
+    """Seconds for the oracle to walk the (view, pixels) items on ``procs``
+    forked worker processes of one torch thread each."""
+    import multiprocessing as mp
     from oracle.cell import scene_tensors
-    rng = np.random.default_rng(11)
-    xs = rng.integers(cam.width // 4, 3 * cam.width // 4, size=n_rays)
-    ys = rng.integers(cam.height // 4, 3 * cam.height // 4, size=n_rays)
-    pix = np.unique(ys * cam.width + xs)
-    S = scene_tensors(sc)
+    _ORACLE.update(scene=sc, cams=cams, S=scene_tensors(sc))
     t0 = time.perf_counter()
-    oracle.render_walk(sc, cam, pix=pix, S=S, chunk_elems=1 << 24)
-    dt = time.perf_counter() - t0
-    return {"value": len(pix) / dt / 1e6, "unit": "Mrays/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"{len(pix)} seeded central pixels of view 0 at {sc.n} cells, FP64 brute-force walk, {dt:.1f} s"}
+    with mp.get_context("fork").Pool(procs) as pool:
+        sum(pool.map(_oracle_rays, items, chunksize=1))
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(sc, cams, n_rays: int, c1: bool = True):
+    """The FP64 oracle (walk form, as written) on a bounded seeded sample of
+    the bench workload, timed on all host cores (one worker process per core,
+    rays split between them), plus the full 128x128 image of the 1,024-cell
+    scene."""
+    import workloads as W
+    procs = min(os.cpu_count() or 1, 16)
+    n_rays = max(n_rays, procs)
+    per = max(1, n_rays // len(cams))
+    items = []
+    for v, c in enumerate(cams):
+        pix = W.pixel_sample(c, per, 11 + v)
+        items += [(v, pix[i:i + 1]) for i in range(len(pix))]
+    items = items[:n_rays]
+    dt = _oracle_timed(sc, cams, items, procs)
+    res = {"value": len(items) / dt / 1e6, "unit": "Mrays/s", "cores": procs, "kind": "oracle",
+           "cpu": cpu_model(), "host_cpus": os.cpu_count(),
+           "sample": f"{len(items)} seeded pixels over the {len(cams)} views at {sc.n} cells, FP64 brute-force walk "
+                     f"(O(cells) per step), {procs} worker processes, {dt:.1f} s"}
+    if c1:
+        sc1, cam1 = W.c1_scene(), W.c1_camera()
+        rows = [(0, np.arange(y * cam1.width, (y + 1) * cam1.width)) for y in range(cam1.height)]
+        dt1 = _oracle_timed(sc1, [cam1], rows, procs)
+        res["c1_full_image"] = {"cells": sc1.n, "rays": cam1.n_rays, "seconds": round(dt1, 2),
+                                "mrays_s": round(cam1.n_rays / dt1 / 1e6, 6)}
+    return res
 
 
 def _rate(fn, rays):
@@ -131,6 +179,56 @@ def _rate(fn, rays):
     e1.record()
     torch.cuda.synchronize()
     return round(rays / (e0.elapsed_time(e1) / 2 * 1e-3) / 1e6, 2)
+
+
+# VALU issue rate of the chip (unpacked FP32 lane-operations per second):
+# 256 CUs x 64 lanes x 2.4 GHz.
+VALU_LANE_OPS = 256 * 64 * 2.4e9
+# Algorithmic bytes a walk step gathers (read once from HBM or cache), by the
+# model's data: per cell entered its site and radius (16 B), cull radius (4),
+# face range (8); per exit face scanned its neighbour (4) and plane (16); per
+# piece (sphere hit) the face count and normal (20) and the detail sites'
+# positions and displacements (96); per contribution the texture (1,632) and
+# base colour (12).  Raster faces read for a piece are counted among the
+# exit faces of that cell.
+WALK_BYTES = {"cell": 28, "face": 20, "piece": 116, "contribution": 1644}
+
+
+def work_counters(pf, scene, cams, out, rays, rates):
+    """Work counters of one plain raster and one walk of the bench views:
+    per-ray averages, the lane efficiency of the composite, its VALU fraction
+    by the algorithmic op counts (115 per pixel-cell test, 1,300 per
+    contribution), and the walk's gathered bytes per step and rate."""
+    rc = torch.zeros(6, dtype=torch.int64, device="cuda")
+    tc = torch.zeros(6, dtype=torch.int64, device="cuda")
+    pf.render_raster(scene, cams, out=out, counters=rc)
+    pf.render_trace(scene, cams, out=out, counters=tc)
+    torch.cuda.synchronize()
+    r, t = [int(x) for x in rc.cpu()], [int(x) for x in tc.cpu()]
+    ras_s = rays / (rates["raster_fwd_mrays_s"] * 1e6)
+    walk_s = rays / (rates["trace_fwd_mrays_s"] * 1e6)
+    ops = 115 * r[0] + 1300 * r[2]
+    raster = {"pixel_cell_tests": r[0], "sphere_hits": r[1], "contributions": r[2],
+              "wave_steps": r[3], "wave_steps_with_piece": r[4], "wave_steps_shaded": r[5],
+              "tests_per_ray": round(r[0] / rays, 2), "contributions_per_ray": round(r[2] / rays, 2),
+              "lanes_per_piece_step": round(r[1] / max(1, r[4]), 2),
+              "lanes_per_shaded_step": round(r[2] / max(1, r[5]), 2),
+              "alg_ops": ops, "valu_frac_alg": round(ops / (ras_s * VALU_LANE_OPS), 4)}
+    gathered = (WALK_BYTES["cell"] * t[1] + WALK_BYTES["face"] * t[4] + WALK_BYTES["piece"] * t[2] +
+                WALK_BYTES["contribution"] * t[3])
+    walk = {"rays": t[0], "cells_per_ray": round(t[1] / max(1, t[0]), 2),
+            "pieces_per_ray": round(t[2] / max(1, t[0]), 2), "contributions_per_ray": round(t[3] / max(1, t[0]), 2),
+            "faces_per_cell": round(t[4] / max(1, t[1]), 2), "max_cells_one_ray": t[5],
+            "bytes_per_cell_walked": round(gathered / max(1, t[1]), 1),
+            "gathered_gb_s": round(gathered / walk_s / 1e9, 1), "hbm_peak_gb_s": HBM_PEAK_GBS}
+    return raster, walk
+
+
+def walk_cells_per_ray(pf, scene, cams, out):
+    tc = torch.zeros(6, dtype=torch.int64, device="cuda")
+    pf.render_trace(scene, cams, out=out, counters=tc)
+    t = [int(x) for x in tc.cpu()]
+    return round(t[1] / max(1, t[0]), 3), round(t[3] / max(1, t[0]), 3)
 
 
 def steiner_side(pf, W, sc, params, cams, out, rays, args):
@@ -149,15 +247,39 @@ def steiner_side(pf, W, sc, params, cams, out, rays, args):
     scene = pf.build_scene(aug, sigma_scale=sc.sigma_scale, tau=sc.tau)
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - t0) * 1e3
-    ref = pf.render_raster(pf.build_scene(base, sigma_scale=sc.sigma_scale, tau=sc.tau), cams)
+    base_scene = pf.build_scene(base, sigma_scale=sc.sigma_scale, tau=sc.tau)
+    ref = [im.clone() for im in pf.render_raster(base_scene, cams)]
     img = pf.render_raster(scene, cams)
     change = max(float((a - b).abs().max()) for a, b in zip(img, ref))
+    cells_before, contrib_before = walk_cells_per_ray(pf, base_scene, cams, out)
+    cells_after, contrib_after = walk_cells_per_ray(pf, scene, cams, out)
+    base_scene.destroy()
     res = {"candidates_per_round": n_cand, "kept_per_round": cells["round_counts"],
            "cells_added": int(cells["p"].shape[0]), "insert_ms": round(ms, 1), "build_ms": round(build_ms, 1),
            "trace_fwd_mrays_s": _rate(lambda: pf.render_trace(scene, cams, out=out), rays),
            "raster_fwd_mrays_s": _rate(lambda: pf.render_raster(scene, cams, out=out), rays),
+           "walk_cells_per_ray": [cells_before, cells_after],
+           "walk_contributions_per_ray": [contrib_before, contrib_after],
            "max_image_change": float(f"{change:.3g}")}
     scene.destroy()
+    # the paper's parameterisation, power = r^2: same sites and radii
+    tied = dict(base)
+    tied["power"] = (base["radius"] * base["radius"]).contiguous()
+    cells_t = pf.steiner(tied, z)
+    aug_t = pf.append_empty_cells(tied, cells_t)
+    s_tied = pf.build_scene(tied, sigma_scale=sc.sigma_scale, tau=sc.tau)
+    s_aug = pf.build_scene(aug_t, sigma_scale=sc.sigma_scale, tau=sc.tau)
+    ref = [im.clone() for im in pf.render_raster(s_tied, cams)]
+    img = pf.render_raster(s_aug, cams)
+    change_t = max(float((a - b).abs().max()) for a, b in zip(img, ref))
+    tb, _ = walk_cells_per_ray(pf, s_tied, cams, out)
+    ta, _ = walk_cells_per_ray(pf, s_aug, cams, out)
+    res["tied_power"] = {"cells_added": int(cells_t["p"].shape[0]), "walk_cells_per_ray": [tb, ta],
+                         "trace_fwd_mrays_s": [_rate(lambda: pf.render_trace(s_tied, cams, out=out), rays),
+                                               _rate(lambda: pf.render_trace(s_aug, cams, out=out), rays)],
+                         "max_image_change": float(f"{change_t:.3g}")}
+    s_tied.destroy()
+    s_aug.destroy()
     return res
 
 
@@ -214,6 +336,12 @@ def main():
     sc = W.c3_scene(n=args.cells)
     cams = W.c3_cameras(n_views=args.views, width=args.width, height=args.height)
     log(f"inputs generated in {time.time() - t0:.1f}s")
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before the GPU is initialised: the oracle runs in forked worker processes
+        log("timing the oracle sample on the host CPU")
+        cpu = cpu_baseline(sc, cams, args.cpu_rays)
+        log(f"cpu baseline: {cpu}")
     params = {k: v.requires_grad_(args.mode == "train") for k, v in pf.to_device_params(sc).items()}
     rays = sum(c.n_rays for c in cams)
     out = torch.empty(4 * rays, dtype=torch.float32, device="cuda")
@@ -223,7 +351,7 @@ def main():
     held = {"scene": None}
     gen = torch.Generator(device="cuda").manual_seed(11)
 
-    def step():
+    def step(state_mode=pf.STORE):
         # the sites move a little between steps, as after an optimiser update,
         # and the adjacency is rebuilt (seeded by the previous step's)
         with torch.no_grad():
@@ -238,7 +366,7 @@ def main():
             return scene
         for v in params.values():
             v.grad = None
-        imgs = pf.render_raster_diff(scene, cams)
+        imgs = pf.render_raster_diff(scene, cams, state_mode=state_mode)
         rgb = torch.cat([im.reshape(-1, 4)[:, :3] for im in imgs])
         loss = ((rgb - tgt) ** 2).mean()
         loss.backward()
@@ -267,10 +395,34 @@ def main():
     kms = {k: v[1] / args.steps for k, v in prof.items()}
     log(f"step {ms:.2f} ms, kernel ms/step: " + ", ".join(f"{k}={v:.2f}" for k, v in sorted(kms.items(), key=lambda kv: -kv[1])))
 
+    extra = {}
+    if args.mode == "train" and args.recompute_steps > 0:
+        # the same step with the traversal replayed inside the backward (no
+        # records kept between forward and backward), beside a store step's
+        # memory high-water mark
+        mem = {}
+        for name, mode in (("store", pf.STORE), ("recompute", pf.RECOMPUTE)):
+            torch.cuda.synchronize()
+            pf.memory_stats(reset_peak=True)
+            step(mode)
+            torch.cuda.synchronize()
+            mem[name] = pf.memory_stats()["peak"]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.recompute_steps):
+            step(pf.RECOMPUTE)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        rms = e0.elapsed_time(e1) / args.recompute_steps
+        extra["recompute"] = {"ms_per_step": round(rms, 3), "mrays_s": round(rays / (rms * 1e-3) / 1e6, 3),
+                              "steps": args.recompute_steps,
+                              "library_peak_bytes": mem["recompute"], "store_library_peak_bytes": mem["store"],
+                              "window_bytes": 1 << 30}
+        log(f"recompute: {extra['recompute']}")
+
     # side measurements on one built scene (not part of the timed step)
     scene = pf.build_scene({k: v.detach() for k, v in params.items()}, sigma_scale=sc.sigma_scale, tau=sc.tau)
     box = scene.info()
-    extra = {}
     for name, fn in (("raster_fwd", lambda: pf.render_raster(scene, cams, out=out)),
                      ("trace_fwd", lambda: pf.render_trace(scene, cams, out=out))):
         fn()
@@ -283,6 +435,9 @@ def main():
         torch.cuda.synchronize()
         extra[name + "_mrays_s"] = round(rays / (e0.elapsed_time(e1) / 2 * 1e-3) / 1e6, 2)
     log(f"side: {extra}")
+    extra["raster_work"], extra["walk_work"] = work_counters(pf, scene, cams, out, rays, extra)
+    log(f"raster work: {extra['raster_work']}")
+    log(f"walk work: {extra['walk_work']}")
     if not args.no_densify:
         extra["densify"] = densify_side(pf, sc, params, args)
         log(f"densify: {extra['densify']}")
@@ -292,12 +447,12 @@ def main():
     serving = None
     if args.serve_seconds > 0:
         from paper_2604_24994_amd import serve
-        reqs = W.request_stream(args.serve_rate, args.serve_seconds)
-        serving = {"rate_req_s": args.serve_rate, "seconds": args.serve_seconds}
+        reqs = W.request_stream(args.serve_rate, args.serve_warmup + args.serve_seconds)
+        serving = {"rate_req_s": args.serve_rate, "seconds": args.serve_seconds, "warmup_s": args.serve_warmup}
         for name, srv in (("batched", serve.Server({0: scene}, hbm_budget_bytes=16 << 30)),
                           ("plain", serve.PlainServer({0: scene}))):
             try:
-                st = serve.replay(srv, reqs)
+                st = serve.replay(srv, reqs, warmup_s=args.serve_warmup)
             finally:
                 srv.close()
             serving[name] = {k: round(v, 3) for k, v in st.items()}
@@ -341,9 +496,8 @@ def main():
         "serving": serving,
         "roofline": roof,
     }
-    if not args.no_cpu_baseline:
-        log("timing the oracle sample on the host CPU")
-        res["cpu_baseline"] = cpu_baseline(sc, cams[0], args.cpu_rays)
+    if cpu is not None:
+        res["cpu_baseline"] = cpu
     print(json.dumps(res), flush=True)
 
 

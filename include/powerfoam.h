@@ -121,6 +121,17 @@ typedef struct {
                                 (the state becomes a recompute-mode state).
                                 Recompute mode: the backward's replay window
                                 (0: 1 GiB).                                   */
+  unsigned long long* counters; /* device, may be NULL: work counters of the
+                                call's kernels, accumulated (+=) over every
+                                composite / walk launch of the call (a store
+                                pass repeated after the record pool was
+                                resized counts twice).  Raster, 6 entries:
+                                pixel-cell tests, sphere hits, contributions,
+                                (wave, cell) steps that tested, that computed
+                                a piece, that shaded.  Walk, 6 entries: rays,
+                                cells walked, pieces computed (sphere hits),
+                                contributions, exit faces scanned, the most
+                                cells one ray walked (maximum).             */
 } pf_render_opts;
 
 /* Caller allocator.  alloc returns a device block of at least `bytes` bytes

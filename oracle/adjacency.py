@@ -33,8 +33,10 @@ def lifted_hull_edges(p, w):
     return np.array(sorted(edges), dtype=np.int64).reshape(-1, 2)
 
 
-def lp_face_exists(p, w, i: int, j: int, box: float = 1e3) -> bool:
-    """True iff cells i and j share a face of positive area (within |x| <= box)."""
+def lp_face_exists(p, w, i: int, j: int, box=1e3) -> bool:
+    """True iff cells i and j share a face of positive area inside the box:
+    ``box`` is a half-width (the cube ``|x_a| <= box``) or a pair
+    ``(lo[3], hi[3])`` of corners."""
     from scipy.optimize import linprog
     p = np.asarray(p, dtype=np.float64)
     w = np.asarray(w, dtype=np.float64)
@@ -51,7 +53,11 @@ def lp_face_exists(p, w, i: int, j: int, box: float = 1e3) -> bool:
             continue
         rows.append(np.r_[2.0 * (p[k] - p[i]), 1.0])
         rhs.append((p[k] @ p[k]) - (p[i] @ p[i]) - w[k] + w[i])
-    bounds = [(-box, box)] * 3 + [(None, 1.0)]
+    if np.ndim(box) == 0:
+        lo, hi = -float(box) * np.ones(3), float(box) * np.ones(3)
+    else:
+        lo, hi = np.asarray(box[0], dtype=np.float64), np.asarray(box[1], dtype=np.float64)
+    bounds = [(lo[a], hi[a]) for a in range(3)] + [(None, 1.0)]
     res = linprog(c=[0, 0, 0, -1.0], A_ub=np.array(rows) if rows else None,
                   b_ub=np.array(rhs) if rows else None, A_eq=a_eq, b_eq=b_eq,
                   bounds=bounds, method="highs")

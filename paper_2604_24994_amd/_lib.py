@@ -37,7 +37,7 @@ class PfBuildOpts(C.Structure):
 
 class PfRenderOpts(C.Structure):
     _fields_ = [("t_min", C.c_float), ("max_steps", C.c_int32), ("state_mode", C.c_int32),
-                ("workspace_limit", C.c_int64)]
+                ("workspace_limit", C.c_int64), ("counters", C.c_void_p)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)

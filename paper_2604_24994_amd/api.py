@@ -157,11 +157,16 @@ def update_scene(scene: Scene, params, stream=None) -> Scene:
 STORE, RECOMPUTE = 0, 1
 
 
-def _opts(t_min: float, max_steps: int, state_mode: int = STORE, workspace_limit: int = 0) -> L.PfRenderOpts:
+def _opts(t_min: float, max_steps: int, state_mode: int = STORE, workspace_limit: int = 0,
+          counters: Optional[torch.Tensor] = None) -> L.PfRenderOpts:
     if state_mode not in (STORE, RECOMPUTE):
         raise ValueError("state_mode must be STORE (0) or RECOMPUTE (1)")
+    if counters is not None and (counters.dtype != torch.int64 or counters.numel() < 6 or not counters.is_cuda
+                                 or not counters.is_contiguous()):
+        raise ValueError("counters must be a contiguous int64 device tensor of at least 6 entries")
     return L.PfRenderOpts(t_min=float(t_min), max_steps=int(max_steps), state_mode=int(state_mode),
-                          workspace_limit=int(workspace_limit))
+                          workspace_limit=int(workspace_limit),
+                          counters=counters.data_ptr() if counters is not None else None)
 
 
 def _alloc_images(shapes, device):
@@ -178,22 +183,30 @@ def _split(buf, shapes):
     return out
 
 
-def render_raster(scene: Scene, cams, t_min: float = 1e-6, stream=None, out: Optional[torch.Tensor] = None):
-    """pf_render_raster: list of [H,W,4] float32 images (one per camera)."""
+def render_raster(scene: Scene, cams, t_min: float = 1e-6, stream=None, out: Optional[torch.Tensor] = None,
+                  counters: Optional[torch.Tensor] = None):
+    """pf_render_raster: list of [H,W,4] float32 images (one per camera).
+    counters: optional int64 device tensor [6] that the composite's work
+    counters are added to (pixel-cell tests, sphere hits, contributions,
+    (wave, cell) steps tested / with a piece / shaded)."""
     arr, nc, shapes = _cams(cams)
     buf = out if out is not None else _alloc_images(shapes, scene.params["p"].device)
-    opts = _opts(t_min, 0)
+    opts = _opts(t_min, 0, counters=counters)
     L.check(L.load().pf_render_raster(scene.handle, arr, nc, C.byref(opts), C.c_void_p(buf.data_ptr()),
                                       None, C.c_void_p(_stream_ptr(stream))))
     return _split(buf, shapes)
 
 
 def render_trace(scene: Scene, cams, t_min: float = 1e-6, max_steps: int = 4096, stream=None,
-                 out: Optional[torch.Tensor] = None, return_truncated: bool = False):
-    """pf_render_trace: list of [H,W,4] float32 images (one per camera)."""
+                 out: Optional[torch.Tensor] = None, return_truncated: bool = False,
+                 counters: Optional[torch.Tensor] = None):
+    """pf_render_trace: list of [H,W,4] float32 images (one per camera).
+    counters: optional int64 device tensor [6] that the walk's work counters
+    are added to (rays, cells walked, pieces, contributions, exit faces
+    scanned, most cells on one ray)."""
     arr, nc, shapes = _cams(cams)
     buf = out if out is not None else _alloc_images(shapes, scene.params["p"].device)
-    opts = _opts(t_min, max_steps)
+    opts = _opts(t_min, max_steps, counters=counters)
     trunc = C.c_int64(0)
     L.check(L.load().pf_render_trace(scene.handle, arr, nc, C.byref(opts), C.c_void_p(buf.data_ptr()),
                                      C.byref(trunc) if return_truncated else None, None,

@@ -258,12 +258,14 @@ namespace {
 // The pass that produces a forward state's records: kind 0 tile raster,
 // kind 1 ray walk (one view after the other).
 pf_status run_pass(pf_scene* scene, const std::vector<pf_camera>& cams, int kind, float t_min, int max_steps,
-                   float* rgba, unsigned long long* trunc_dev, hipStream_t s, const pf::RecBuf* rec) {
+                   float* rgba, unsigned long long* trunc_dev, hipStream_t s, const pf::RecBuf* rec,
+                   unsigned long long* counters = nullptr) {
   const int ncam = (int)cams.size();
-  if (kind == 0) return pf::raster_views(scene->s, cams.data(), ncam, t_min, rgba, s, rec);
+  if (kind == 0) return pf::raster_views(scene->s, cams.data(), ncam, t_min, rgba, s, rec, nullptr, counters);
   int64_t off = 0;
   for (int c = 0; c < ncam; ++c) {
-    const pf_status st = pf::trace_view(scene->s, cams[c], t_min, max_steps, rgba + 4 * off, trunc_dev, s, rec, c, off);
+    const pf_status st = pf::trace_view(scene->s, cams[c], t_min, max_steps, rgba + 4 * off, trunc_dev, s, rec, c, off,
+                                        0, -1, nullptr, counters);
     if (st != PF_OK) return st;
     off += (int64_t)cams[c].width * cams[c].height;
   }
@@ -395,7 +397,7 @@ Caps store_caps(const pf_fwd_state* fs, int64_t need_rec, int64_t need_seg) {
 // (*demoted = true; the image of the pass is complete either way).  rgba
 // receives the image; trunc_dev (walk only) is zeroed before each attempt.
 pf_status fill_records(pf_fwd_state* fs, float* rgba, unsigned long long* trunc_dev, hipStream_t s,
-                       const char* who, bool* demoted) {
+                       const char* who, bool* demoted, unsigned long long* counters = nullptr) {
   *demoted = false;
   pf_scene* scene = fs->scene;
   const int64_t npix = fs->st.npix;
@@ -409,7 +411,8 @@ pf_status fill_records(pf_fwd_state* fs, float* rgba, unsigned long long* trunc_
       const hipError_t e = hipMemsetAsync(trunc_dev, 0, sizeof(unsigned long long), s);
       if (e != hipSuccess) st = hip_status(e, who);
     }
-    if (st == PF_OK) st = run_pass(scene, fs->cams, fs->kind, fs->t_min, fs->max_steps, rgba, trunc_dev, s, &fs->st.rec);
+    if (st == PF_OK)
+      st = run_pass(scene, fs->cams, fs->kind, fs->t_min, fs->max_steps, rgba, trunc_dev, s, &fs->st.rec, counters);
     unsigned long long used[3];
     if (st == PF_OK) st = pool_usage(fs->st.rec, s, used, who);
     if (st != PF_OK) return st;
@@ -564,8 +567,9 @@ pf_status pf_render_raster(pf_scene* scene, const pf_camera* cams, int32_t ncam,
   if (mode != 0 && mode != 1) return invalid("pf_render_raster: state_mode must be 0 (store) or 1 (recompute)");
   if (limit < 0) return invalid("pf_render_raster: workspace_limit must be >= 0");
   hipStream_t s = (hipStream_t)stream;
+  unsigned long long* counters = opts ? opts->counters : nullptr;
   if (!state || mode == 1) {
-    st = pf::raster_views(scene->s, cams, ncam, t_min, rgba, s);
+    st = pf::raster_views(scene->s, cams, ncam, t_min, rgba, s, nullptr, nullptr, counters);
     if (st != PF_OK || !state) return st;
     return new_state(scene, cams, ncam, 0, 1, t_min, 0, limit, s, state, "pf_render_raster");
   }
@@ -573,7 +577,7 @@ pf_status pf_render_raster(pf_scene* scene, const pf_camera* cams, int32_t ncam,
   st = new_state(scene, cams, ncam, 0, 0, t_min, 0, limit, s, &fs, "pf_render_raster");
   if (st != PF_OK) return st;
   bool demoted = false;
-  st = fill_records(fs, rgba, nullptr, s, "pf_render_raster", &demoted);
+  st = fill_records(fs, rgba, nullptr, s, "pf_render_raster", &demoted, counters);
   if (st != PF_OK) {
     free_state_mem(fs);
     delete fs;
@@ -612,14 +616,15 @@ pf_status pf_render_trace(pf_scene* scene, const pf_camera* cams, int32_t ncam, 
   }
   pf_fwd_state* fs = nullptr;
   const std::vector<pf_camera> cv(cams, cams + ncam);
+  unsigned long long* counters = opts ? opts->counters : nullptr;
   if (!state || mode == 1) {
-    st = run_pass(scene, cv, 1, t_min, max_steps, rgba, trunc, s, nullptr);
+    st = run_pass(scene, cv, 1, t_min, max_steps, rgba, trunc, s, nullptr, counters);
     if (st == PF_OK && state)
       st = new_state(scene, cams, ncam, 1, 1, t_min, max_steps, limit, s, &fs, "pf_render_trace");
   } else {
     st = new_state(scene, cams, ncam, 1, 0, t_min, max_steps, limit, s, &fs, "pf_render_trace");
     bool demoted = false;
-    if (st == PF_OK) st = fill_records(fs, rgba, trunc, s, "pf_render_trace", &demoted);
+    if (st == PF_OK) st = fill_records(fs, rgba, trunc, s, "pf_render_trace", &demoted, counters);
   }
   if (st == PF_OK && truncated) {
     unsigned long long h = 0;

@@ -373,7 +373,10 @@ __device__ inline void tile_pixel(int tiles_x, int& px, int& py, int tile = -1) 
   py = ty * TILE + (w >> 1) * 8 + (lane >> 3);
 }
 
-template <bool STORE>
+// COUNT: the work counters of the composite are added to counters[0..5]
+// (RASTER_COUNTERS): pixel-cell tests, sphere hits, contributions, and the
+// (wave, cell) steps that tested, that computed a piece, that shaded.
+template <bool STORE, bool COUNT>
 __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ views, int nview, SceneDev S,
                                                 const unsigned long long* __restrict__ list,
                                                 const uint32_t* __restrict__ tile_off, float t_min,
@@ -383,8 +386,7 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
                                                 unsigned long long* __restrict__ rec_counter,
                                                 int4* __restrict__ rec_seg, int2* __restrict__ rec_wtail,
                                                 int64_t tile_first, int64_t wtail_base, int64_t rec_cap,
-                                                int64_t seg_cap, int64_t count,
-                                                unsigned long long* __restrict__ work) {
+                                                int64_t seg_cap, unsigned long long* __restrict__ counters) {
   // the tile's sorted cells are staged RB at a time: list entry and the cell
   // record fields every lane needs, loaded by the whole workgroup at once
   __shared__ int s_ci[RB];
@@ -394,18 +396,13 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
   __shared__ int s_row[RB];
   __shared__ int s_nr[RB];
   __shared__ int s_more[4];
-  __shared__ long long s_item;
 
-  // work items = the launch's tiles: one per workgroup, or (work != null, a
-  // persistent launch) taken in turn from the counter until none is left
-  for (int64_t item = blockIdx.x;;) {
-  if (work) {
-    if (threadIdx.x == 0) s_item = (long long)atomicAdd(work, 1ull);
-    __syncthreads();
-    item = s_item;
-    __syncthreads();
-  }
-  if (item >= count) break;
+  // one workgroup per work item (a tile of one of the launch's views); the
+  // hardware dispatcher hands the next item to whichever CU frees up, so the
+  // tiles of all views of a call (the requests of a serving batch) share
+  // the CUs.  (A persistent loop over items held twice the registers and
+  // halved the occupancy.)
+  const int64_t item = blockIdx.x;
   // tile of the view group; its view: the last one whose tiles start at or before it
   const int64_t gtile = tile_first + item;
   int lo = 0, hi = nview - 1;
@@ -432,6 +429,7 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
   long long rblk = 0, sblk = 0;   // the wave's current record / segment block
   long long cblk = -1;            // first slot (header) of the wave's current segment block
   int rleft = 0, sleft = 0;
+  unsigned long long n_test = 0, n_hit = 0, n_contrib = 0, n_step = 0, n_step_hit = 0, n_step_shade = 0;
   for (uint32_t b0 = e0; b0 < e1; b0 += RB) {
     {
       const uint32_t e = b0 + threadIdx.x;
@@ -454,7 +452,13 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
       const float rho = s_rho[q];
       const Local L = make_local(R, g.x, g.y, g.z);
       const bool hit = live && (rho >= 0.0f) && (L.qq < (double)rho * (double)rho);
+      if constexpr (COUNT) {
+        n_test += (unsigned long long)__popcll(__ballot(live));
+        n_hit += (unsigned long long)__popcll(__ballot(hit));
+        ++n_step;
+      }
       if (!__any(hit)) continue;
+      if constexpr (COUNT) ++n_step_hit;
       const float* tx = S.tex + (int64_t)ci * (KD * TEXW);
       Piece P;
       P.alpha = 0.0f;
@@ -465,6 +469,11 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
         if (P.alpha > 0.0f) radiance(tx, S.rgb + 3 * (int64_t)ci, P.ux, P.uy, R.fx, R.fy, R.fz, S.tau, r, gg, b);
       }
       const bool contrib = hit && P.alpha > 0.0f;
+      if constexpr (COUNT) {
+        const uint64_t mc = __ballot(contrib);
+        n_contrib += (unsigned long long)__popcll(mc);
+        n_step_shade += mc ? 1ull : 0ull;
+      }
       if constexpr (STORE) {
         const uint64_t m = __ballot(contrib);
         if (m) {
@@ -535,7 +544,15 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
       if (sblk + j < seg_cap) rec_seg[sblk + j] = make_int4(0, 0, 0, 0);
     if (lane == 0) rec_wtail[(wtail_base + item) * 4 + wave] = make_int2((int)cblk, SBLK - sleft);
   }
-  if (!work) break;
+  if constexpr (COUNT) {
+    if (lane == 0) {
+      atomicAdd(&counters[0], n_test);
+      atomicAdd(&counters[1], n_hit);
+      atomicAdd(&counters[2], n_contrib);
+      atomicAdd(&counters[3], n_step);
+      atomicAdd(&counters[4], n_step_hit);
+      atomicAdd(&counters[5], n_step_shade);
+    }
   }
 }
 
@@ -627,7 +644,11 @@ __global__ void __launch_bounds__(256) k_start_final(const double* __restrict__ 
 // Six waves per SIMD (at most 80 VGPRs): the walk is bound by the latency of
 // its per-step gathers, and occupancy hides it (100 Mrays/s at the three
 // waves that 136 unconstrained VGPRs allow, 125 at six).
-template <bool STORE>
+// COUNT: the walk's work counters are added to counters[0..5]
+// (TRACE_COUNTERS): rays walked, cells walked, pieces computed (sphere
+// hits), contributions, exit faces scanned, and the most cells one ray
+// walked (maximum).
+template <bool STORE, bool COUNT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6)))
 k_trace(ViewArgs v, int64_t tile_first, SceneDev S, const int32_t* __restrict__ start,
                                                float t_min, int max_steps, float* __restrict__ rgba,
@@ -635,7 +656,8 @@ k_trace(ViewArgs v, int64_t tile_first, SceneDev S, const int32_t* __restrict__ 
                                                int4* __restrict__ rec_ri, float4* __restrict__ rec_rf,
                                                float* __restrict__ rec_rt, int32_t* __restrict__ rec_head,
                                                unsigned long long* __restrict__ rec_counter,
-                                               int4* __restrict__ rec_seg, int64_t rec_cap, int64_t seg_cap) {
+                                               int4* __restrict__ rec_seg, int64_t rec_cap, int64_t seg_cap,
+                                               unsigned long long* __restrict__ counters) {
   int px, py;
   tile_pixel(v.tiles_x, px, py, (int)(tile_first + blockIdx.x));
   const bool inside = px < v.cam.width && py < v.cam.height;
@@ -654,6 +676,9 @@ k_trace(ViewArgs v, int64_t tile_first, SceneDev S, const int32_t* __restrict__ 
   // update them together
   long long rblk = 0, sblk = 0;
   int rleft = 0, sleft = 0;
+  unsigned long long n_pieces = 0, n_contrib = 0, n_faces = 0;
+  int n_steps = 0;
+  const bool walked = live && cell >= 0;
   if (live && cell >= 0) {
     int step = 0;
     for (; step < max_steps; ++step) {
@@ -671,6 +696,10 @@ k_trace(ViewArgs v, int64_t tile_first, SceneDev S, const int32_t* __restrict__ 
         if (P.alpha > 0.0f) {
           radiance(tx, S.rgb + 3 * (int64_t)cell, P.ux, P.uy, R.fx, R.fy, R.fz, S.tau, r, gg, b);
           contrib = true;
+        }
+        if constexpr (COUNT) {
+          ++n_pieces;
+          n_contrib += contrib ? 1ull : 0ull;
         }
       }
       if constexpr (STORE) {
@@ -717,6 +746,7 @@ k_trace(ViewArgs v, int64_t tile_first, SceneDev S, const int32_t* __restrict__ 
       // exit: nearest face ahead of the current position that the ray leaves through
       const float s_cur = (float)(t_cur + L.b);
       const int f0 = S.row[cell], f1 = S.row[cell + 1];
+      if constexpr (COUNT) n_faces += (unsigned long long)(f1 - f0);
       float best = INFINITY, best_any = INFINITY;
       int bf = -1, bf_any = -1;
       for (int f = f0; f < f1; ++f) {
@@ -738,6 +768,7 @@ k_trace(ViewArgs v, int64_t tile_first, SceneDev S, const int32_t* __restrict__ 
       cell = nx;
     }
     cut = step == max_steps;
+    n_steps = step + (step < max_steps ? 1 : 0);
   }
   if (inside) {
     float* o = rgba + 4 * ((int64_t)py * v.cam.width + px);
@@ -749,6 +780,27 @@ k_trace(ViewArgs v, int64_t tile_first, SceneDev S, const int32_t* __restrict__ 
   }
   const uint64_t bc = __ballot(cut);
   if ((threadIdx.x & 63) == 0 && bc) atomicAdd(truncated, (unsigned long long)__popcll(bc));
+  if constexpr (COUNT) {
+    unsigned long long w_steps = (unsigned long long)n_steps, w_pieces = n_pieces, w_contrib = n_contrib,
+                       w_faces = n_faces;
+    int w_max = n_steps;
+    for (int o = 32; o > 0; o >>= 1) {
+      w_steps += __shfl_xor(w_steps, o, 64);
+      w_pieces += __shfl_xor(w_pieces, o, 64);
+      w_contrib += __shfl_xor(w_contrib, o, 64);
+      w_faces += __shfl_xor(w_faces, o, 64);
+      w_max = max(w_max, __shfl_xor(w_max, o, 64));
+    }
+    const uint64_t bw = __ballot(walked);
+    if (lane == 0) {
+      atomicAdd(&counters[0], (unsigned long long)__popcll(bw));
+      atomicAdd(&counters[1], w_steps);
+      atomicAdd(&counters[2], w_pieces);
+      atomicAdd(&counters[3], w_contrib);
+      atomicAdd(&counters[4], w_faces);
+      atomicMax(&counters[5], (unsigned long long)w_max);
+    }
+  }
 }
 
 SceneDev scene_dev(const Scene& sc) {
@@ -806,7 +858,7 @@ int64_t raster_group_bytes(int64_t n, int nv, int64_t ntiles, int64_t np) {
   auto b = [](int64_t count, int64_t size) { return std::max<int64_t>(count, 1) * size; };
   const int64_t nvc = (int64_t)nv * n;
   return b(nv, sizeof(ViewDev)) + b(nvc + 1, 4) * 2 + b(nvc, 4) * 2 + b(ntiles + 1, 4) * 2 + b(ntiles, 4) +
-         b(1, 4) + b(1, 8) + scan_scratch_bytes(nvc + 1) + scan_scratch_bytes(ntiles + 1) + b(np, 4) + b(np, 8) * 2;
+         b(1, 4) + scan_scratch_bytes(nvc + 1) + scan_scratch_bytes(ntiles + 1) + b(np, 4) + b(np, 8) * 2;
 }
 
 namespace {
@@ -819,10 +871,10 @@ struct Group {
   uint32_t np = 0;
   Buf<ViewDev> views;
   Buf<uint32_t> cnt, key, off, tcnt, toff, fill, cone_list, cone_n, ptile;
-  Buf<unsigned long long> pval, sorted, work;
+  Buf<unsigned long long> pval, sorted;
   explicit Group(hipStream_t s)
       : views(s), cnt(s), key(s), off(s), tcnt(s), toff(s), fill(s), cone_list(s), cone_n(s), ptile(s), pval(s),
-        sorted(s), work(s) {}
+        sorted(s) {}
 };
 
 // Cull and count (count_only: stops after the pair count), then emit,
@@ -855,7 +907,6 @@ pf_status bin_group(Scene& sc, const pf_camera* cams, Group& G, hipStream_t s, b
   PF_HIP_TRY(G.fill.alloc(ntiles));
   PF_HIP_TRY(G.cone_list.alloc(nvc));
   PF_HIP_TRY(G.cone_n.alloc(1));
-  PF_HIP_TRY(G.work.alloc(1));
   PF_HIP_TRY(hipMemsetAsync(G.cone_n.p, 0, sizeof(uint32_t), s));
   const dim3 g((unsigned)((n + 255) / 256), (unsigned)nv);
   {
@@ -905,29 +956,32 @@ pf_status bin_group(Scene& sc, const pf_camera* cams, Group& G, hipStream_t s, b
   return PF_OK;
 }
 
-// Composite of the group's tiles [first, first + count); with records, the
-// wave segment tails go to rec->wtail from index wtail_base.
-// The plain composite is one persistent launch: PERSIST_GROUPS workgroups
-// take the (view, tile) work items in turn from a counter, so that tiles of
-// all the call's views (the requests of a serving batch) share the CUs and
-// long tile lists do not leave CUs idle at the end of the launch.
-constexpr unsigned PERSIST_GROUPS = 256 * 8;
-
+// Composite of the group's tiles [first, first + count) (one launch, one
+// workgroup per tile); with records, the wave segment tails go to
+// rec->wtail from index wtail_base.
 pf_status composite(Scene& sc, Group& G, float t_min, float* rgba, hipStream_t s, const RecBuf* rec,
-                    int64_t first, int64_t count, int64_t wtail_base) {
+                    int64_t first, int64_t count, int64_t wtail_base, unsigned long long* counters) {
   if (count <= 0) return PF_OK;
   ProfScope ps(rec ? "k_raster_store" : "k_raster", s);
+  const unsigned grid = (unsigned)count;
   if (rec) {
     const RecBuf& rb = *rec;
-    k_raster<true><<<(unsigned)count, 256, 0, s>>>(G.views.p, G.nv, scene_dev(sc), G.sorted.p, G.toff.p, t_min, rgba,
-                                                   rb.ri, rb.rf, rb.rt, rb.head, rb.counter, rb.seg, rb.wtail, first,
-                                                   wtail_base, rb.cap, rb.seg_cap, count, nullptr);
+    if (counters)
+      k_raster<true, true><<<grid, 256, 0, s>>>(G.views.p, G.nv, scene_dev(sc), G.sorted.p, G.toff.p, t_min, rgba,
+                                                rb.ri, rb.rf, rb.rt, rb.head, rb.counter, rb.seg, rb.wtail, first,
+                                                wtail_base, rb.cap, rb.seg_cap, counters);
+    else
+      k_raster<true, false><<<grid, 256, 0, s>>>(G.views.p, G.nv, scene_dev(sc), G.sorted.p, G.toff.p, t_min, rgba,
+                                                 rb.ri, rb.rf, rb.rt, rb.head, rb.counter, rb.seg, rb.wtail, first,
+                                                 wtail_base, rb.cap, rb.seg_cap, nullptr);
+  } else if (counters) {
+    k_raster<false, true><<<grid, 256, 0, s>>>(G.views.p, G.nv, scene_dev(sc), G.sorted.p, G.toff.p, t_min, rgba,
+                                               nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, first, 0,
+                                               0, 0, counters);
   } else {
-    PF_HIP_TRY(hipMemsetAsync(G.work.p, 0, sizeof(unsigned long long), s));
-    const unsigned grid = (unsigned)std::min<int64_t>(count, PERSIST_GROUPS);
-    k_raster<false><<<grid, 256, 0, s>>>(G.views.p, G.nv, scene_dev(sc), G.sorted.p, G.toff.p, t_min, rgba, nullptr,
-                                         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, first, 0, 0, 0, count,
-                                         G.work.p);
+    k_raster<false, false><<<grid, 256, 0, s>>>(G.views.p, G.nv, scene_dev(sc), G.sorted.p, G.toff.p, t_min, rgba,
+                                                nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, first,
+                                                0, 0, 0, nullptr);
   }
   PF_HIP_TRY(hipGetLastError());
   return PF_OK;
@@ -936,7 +990,7 @@ pf_status composite(Scene& sc, Group& G, float t_min, float* rgba, hipStream_t s
 }  // namespace
 
 pf_status raster_views(Scene& sc, const pf_camera* cams, int ncam, float t_min, float* rgba, hipStream_t s,
-                       const RecBuf* rec, const GroupFn* fn) {
+                       const RecBuf* rec, const GroupFn* fn, unsigned long long* counters) {
   const int group = raster_group_size(sc.n, ncam);
   int64_t pix_done = 0, tiles_done = 0;
   for (int c0 = 0; c0 < ncam; c0 += group) {
@@ -949,11 +1003,11 @@ pf_status raster_views(Scene& sc, const pf_camera* cams, int ncam, float t_min, 
     if (st != PF_OK) return st;
     if (fn) {
       const GroupComposite run = [&](int64_t first, int64_t count, const RecBuf* r) {
-        return composite(sc, G, t_min, rgba, s, r, first, count, 0);
+        return composite(sc, G, t_min, rgba, s, r, first, count, 0, counters);
       };
       st = (*fn)(tiles_done, G.ntiles, run);
     } else {
-      st = composite(sc, G, t_min, rgba, s, rec, 0, G.ntiles, tiles_done);
+      st = composite(sc, G, t_min, rgba, s, rec, 0, G.ntiles, tiles_done, counters);
     }
     if (st != PF_OK) return st;
     tiles_done += G.ntiles;
@@ -991,7 +1045,8 @@ pf_status seg_record_total(const int4* seg, int64_t nseg, unsigned long long* to
 
 pf_status trace_view(const Scene& sc, const pf_camera& cam, float t_min, int max_steps, float* rgba,
                      unsigned long long* trunc_dev, hipStream_t s, const RecBuf* rec, int view, int64_t pix_base,
-                     int64_t tile_first, int64_t tile_count) {
+                     int64_t tile_first, int64_t tile_count, const TraceScratch* scratch,
+                     unsigned long long* counters) {
   const int64_t n = sc.n;
   ViewArgs v;
   v.cam = cam;
@@ -999,29 +1054,47 @@ pf_status trace_view(const Scene& sc, const pf_camera& cam, float t_min, int max
   v.tiles_y = (cam.height + TILE - 1) / TILE;
   const int64_t ntiles = tile_count >= 0 ? tile_count : (int64_t)v.tiles_x * v.tiles_y - tile_first;
   if (ntiles <= 0) return PF_OK;
-  const int nb = (int)std::min<int64_t>(1024, (n + 255) / 256);
-  Buf<double> pk(s);
-  Buf<long long> pi(s);
-  Buf<int32_t> start(s);
-  PF_HIP_TRY(pk.alloc(nb));
-  PF_HIP_TRY(pi.alloc(nb));
-  PF_HIP_TRY(start.alloc(1));
+  const int nb = (int)std::min<int64_t>(TRACE_START_BLOCKS, (n + 255) / 256);
+  Buf<double> pk_own(s);
+  Buf<long long> pi_own(s);
+  Buf<int32_t> start_own(s);
+  double* pk = scratch ? scratch->pk : nullptr;
+  long long* pi = scratch ? scratch->pi : nullptr;
+  int32_t* start = scratch ? scratch->start : nullptr;
+  if (!scratch) {
+    PF_HIP_TRY(pk_own.alloc(nb));
+    PF_HIP_TRY(pi_own.alloc(nb));
+    PF_HIP_TRY(start_own.alloc(1));
+    pk = pk_own.p;
+    pi = pi_own.p;
+    start = start_own.p;
+  }
   k_start_partial<<<nb, 256, 0, s>>>(sc.prm.p, sc.prm.power, sc.flags, n, cam.c2w[3], cam.c2w[7], cam.c2w[11],
-                                     pk.p, pi.p);
+                                     pk, pi);
   PF_HIP_TRY(hipGetLastError());
-  k_start_final<<<1, 256, 0, s>>>(pk.p, pi.p, nb, start.p);
+  k_start_final<<<1, 256, 0, s>>>(pk, pi, nb, start);
   PF_HIP_TRY(hipGetLastError());
   ProfScope ps(rec ? "k_trace_store" : "k_trace", s);
   if (rec) {
     const RecBuf& rb = *rec;
-    k_trace<true><<<(unsigned)ntiles, 256, 0, s>>>(v, tile_first, scene_dev(sc), start.p, t_min, max_steps, rgba,
-                                                   trunc_dev,
-                                                   view, rb.ri, rb.rf, rb.rt, rb.head + pix_base, rb.counter,
-                                                   rb.seg, rb.cap, rb.seg_cap);
+    if (counters)
+      k_trace<true, true><<<(unsigned)ntiles, 256, 0, s>>>(v, tile_first, scene_dev(sc), start, t_min, max_steps,
+                                                           rgba, trunc_dev, view, rb.ri, rb.rf, rb.rt,
+                                                           rb.head + pix_base, rb.counter, rb.seg, rb.cap, rb.seg_cap,
+                                                           counters);
+    else
+      k_trace<true, false><<<(unsigned)ntiles, 256, 0, s>>>(v, tile_first, scene_dev(sc), start, t_min, max_steps,
+                                                            rgba, trunc_dev, view, rb.ri, rb.rf, rb.rt,
+                                                            rb.head + pix_base, rb.counter, rb.seg, rb.cap,
+                                                            rb.seg_cap, nullptr);
+  } else if (counters) {
+    k_trace<false, true><<<(unsigned)ntiles, 256, 0, s>>>(v, tile_first, scene_dev(sc), start, t_min, max_steps, rgba,
+                                                          trunc_dev, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                                          nullptr, 0, 0, counters);
   } else {
-    k_trace<false><<<(unsigned)ntiles, 256, 0, s>>>(v, tile_first, scene_dev(sc), start.p, t_min, max_steps, rgba,
-                                                    trunc_dev,
-                                                    0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0);
+    k_trace<false, false><<<(unsigned)ntiles, 256, 0, s>>>(v, tile_first, scene_dev(sc), start, t_min, max_steps,
+                                                           rgba, trunc_dev, 0, nullptr, nullptr, nullptr, nullptr,
+                                                           nullptr, nullptr, 0, 0, nullptr);
   }
   PF_HIP_TRY(hipGetLastError());
   return PF_OK;

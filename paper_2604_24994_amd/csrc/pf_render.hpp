@@ -22,8 +22,12 @@ using GroupFn = std::function<pf_status(int64_t tiles_before, int64_t ntiles, co
 // Without fn: each group is composited whole, with records into rec (null:
 // plain forward), wave segment tails indexed by the call's tile index.
 // With fn: fn decides how each group is composited.
+// counters (device, may be null): RASTER_COUNTERS work counters of the
+// composite, accumulated.
+constexpr int RASTER_COUNTERS = 6;
 pf_status raster_views(Scene& sc, const pf_camera* cams, int ncam, float t_min, float* rgba, hipStream_t s,
-                       const RecBuf* rec = nullptr, const GroupFn* fn = nullptr);
+                       const RecBuf* rec = nullptr, const GroupFn* fn = nullptr,
+                       unsigned long long* counters = nullptr);
 // Views per binning group, 16x16 tiles of a camera.
 int raster_group_size(int64_t n, int ncam);
 int64_t view_tiles(const pf_camera& c);
@@ -38,8 +42,20 @@ pf_status seg_record_total(const int4* seg, int64_t nseg, unsigned long long* to
 // rec: store-mode records (null: plain walk); the records' view index and
 // the offset of this view's pixels in the per-pixel arrays; the tiles
 // [tile_first, tile_first + tile_count) of the view (tile_count < 0: to the end).
+// scratch: device memory of the start-cell search given by the caller (null:
+// taken from the library's allocator for the call).
+struct TraceScratch {
+  double* pk;        // [TRACE_START_BLOCKS] per-block least power distance
+  long long* pi;     // [TRACE_START_BLOCKS] its cell
+  int32_t* start;    // [1] the start cell
+};
+constexpr int TRACE_START_BLOCKS = 1024;
+// counters (device, may be null): TRACE_COUNTERS work counters of the walk,
+// accumulated.
+constexpr int TRACE_COUNTERS = 6;
 pf_status trace_view(const Scene& sc, const pf_camera& cam, float t_min, int max_steps, float* rgba,
                      unsigned long long* trunc_dev, hipStream_t s, const RecBuf* rec = nullptr, int view = 0,
-                     int64_t pix_base = 0, int64_t tile_first = 0, int64_t tile_count = -1);
+                     int64_t pix_base = 0, int64_t tile_first = 0, int64_t tile_count = -1,
+                     const TraceScratch* scratch = nullptr, unsigned long long* counters = nullptr);
 
 }  // namespace pf

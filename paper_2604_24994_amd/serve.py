@@ -6,8 +6,9 @@ each sized by the library's bound on the device memory its render requests
 plus its RGBA output.  A pool of worker threads, each with its own HIP
 stream, repeatedly takes the oldest waiting requests of one scene whose
 bounds fit the free part of the HBM budget (and a ray cap), and renders
-them as ONE batched pf_render_raster call: one persistent composite launch
-over the (request, tile) work items of the whole batch.  Requests arriving
+them as ONE batched pf_render_raster call: one composite launch over the
+(request, tile) work items of the whole batch, one workgroup per item, which
+the hardware dispatcher hands to whichever CU frees up.  Requests arriving
 while batches run join the next batch as soon as a worker and budget free
 up, so device work of consecutive batches overlaps; a request that does not
 fit waits until enough in-flight work completes.  Each request's image is
@@ -176,6 +177,7 @@ class Server:
                         self.rays_done += r.rays
                     self.batches.append(len(batch))
                 for r, img in zip(batch, imgs):
+                    r.future.done_at = done
                     r.future.set_result(img)
             except Exception as e:   # noqa: BLE001 - forwarded to the callers
                 for r in batch:
@@ -229,8 +231,10 @@ class PlainServer:
                     ev = torch.cuda.Event()
                     ev.record(stream)
                 ev.synchronize()
-                self.latencies.append(time.perf_counter() - r.arrival)
+                done = time.perf_counter()
+                self.latencies.append(done - r.arrival)
                 self.rays_done += r.rays
+                r.future.done_at = done
                 r.future.set_result(img)
             except Exception as e:   # noqa: BLE001
                 r.future.set_exception(e)
@@ -242,22 +246,31 @@ class PlainServer:
         self._worker.join()
 
 
-def replay(server, requests, time_scale: float = 1.0) -> dict:
+def replay(server, requests, time_scale: float = 1.0, warmup_s: float = 0.0) -> dict:
     """Submits ``requests`` (objects with arrival_s, camera, scene_id) at
-    their arrival times, waits for all, and returns latency statistics."""
+    their arrival times, waits for all, and returns latency statistics of the
+    requests that arrive at or after ``warmup_s`` (arrival to completion) and
+    their throughput over the window from ``warmup_s`` to the last one's
+    completion."""
     t0 = time.perf_counter()
-    futs = []
+    futs, arrivals = [], []
     for req in requests:
         due = t0 + req.arrival_s * time_scale
         now = time.perf_counter()
         if due > now:
             time.sleep(due - now)
-        futs.append(server.submit(req.scene_id, req.camera, arrival=max(due, t0)))
+        arrival = max(due, t0)
+        futs.append(server.submit(req.scene_id, req.camera, arrival=arrival))
+        arrivals.append(arrival)
     for f in futs:
         f.result()
-    wall = time.perf_counter() - t0
-    lat = np.array(server.latencies[-len(futs):]) * 1e3
-    rays = sum(int(r.camera.width) * int(r.camera.height) for r in requests)
-    return {"requests": len(futs), "p50_ms": float(np.percentile(lat, 50)),
-            "p99_ms": float(np.percentile(lat, 99)), "frames_per_s": len(futs) / wall,
-            "mrays_per_s": rays / wall / 1e6, "wall_s": wall}
+    meas = [i for i, req in enumerate(requests) if req.arrival_s >= warmup_s]
+    if not meas:
+        raise ValueError("no request arrives after the warm-up")
+    lat = np.array([futs[i].done_at - arrivals[i] for i in meas]) * 1e3
+    start = t0 + warmup_s * time_scale
+    wall = max(futs[i].done_at for i in meas) - start
+    rays = sum(int(requests[i].camera.width) * int(requests[i].camera.height) for i in meas)
+    return {"requests": len(meas), "warmup_requests": len(requests) - len(meas),
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "frames_per_s": len(meas) / wall, "mrays_per_s": rays / wall / 1e6, "wall_s": wall}

@@ -41,7 +41,7 @@ def test_binding_struct_sizes_match_header_layout():
     from paper_2604_24994_amd import _lib as L
     assert ctypes.sizeof(L.PfCamera) == 4 * (3 + 12 + 6)
     assert ctypes.sizeof(L.PfParams) == 8 + 4 + 4 + 7 * 8 + 8
-    assert ctypes.sizeof(L.PfRenderOpts) == 24       # float, int32, int32, int64
+    assert ctypes.sizeof(L.PfRenderOpts) == 32       # float, int32, int32, int64, pointer
     assert ctypes.sizeof(L.PfAllocator) == 3 * 8
     assert ctypes.sizeof(L.PfSceneInfo) == 6 * 8 + 6 * 4
     assert ctypes.sizeof(L.PfSteinerOpts) == 8 + 4 * 4

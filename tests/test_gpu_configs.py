@@ -140,7 +140,10 @@ def test_high_degree_cells_match_lifted_hull_and_oracle(n_shell):
     extra, missing = gpu - ref, ref - gpu
     _flush(f"  edges gpu {len(gpu)} lifted hull {len(ref)}: extra {len(extra)} missing {len(missing)}")
     assert not extra
-    inside = [e for e in sorted(missing) if lp_face_exists(p64, w64, e[0], e[1], box=info["box_max"][0])]
+    # a face the GPU lacks must lie outside the domain box (the build clips
+    # every cell by it)
+    box = (np.asarray(info["box_min"]), np.asarray(info["box_max"]))
+    inside = [e for e in sorted(missing) if lp_face_exists(p64, w64, e[0], e[1], box=box)]
     assert not inside, inside[:3]
     scene.destroy()
     _check(pf, sc, cams, f"hub {n_shell}")

@@ -58,7 +58,8 @@ def test_single_cell_forward_and_backward():
     ref, _ = oracle.adjoint_gradients(sc, cam, G)
     for f in FIELDS:
         g = params[f].grad.cpu().numpy().astype(np.float64)
-        assert_grad_close(g, np.asarray(ref[f]).reshape(g.shape), f, log=_flush)
+        # a lone cell has no bisector: its weight has no influence
+        assert_grad_close(g, np.asarray(ref[f]).reshape(g.shape), f, log=_flush, may_vanish=(f == "power"))
 
 
 def test_coincident_sites():

@@ -79,7 +79,9 @@ def test_adjacency_is_regular_triangulation(pf, n, seed, wscale):
     assert len(extra) == 0, f"{len(extra)} GPU edges are not regular-triangulation edges"
     # an edge the GPU lacks must have no face inside the domain box (or be a
     # triangulation artefact of a degenerate hull facet)
-    inside = [e for e in sorted(missing) if lp_face_exists(p64, w64, e[0], e[1], box=scene.info()["box_max"][0])]
+    info = scene.info()
+    box = (np.asarray(info["box_min"]), np.asarray(info["box_max"]))
+    inside = [e for e in sorted(missing) if lp_face_exists(p64, w64, e[0], e[1], box=box)]
     assert len(inside) == 0, f"{len(inside)} faces inside the box are missing, e.g. {inside[:3]}"
     # symmetric
     directed = {(i, int(j)) for i in range(n) for j in col[row[i]:row[i + 1]] if j >= 0}
