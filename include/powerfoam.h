@@ -232,6 +232,28 @@ pf_status pf_render_trace(pf_scene* scene, const pf_camera* cams, int32_t ncam,
                           const pf_render_opts* opts, float* rgba,
                           int64_t* truncated, pf_fwd_state** state, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the plain
+   ray walk of pf_render_trace (no forward state) with its scratch memory (the
+   start-cell search and the truncation counter) in a fixed device array of
+   PF_NOALLOC_SCRATCH_BYTES bytes inside the library, one per device, held
+   until the process ends.  The call allocates nothing: no hipMalloc or
+   hipFree, no allocator callback, no library cache; the caller passes the
+   scene, the cameras and the image.  Every call on a device shares that
+   device's array, so calls that overlap on one device (several streams,
+   several threads) race and must be serialised by the caller; calls on one
+   stream are ordered.  The start-cell search needs at most 16 KiB whatever
+   the scene size, so no scene or camera count is beyond the array.
+   Arguments as for pf_render_trace with state = NULL; opts->state_mode must
+   be 0.  truncated (host, may be NULL) as for pf_render_trace: reading it
+   back synchronises the stream, so pass NULL under capture.  Leave
+   pf_profile_enable off: its event pairs are created per launch.
+   Errors: INVALID (as pf_render_trace, also state_mode != 0), HIP. */
+#define PF_NOALLOC_SCRATCH_BYTES 16896
+pf_status pf_render_trace_noalloc(pf_scene* scene, const pf_camera* cams, int32_t ncam,
+                                  const pf_render_opts* opts, float* rgba, int64_t* truncated,
+                                  void* stream);
+
 /* Options of pf_backward (host struct; all fields may be zero / NULL).
    The regularisers of the training objective (supplementary material, loss
    functions) that depend on the rendered rays:

@@ -5,12 +5,12 @@ include/powerfoam.h; this package is its Python binding.
 """
 from .api import (RECOMPUTE, STORE, ForwardState, Scene, append_empty_cells, backward, build_scene, camera_struct,
                   connect_loss, densify_prune, ema_update, memory_stats, query_workspace, set_allocator, steiner,
-                  render_raster, render_raster_state, render_trace, render_trace_state,
+                  render_raster, render_raster_state, render_trace, render_trace_noalloc, render_trace_state,
                   to_device_params,
                   update_scene, use_library_allocator, use_torch_allocator)
 from .autograd import render_raster_diff, render_trace_diff
 
 __all__ = ["RECOMPUTE", "STORE", "ForwardState", "Scene", "append_empty_cells", "backward", "build_scene", "camera_struct", "connect_loss", "densify_prune", "ema_update",
            "query_workspace", "render_raster", "render_raster_state", "render_raster_diff", "render_trace",
-           "render_trace_state", "render_trace_diff", "steiner", "to_device_params", "update_scene", "memory_stats",
+           "render_trace_state", "render_trace_diff", "render_trace_noalloc", "steiner", "to_device_params", "update_scene", "memory_stats",
            "set_allocator", "use_library_allocator", "use_torch_allocator"]

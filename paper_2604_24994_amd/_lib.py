@@ -14,7 +14,7 @@ EXPORTS = ("pf_build_scene", "pf_scene_info_get", "pf_scene_adjacency", "pf_scen
            "pf_render_raster", "pf_render_trace", "pf_backward", "pf_state_release", "pf_last_error",
            "pf_profile_enable", "pf_profile_read", "pf_state_info", "pf_update_scene", "pf_query_workspace",
            "pf_connect_loss", "pf_steiner", "pf_ema_update", "pf_densify_prune", "pf_set_allocator",
-           "pf_set_cache_limit", "pf_memory_stats")
+           "pf_set_cache_limit", "pf_memory_stats", "pf_render_trace_noalloc")
 
 
 class PfParams(C.Structure):
@@ -107,6 +107,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                      C.POINTER(vp), vp]
     lib.pf_render_trace.argtypes = [vp, C.POINTER(PfCamera), i32, C.POINTER(PfRenderOpts), vp,
                                     C.POINTER(i64), C.POINTER(vp), vp]
+    lib.pf_render_trace_noalloc.argtypes = [vp, C.POINTER(PfCamera), i32, C.POINTER(PfRenderOpts), vp,
+                                            C.POINTER(i64), vp]
     lib.pf_update_scene.argtypes = [vp, C.POINTER(PfParams), vp]
     lib.pf_query_workspace.argtypes = [vp, C.POINTER(PfCamera), i32, i32, C.POINTER(PfRenderOpts), vp,
                                        C.POINTER(i64)]

@@ -215,6 +215,26 @@ def render_trace(scene: Scene, cams, t_min: float = 1e-6, max_steps: int = 4096,
     return (imgs, int(trunc.value)) if return_truncated else imgs
 
 
+def render_trace_noalloc(scene: Scene, cams, out: torch.Tensor, t_min: float = 1e-6, max_steps: int = 4096,
+                         stream=None, return_truncated: bool = False):
+    """pf_render_trace_noalloc: the walk of ``render_trace`` with no device
+    allocation (scratch in the library's fixed per-device array).  ``out``
+    (caller-allocated float32 device tensor of 4 H W floats per camera,
+    images back to back) is required.  Calls that overlap on one device
+    race on the shared scratch."""
+    arr, nc, shapes = _cams(cams)
+    need = sum(4 * h * w for h, w in shapes)
+    if out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous() or out.numel() < need:
+        raise ValueError(f"out must be a contiguous float32 device tensor of at least {need} floats")
+    opts = _opts(t_min, max_steps)
+    trunc = C.c_int64(0)
+    L.check(L.load().pf_render_trace_noalloc(scene.handle, arr, nc, C.byref(opts), C.c_void_p(out.data_ptr()),
+                                             C.byref(trunc) if return_truncated else None,
+                                             C.c_void_p(_stream_ptr(stream))))
+    imgs = _split(out, shapes)
+    return (imgs, int(trunc.value)) if return_truncated else imgs
+
+
 class ForwardState:
     """pf_fwd_state handle of a forward (raster or walk, store or recompute
     mode)."""

@@ -649,6 +649,109 @@ pf_status pf_render_trace(pf_scene* scene, const pf_camera* cams, int32_t ncam, 
   return PF_OK;
 }
 
+namespace {
+
+// Scratch of pf_render_trace_noalloc: a device array in the library's code
+// object, one copy per device, shared by every call on that device (calls
+// that overlap on one device race on it).  Layout (bytes):
+//   [0, 8192)        start-cell search, least power distance per block
+//   [8192, 16384)    its cell per block
+//   [16384, 16388)   the start cell
+//   [16640, 16648)   rays cut by max_steps
+constexpr size_t NOALLOC_PK = 0;
+constexpr size_t NOALLOC_PI = NOALLOC_PK + sizeof(double) * pf::TRACE_START_BLOCKS;
+constexpr size_t NOALLOC_START = NOALLOC_PI + sizeof(long long) * pf::TRACE_START_BLOCKS;
+constexpr size_t NOALLOC_TRUNC = (NOALLOC_START + sizeof(int32_t) + 255) / 256 * 256;
+constexpr size_t NOALLOC_BYTES = NOALLOC_TRUNC + 256;
+static_assert(NOALLOC_BYTES == PF_NOALLOC_SCRATCH_BYTES, "scratch layout and the documented size differ");
+
+__device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};   // device address of scratch per device
+
+// Device address of the current device's scratch (looked up once per device).
+pf_status noalloc_scratch(unsigned char** out, const char* who) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    pf::set_error(std::string(who) + ": " + hipGetErrorString(e));
+    return PF_ERR_HIP;
+  }
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return invalid(std::string(who) + ": device index above 63");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      pf::set_error(std::string(who) + ": hipGetSymbolAddress of the scratch array failed: " +
+                    hipGetErrorString(e));
+      return PF_ERR_HIP;
+    }
+    g_noalloc_ptr[dev] = ptr;
+  }
+  *out = (unsigned char*)g_noalloc_ptr[dev];
+  return PF_OK;
+}
+
+__global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
+
+}  // namespace
+
+pf_status pf_render_trace_noalloc(pf_scene* scene, const pf_camera* cams, int32_t ncam,
+                                  const pf_render_opts* opts, float* rgba, int64_t* truncated, void* stream) {
+  const char* who = "pf_render_trace_noalloc";
+  pf_status st = check_render(scene, cams, ncam, rgba, who);
+  if (st != PF_OK) return st;
+  for (int c = 0; c < ncam; ++c) {
+    const float* m = cams[c].c2w;
+    const float o[3] = {m[3], m[7], m[11]};
+    for (int a = 0; a < 3; ++a)
+      if (!(o[a] >= scene->s.box_min[a] && o[a] <= scene->s.box_max[a]))
+        return invalid(std::string(who) + ": camera " + std::to_string(c) +
+                       " centre lies outside the domain box; rebuild the scene with a box containing it");
+  }
+  if (opts && opts->state_mode != 0) return invalid(std::string(who) + ": no forward state (state_mode must be 0)");
+  // the start-cell search takes one partial per block of 256 cells, at most
+  // TRACE_START_BLOCKS of them, so its scratch need never exceeds the array
+  const int64_t nb = std::min<int64_t>(pf::TRACE_START_BLOCKS, (scene->s.n + 255) / 256);
+  if ((size_t)nb * (sizeof(double) + sizeof(long long)) + sizeof(int32_t) > NOALLOC_TRUNC)
+    return invalid(std::string(who) + ": start-cell search larger than the scratch array");
+  const float t_min = (opts && opts->t_min > 0) ? opts->t_min : 1e-6f;
+  const int max_steps = (opts && opts->max_steps > 0) ? opts->max_steps : 4096;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned char* base = nullptr;
+  st = noalloc_scratch(&base, who);
+  if (st != PF_OK) return st;
+  pf::TraceScratch ts;
+  ts.pk = (double*)(base + NOALLOC_PK);
+  ts.pi = (long long*)(base + NOALLOC_PI);
+  ts.start = (int32_t*)(base + NOALLOC_START);
+  unsigned long long* trunc = (unsigned long long*)(base + NOALLOC_TRUNC);
+  // cleared by a kernel, not a memset node, so that the call can be captured
+  k_zero_u64<<<1, 1, 0, s>>>(trunc);
+  PF_HIP_TRY(hipGetLastError());
+  int64_t off = 0;
+  for (int c = 0; c < ncam; ++c) {
+    st = pf::trace_view(scene->s, cams[c], t_min, max_steps, rgba + 4 * off, trunc, s, nullptr, c, off, 0, -1, &ts,
+                        opts ? opts->counters : nullptr);
+    if (st != PF_OK) return st;
+    off += (int64_t)cams[c].width * cams[c].height;
+  }
+  if (truncated) {
+    unsigned long long h = 0;
+    hipError_t e = hipMemcpyAsync(&h, trunc, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      pf::set_error(std::string(who) + ": " + hipGetErrorString(e));
+      return PF_ERR_HIP;
+    }
+    *truncated = (int64_t)h;
+  }
+  return PF_OK;
+}
+
 pf_status pf_backward(pf_scene* scene, pf_fwd_state* state, const float* d_rgba, const pf_grads* grads,
                       const pf_backward_opts* opts, void* stream) {
   if (!scene || !state || !d_rgba || !grads) return invalid("pf_backward: NULL argument");

@@ -76,3 +76,5 @@ def test_binding_struct_sizes_match_header_layout():
     st = lib.pf_densify_prune(None, None, None, None, None, None, None, None, None, None, ctypes.byref(nk),
                               ctypes.byref(nd), None)
     assert st == L.PF_ERR_INVALID and b"pf_densify_prune" in lib.pf_last_error()
+    st = lib.pf_render_trace_noalloc(None, None, 0, None, None, None, None)
+    assert st == L.PF_ERR_INVALID and b"pf_render_trace_noalloc" in lib.pf_last_error()
