@@ -393,6 +393,8 @@ def main():
     ms = ev0.elapsed_time(ev1) / args.steps
     value = rays / (ms * 1e-3) / 1e6
     kms = {k: v[1] / args.steps for k, v in prof.items()}
+    from paper_2604_24994_amd.autograd import LAST_FORWARD
+    nrec = LAST_FORWARD["records"]   # contributions of the timed step's forward
     log(f"step {ms:.2f} ms, kernel ms/step: " + ", ".join(f"{k}={v:.2f}" for k, v in sorted(kms.items(), key=lambda kv: -kv[1])))
 
     extra = {}
@@ -461,8 +463,6 @@ def main():
     dom_name, dom_ms = max(kms.items(), key=lambda kv: kv[1]) if kms else ("none", 0.0)
     dom_launches = prof[dom_name][0] / args.steps if prof else 1
     avg_ms = dom_ms / max(1, dom_launches)
-    from paper_2604_24994_amd.autograd import LAST_FORWARD
-    nrec = LAST_FORWARD["records"]
     per = {"k_bwd_cell": FLOPS_BWD_PER_CONTRIB, "k_raster_store": FLOPS_FWD_PER_CONTRIB,
            "k_raster": FLOPS_FWD_PER_CONTRIB}.get(dom_name)
     achieved = per * nrec / max(1, dom_launches) / (avg_ms * 1e-3) / 1e12 if (per and nrec) else None

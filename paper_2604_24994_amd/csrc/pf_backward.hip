@@ -610,7 +610,10 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
       } else if (b == -2) {                // s = beta (ray start)
         g_beta += ge;
       } else if (b < nf) {                 // s = (h - q.m)/(d.m), neighbour face
-        const float ia = frcp(a);
+        // 1/(d.m) from the float64 direction: for a face the ray grazes, d.m
+        // cancels and the float32 product loses the digits that the
+        // derivatives (all proportional to 1/(d.m)) need
+        const float ia = (float)rcp_d(R.dx * (double)pl.x + R.dy * (double)pl.y + R.dz * (double)pl.z);
         gqx -= ge * pl.x * ia;
         gqy -= ge * pl.y * ia;
         gqz -= ge * pl.z * ia;

@@ -464,7 +464,7 @@ __global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ view
       P.alpha = 0.0f;
       float r = 0.0f, gg = 0.0f, b = 0.0f;
       if (hit) {
-        P = piece_geometry(R, L, g.w, S.plane + __builtin_amdgcn_readfirstlane(s_row[q]),
+        P = piece_geometry<true>(R, L, g.w, S.plane + __builtin_amdgcn_readfirstlane(s_row[q]),
                            __builtin_amdgcn_readfirstlane(s_nr[q]), s_nrm[q], tx, S.tau);
         if (P.alpha > 0.0f) radiance(tx, S.rgb + 3 * (int64_t)ci, P.ux, P.uy, R.fx, R.fy, R.fz, S.tau, r, gg, b);
       }
@@ -692,7 +692,7 @@ k_trace(ViewArgs v, int64_t tile_first, SceneDev S, const int32_t* __restrict__ 
       if (rho >= 0.0f && L.qq < (double)rho * (double)rho) {
         const float* tx = S.tex + (int64_t)cell * (KD * TEXW);
         const int r0 = S.row[cell];
-        P = piece_geometry(R, L, g.w, S.plane + r0, S.nrast[cell], S.nrm[cell], tx, S.tau);
+        P = piece_geometry<false>(R, L, g.w, S.plane + r0, S.nrast[cell], S.nrm[cell], tx, S.tau);
         if (P.alpha > 0.0f) {
           radiance(tx, S.rgb + 3 * (int64_t)cell, P.ux, P.uy, R.fx, R.fy, R.fz, S.tau, r, gg, b);
           contrib = true;

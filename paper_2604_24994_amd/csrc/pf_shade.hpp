@@ -174,6 +174,12 @@ struct Piece {
   float t1x, t1y, t1z, t2x, t2y, t2z;
 };
 
+// SKIP_EMPTY: test first whether the dense part is empty for every
+// displacement the sites allow (worth it where the texture is read through
+// the scalar cache, one cell per wave, as in the rasteriser; the walk's
+// per-lane loads cost more than the test saves).  Either way alpha is the
+// same.
+template <bool SKIP_EMPTY>
 __device__ inline Piece piece_geometry(const RayD& R, const Local& L, float r, const float4* __restrict__ faces,
                                        int nfaces, float4 nrm, const float* __restrict__ tx, float tau) {
   Piece P;
@@ -227,6 +233,24 @@ __device__ inline Piece piece_geometry(const RayD& R, const Local& L, float r, c
   float j0 = s0, j1 = s1;
   if (den != 0.0f) {
     const float idn = frcp(den);
+    // The displacement is a convex combination of the sites' d_k, so the
+    // displaced face lies between the faces moved by min d_k and max d_k.
+    // When even the face moved by max d_k leaves [s0, s1] on the empty side
+    // (beyond s1 going in, before s0 going out), the dense part is empty
+    // whatever the weights: alpha = 0 without evaluating them.  The test
+    // keeps a relative margin far above the rounding of the exact path, so
+    // it only fires where that path gives an empty dense part too.
+    if constexpr (SKIP_EMPTY) {
+      float dmax = tx[2], dabs = fabsf(tx[2]);
+#pragma unroll
+      for (int k = 1; k < KD; ++k) {
+        dmax = fmaxf(dmax, tx[k * TEXW + 2]);
+        dabs = fmaxf(dabs, fabsf(tx[k * TEXW + 2]));
+      }
+      const float bound = (dmax + 1e-5f * dabs - qn) * idn;
+      const float tol = 1e-4f * (fabsf(s0) + fabsf(s1) + fabsf(bound)) + 1e-30f;
+      if (den > 0.0f ? bound + tol <= s0 : bound - tol >= s1) return P;
+    }
     const float sbar = -qn * idn;
     float w[KD];
     sv_weights(tx, qt1 + sbar * dt1, qt2 + sbar * dt2, tau, w);
