@@ -49,15 +49,18 @@ FLOPS_BWD_PER_CONTRIB = 5100
 # (FETCH_SIZE reads 0.5 GiB: x2.0; WRITE_SIZE reads 1 GiB: x1.0).  Valid only
 # for the kernel sources with these hashes; otherwise the bench reports null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+_SRC_SHADE = {"pf_shade.hpp": "a6941abe41bd58ca", "pf_internal.hpp": "cf1b6d1fee18a09d",
+              "pf_record.hpp": "d8db4e8267ff8479"}
 TRAFFIC = {
-    "k_bwd_cell": {"fetch_kib": 8209004.9, "write_kib": 4483412.9,
-                   "sources": {"pf_backward.hip": "458b6967458821ba", "pf_shade.hpp": "a630fdb381c7dae7",
-                               "pf_internal.hpp": "95396ae9bc7369b2"}},
-    "k_raster_store": {"fetch_kib": 16565845.6, "write_kib": 11283653.3,
-                       "sources": {"pf_render.hip": "e2ac3b958af638c9", "pf_shade.hpp": "a630fdb381c7dae7",
-                                   "pf_internal.hpp": "95396ae9bc7369b2"}},
-    "k_clip": {"fetch_kib": 409618.1, "write_kib": 180464.1,
-               "sources": {"pf_build.hip": "60ddab952277c61e", "pf_internal.hpp": "95396ae9bc7369b2"}},
+    "k_bwd_cell": {"fetch_kib": 8093849.2, "write_kib": 3984548.9,
+                   "sources": {"pf_backward.hip": "e2adef89187752bc", **_SRC_SHADE}},
+    "k_raster_store": {"fetch_kib": 16542742.0, "write_kib": 11314482.6,
+                       "sources": {"pf_render.hip": "6e14c345d96e4a68", **_SRC_SHADE}},
+    "k_trace": {"fetch_kib": 8345572.3, "write_kib": 33312.5,
+                "sources": {"pf_render.hip": "6e14c345d96e4a68", **_SRC_SHADE}},
+    "k_clip": {"fetch_kib": 409414.4, "write_kib": 180395.2,
+               "sources": {"pf_build.hip": "60ddab952277c61e", "pf_internal.hpp": "cf1b6d1fee18a09d",
+                           "pf_record.hpp": "d8db4e8267ff8479"}},
 }
 
 
