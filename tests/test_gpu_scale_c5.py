@@ -1,9 +1,12 @@
 """The 4,194,304-cell workload: a training step (4 views 2048x1365, the
 forward replayed inside the backward instead of stored) runs while a server
 renders requests on four resident scenes of 0.5M, 1M, 2M and 4M cells.
-Checks: the training gradients equal those of the same step run alone, and
-every served image equals a render of that camera alone; raster and walk
-agree on sampled pixels of the training views.  Timings are printed."""
+Checks: the step's library memory stays a few GiB (no stored contribution
+records), its colours equal the FP64 oracle on sampled pixels, the training
+gradients equal those of the same step run alone, and every served image
+equals a render of that camera alone; raster and walk agree on sampled
+pixels of the training views.  Timings are printed."""
+import multiprocessing as mp
 import threading
 import time
 
@@ -11,6 +14,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -34,6 +38,16 @@ def _train_step(pf, params, sc, cams, tgt):
     return scene, imgs, grads
 
 
+def _oracle_pixels(args):
+    """FP64 oracle colours of sampled pixels of one training view (runs in
+    a worker process)."""
+    c, pix = args
+    torch.set_num_threads(4)
+    sc = W.c3_scene(n=4194304)
+    cam = W.c3_cameras(n_views=4, width=2048, height=1365)[c]
+    return c, oracle.render_walk(sc, cam, pix=pix)
+
+
 def test_c5_training_while_serving():
     import paper_2604_24994_amd as pf
     from paper_2604_24994_amd import serve
@@ -53,10 +67,23 @@ def test_c5_training_while_serving():
     _flush(f"  inputs ready in {time.time() - t0:.1f}s; "
            f"HBM in use {torch.cuda.memory_allocated() / 2**30:.1f} GiB (torch)")
 
-    # the step alone
+    # the step alone; the recompute-mode backward keeps no records between
+    # forward and backward and replays the forward in windows of at most
+    # 1 GiB of records, so the library's own memory stays a few GiB
     t1 = time.time()
+    pf.memory_stats(reset_peak=True)
     scene, imgs, g_alone = _train_step(pf, params, sc, cams, tgt)
-    _flush(f"  training step alone: {time.time() - t1:.2f}s")
+    peak = pf.memory_stats()["peak"]
+    _flush(f"  training step alone: {time.time() - t1:.2f}s; library memory peak {peak / 2**30:.2f} GiB")
+    assert peak < 6 * 2**30
+    # colours of the step's raster against the oracle on 2 seeded pixels per view
+    picks = [W.pixel_sample(cam, 2, seed=40 + c) for c, cam in enumerate(cams)]
+    with mp.get_context("spawn").Pool(4) as pool:
+        for c, ref in pool.imap_unordered(_oracle_pixels, [(c, p) for c, p in enumerate(picks)]):
+            got = imgs[c].detach().reshape(-1, 4)[torch.as_tensor(picks[c], device="cuda")].cpu().numpy()
+            err = float(np.abs(got.astype(np.float64) - ref).max())
+            _flush(f"  view {c}: colour err vs oracle {err:.2e} (A {ref[:, 3].round(3).tolist()})")
+            assert err <= 1e-4
     # raster and walk agree on sampled pixels of the views
     for c, (cam, img) in enumerate(zip(cams, imgs)):
         trc = pf.render_trace(scene, cam, max_steps=8192)[0]
