@@ -372,7 +372,8 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
   // (site, axis) owned by this lane in the transposed phase
   const int km = lane >> 3, mm = lane & 7;
   const float* tkm = txc + km * TEXW;
-  const float ax = tkm[3 + 3 * mm], ay = tkm[4 + 3 * mm], az = tkm[5 + 3 * mm];
+  // the lane's lobe axis, scaled by log2(e): its logits are base 2
+  const float ax = tkm[3 + 3 * mm] * LOG2E_F, ay = tkm[4 + 3 * mm] * LOG2E_F, az = tkm[5 + 3 * mm] * LOG2E_F;
   const float ccr = tkm[3 + 3 * MA + 3 * mm], ccg = tkm[4 + 3 * MA + 3 * mm], ccb = tkm[5 + 3 * MA + 3 * mm];
   float gax = 0.0f, gay = 0.0f, gaz = 0.0f, gcr_a = 0.0f, gcg_a = 0.0f, gcb_a = 0.0f;
 
@@ -491,31 +492,17 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     sv_weights(tx, (float)ux, (float)uy, tau, wr);
     double sum_wg = 0.0;
     float gwr[KD];
+    const float gx = fx * LOG2E_F, gy = fy * LOG2E_F, gz = fz * LOG2E_F;
 #pragma unroll
     for (int k = 0; k < KD; ++k) {
-      const float* t = tx + k * TEXW;
-      float lg[MA], mx = -INFINITY;
-#pragma unroll
-      for (int m = 0; m < MA; ++m) {
-        lg[m] = t[3 + 3 * m] * fx + t[4 + 3 * m] * fy + t[5 + 3 * m] * fz;
-        mx = fmaxf(mx, lg[m]);
-      }
-      float sum = 0.0f, sr = 0.0f, sg = 0.0f, sb = 0.0f;
-      const float mxl = mx * LOG2E_F;
-#pragma unroll
-      for (int m = 0; m < MA; ++m) {
-        const float e = exp_shifted(lg[m], mxl);
-        sum += e;
-        sr += e * t[3 + 3 * MA + 3 * m];
-        sg += e * t[4 + 3 * MA + 3 * m];
-        sb += e * t[5 + 3 * MA + 3 * m];
-      }
+      float sum, sr, sg, sb;
+      const float sh = sv_lobes(tx + k * TEXW, gx, gy, gz, sum, sr, sg, sb);
       const float inv = frcp(sum);
       gwr[k] = (gcr * sr + gcg * sg + gcb * sb) * inv;   // dL/dw_k = gC . sv_k
       sum_wg += (double)wr[k] * (double)gwr[k];
-      // w_k softmax_m(a_km.d) = exp(a_km.d - shift_k)
+      // w_k softmax_m(a_km.d) = 2^(a_km.d log2(e) - shift_k), shift_k = sh - log2(w_k / sum)
       const float wi = wr[k] * inv;
-      st_k[k][lane] = make_float2(wi > 0.0f ? mx - __logf(wi) : INFINITY, gwr[k]);
+      st_k[k][lane] = make_float2(wi > 0.0f ? sh - __log2f(wi) : INFINITY, gwr[k]);
     }
     double gux = 0.0, guy = 0.0;
     {
@@ -670,8 +657,7 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
       const float4 dd = st_dir[r];
       const float4 gc = st_gc[r];
       const float2 kk = st_k[km][r];
-      const float lg = ax * dd.x + ay * dd.y + az * dd.z;
-      const float vw = __expf(lg - kk.x);
+      const float vw = __builtin_amdgcn_exp2f(ax * dd.x + ay * dd.y + az * dd.z - kk.x);
       const float gcm = gc.x * ccr + gc.y * ccg + gc.z * ccb;
       const float gl = vw * (gcm - kk.y);
       gax += gl * dd.x;

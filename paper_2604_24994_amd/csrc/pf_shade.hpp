@@ -131,6 +131,36 @@ __device__ inline void onb(float nx, float ny, float nz, float& t1x, float& t1y,
   t2z = -ny;
 }
 
+// Softmax of up to 8 base-2 logits z into p (normalised in place by the
+// caller): p_k = 2^z_k, returned sum.  The logits are exponentiated
+// unshifted (2^z is exact in float range), and only when the sum leaves
+// [2^-100, 2^100] (a logit near the range's ends) are they shifted by their
+// largest, as a softmax usually is; *shift receives the shift (0 or that
+// largest logit).  Saves the max and the subtraction on every call.
+template <int N>
+__device__ inline float softmax2_sum(const float (&z)[N], float (&p)[N], float* shift) {
+  float sum = 0.0f;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    p[k] = __builtin_amdgcn_exp2f(z[k]);
+    sum += p[k];
+  }
+  float sh = 0.0f;
+  if (!(sum >= 0x1p-100f && sum <= 0x1p100f)) {
+    sh = z[0];
+#pragma unroll
+    for (int k = 1; k < N; ++k) sh = fmaxf(sh, z[k]);
+    sum = 0.0f;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      p[k] = __builtin_amdgcn_exp2f(z[k] - sh);
+      sum += p[k];
+    }
+  }
+  *shift = sh;
+  return sum;
+}
+
 // Soft-Voronoi weights over the K detail sites at face point u (Sec. 3.4,
 // Eq. svdisp / Eq. svrad).  The logits are shifted by tau*|u| and written as
 //   |u - s_k| - |u| = (|s_k|^2 - 2 u.s_k) / (|u - s_k| + |u|),
@@ -159,6 +189,25 @@ __device__ inline void sv_weights(const float* __restrict__ tx, float ux, float 
   const float inv = frcp(sum);
 #pragma unroll
   for (int k = 0; k < KD; ++k) w[k] *= inv;
+}
+
+// Sums of detail site t's M Spherical-Voronoi lobes for direction g = d log2(e):
+// *sum = sum_m 2^(a_m.g - shift), (sr, sg, sb) = sum_m 2^(a_m.g - shift) c_m;
+// returns the base-2 shift (softmax2_sum).
+__device__ inline float sv_lobes(const float* __restrict__ t, float gx, float gy, float gz, float& sum, float& sr,
+                                 float& sg, float& sb) {
+  float lg[MA], e[MA], sh;
+#pragma unroll
+  for (int m = 0; m < MA; ++m) lg[m] = t[3 + 3 * m] * gx + t[4 + 3 * m] * gy + t[5 + 3 * m] * gz;
+  sum = softmax2_sum(lg, e, &sh);
+  sr = sg = sb = 0.0f;
+#pragma unroll
+  for (int m = 0; m < MA; ++m) {
+    sr += e[m] * t[3 + 3 * MA + 3 * m];
+    sg += e[m] * t[4 + 3 * MA + 3 * m];
+    sb += e[m] * t[5 + 3 * MA + 3 * m];
+  }
+  return sh;
 }
 
 // Geometry of one (ray, cell) piece: bounded interval, dipole split and
