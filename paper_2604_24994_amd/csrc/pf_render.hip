@@ -376,17 +376,16 @@ __device__ inline void tile_pixel(int tiles_x, int& px, int& py, int tile = -1) 
 // COUNT: the work counters of the composite are added to counters[0..5]
 // (RASTER_COUNTERS): pixel-cell tests, sphere hits, contributions, and the
 // (wave, cell) steps that tested, that computed a piece, that shaded.
+// Seven waves per SIMD (at most 72 VGPRs) are asked for explicitly: the
+// compiler's own choice lands a few registers above, at six.
 template <bool STORE, bool COUNT>
-__global__ void __launch_bounds__(256) k_raster(const ViewDev* __restrict__ views, int nview, SceneDev S,
-                                                const unsigned long long* __restrict__ list,
-                                                const uint32_t* __restrict__ tile_off, float t_min,
-                                                float* __restrict__ rgba_all, int4* __restrict__ rec_ri,
-                                                float4* __restrict__ rec_rf, float* __restrict__ rec_rt,
-                                                int32_t* __restrict__ rec_head,
-                                                unsigned long long* __restrict__ rec_counter,
-                                                int4* __restrict__ rec_seg, int2* __restrict__ rec_wtail,
-                                                int64_t tile_first, int64_t wtail_base, int64_t rec_cap,
-                                                int64_t seg_cap, unsigned long long* __restrict__ counters) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7)))
+k_raster(const ViewDev* __restrict__ views, int nview, SceneDev S, const unsigned long long* __restrict__ list,
+         const uint32_t* __restrict__ tile_off, float t_min, float* __restrict__ rgba_all, int4* __restrict__ rec_ri,
+         float4* __restrict__ rec_rf, float* __restrict__ rec_rt, int32_t* __restrict__ rec_head,
+         unsigned long long* __restrict__ rec_counter, int4* __restrict__ rec_seg, int2* __restrict__ rec_wtail,
+         int64_t tile_first, int64_t wtail_base, int64_t rec_cap, int64_t seg_cap,
+         unsigned long long* __restrict__ counters) {
   // the tile's sorted cells are staged RB at a time: list entry and the cell
   // record fields every lane needs, loaded by the whole workgroup at once
   __shared__ int s_ci[RB];

@@ -223,12 +223,13 @@ struct Piece {
   float t1x, t1y, t1z, t2x, t2y, t2z;
 };
 
-// SKIP_EMPTY: test first whether the dense part is empty for every
-// displacement the sites allow (worth it where the texture is read through
-// the scalar cache, one cell per wave, as in the rasteriser; the walk's
-// per-lane loads cost more than the test saves).  Either way alpha is the
-// same.
-template <bool SKIP_EMPTY>
+// WAVE_CELL: every lane of the wave evaluates the same cell (the
+// rasteriser).  Its faces and texture are then read through the scalar
+// cache, the wave leaves the face loop as soon as no lane's interval is left,
+// and, before the displacement weights, it tests whether the dense part is
+// empty for every displacement the sites allow (for the walk's per-lane loads
+// that test costs more than it saves).  Either way alpha is the same.
+template <bool WAVE_CELL>
 __device__ inline Piece piece_geometry(const RayD& R, const Local& L, float r, const float4* __restrict__ faces,
                                        int nfaces, float4 nrm, const float* __restrict__ tx, float tau) {
   Piece P;
@@ -245,12 +246,8 @@ __device__ inline Piece piece_geometry(const RayD& R, const Local& L, float r, c
   const float fx = R.fx, fy = R.fy, fz = R.fz;
   // exit (a > 0) and entry (a < 0) bounds by selects rather than branches;
   // a face parallel to the ray (a = 0) empties the interval when the ray
-  // lies on its outer side
-  // (the next face is loaded while this one is tested)
-  float4 nxt = nfaces > 0 ? faces[0] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  for (int f = 0; f < nfaces; ++f) {
-    const float4 pl = nxt;
-    if (f + 1 < nfaces) nxt = faces[f + 1];
+  // lies on its outer side.  Once empty, an interval stays empty.
+  auto clip = [&](const float4 pl, int f) {
     const float a = fx * pl.x + fy * pl.y + fz * pl.z;
     const float bb = pl.w - (L.qx * pl.x + L.qy * pl.y + L.qz * pl.z);
     const float s = bb * frcp(a);
@@ -261,6 +258,26 @@ __device__ inline Piece piece_geometry(const RayD& R, const Local& L, float r, c
     s0 = in ? s : s0;
     b0 = in ? f : b0;
     s1 = (a == 0.0f && bb < 0.0f) ? -INFINITY : s1;
+  };
+  if constexpr (WAVE_CELL) {
+    // two faces per step from one wave-uniform (scalar) address
+    int f = 0;
+    for (; f + 2 <= nfaces; f += 2) {
+      const float4* fp = faces + __builtin_amdgcn_readfirstlane(f);
+      const float4 p0 = fp[0], p1 = fp[1];
+      clip(p0, f);
+      clip(p1, f + 1);
+      if (!__any(s0 < s1)) break;
+    }
+    if (f + 1 == nfaces) clip(faces[__builtin_amdgcn_readfirstlane(f)], f);
+  } else {
+    // (the next face is loaded while this one is tested)
+    float4 nxt = nfaces > 0 ? faces[0] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int f = 0; f < nfaces; ++f) {
+      const float4 pl = nxt;
+      if (f + 1 < nfaces) nxt = faces[f + 1];
+      clip(pl, f);
+    }
   }
   if (L.beta > s0) { s0 = L.beta; b0 = -2; }
   P.s0 = s0;
@@ -289,7 +306,7 @@ __device__ inline Piece piece_geometry(const RayD& R, const Local& L, float r, c
     // whatever the weights: alpha = 0 without evaluating them.  The test
     // keeps a relative margin far above the rounding of the exact path, so
     // it only fires where that path gives an empty dense part too.
-    if constexpr (SKIP_EMPTY) {
+    if constexpr (WAVE_CELL) {
       float dmax = tx[2], dabs = fabsf(tx[2]);
 #pragma unroll
       for (int k = 1; k < KD; ++k) {
@@ -331,38 +348,65 @@ __device__ inline Piece piece_geometry(const RayD& R, const Local& L, float r, c
 }
 
 // Radiance at texture point u for direction d: base colour plus the
-// soft-Voronoi blend of the detail sites' Spherical-Voronoi colours.
+// soft-Voronoi blend of the detail sites' Spherical-Voronoi colours.  The
+// lobes are exponentiated in base 2 without the max shift; if any site's sum
+// leaves [2^-100, 2^100], the colour is evaluated again with each site's
+// logits shifted by their largest (as in softmax2_sum).  That rare pass runs
+// over the sites in a loop that is not unrolled, so that its texture reads
+// are its own and the common pass holds no texture values for it.
 __device__ inline void radiance(const float* __restrict__ tx, const float* __restrict__ rgb, float ux, float uy,
                                 float fx, float fy, float fz, float tau, float& cr, float& cg, float& cb) {
   float w[KD];
   sv_weights(tx, ux, uy, tau, w);
+  const float gx = fx * LOG2E_F, gy = fy * LOG2E_F, gz = fz * LOG2E_F;
   cr = rgb[0];
   cg = rgb[1];
   cb = rgb[2];
+  bool in_range = true;
 #pragma unroll
   for (int k = 0; k < KD; ++k) {
     const float* t = tx + k * TEXW;
-    float lg[MA];
-    float mx = -INFINITY;
-#pragma unroll
-    for (int m = 0; m < MA; ++m) {
-      lg[m] = t[3 + 3 * m] * fx + t[4 + 3 * m] * fy + t[5 + 3 * m] * fz;
-      mx = fmaxf(mx, lg[m]);
-    }
     float sum = 0.0f, sr = 0.0f, sg = 0.0f, sb = 0.0f;
-    const float mxl = mx * LOG2E_F;
 #pragma unroll
     for (int m = 0; m < MA; ++m) {
-      const float e = exp_shifted(lg[m], mxl);
+      const float e = __builtin_amdgcn_exp2f(t[3 + 3 * m] * gx + t[4 + 3 * m] * gy + t[5 + 3 * m] * gz);
       sum += e;
       sr += e * t[3 + 3 * MA + 3 * m];
       sg += e * t[4 + 3 * MA + 3 * m];
       sb += e * t[5 + 3 * MA + 3 * m];
     }
+    in_range = in_range && sum >= 0x1p-100f && sum <= 0x1p100f;
     const float sc = w[k] * frcp(sum);
     cr += sc * sr;
     cg += sc * sg;
     cb += sc * sb;
+  }
+  if (!in_range) {
+    cr = rgb[0];
+    cg = rgb[1];
+    cb = rgb[2];
+#pragma unroll 1
+    for (int k = 0; k < KD; ++k) {
+      float wk = w[0];
+#pragma unroll
+      for (int j = 1; j < KD; ++j) wk = (k == j) ? w[j] : wk;
+      const float* t = tx + k * TEXW;
+      float mx = -INFINITY;
+      for (int m = 0; m < MA; ++m) mx = fmaxf(mx, t[3 + 3 * m] * gx + t[4 + 3 * m] * gy + t[5 + 3 * m] * gz);
+      float sum = 0.0f, sr = 0.0f, sg = 0.0f, sb = 0.0f;
+      for (int m = 0; m < MA; ++m) {
+        const float e =
+            __builtin_amdgcn_exp2f(t[3 + 3 * m] * gx + t[4 + 3 * m] * gy + t[5 + 3 * m] * gz - mx);
+        sum += e;
+        sr += e * t[3 + 3 * MA + 3 * m];
+        sg += e * t[4 + 3 * MA + 3 * m];
+        sb += e * t[5 + 3 * MA + 3 * m];
+      }
+      const float sc = wk * frcp(sum);
+      cr += sc * sr;
+      cg += sc * sg;
+      cb += sc * sb;
+    }
   }
 }
 
