@@ -20,7 +20,8 @@
 //                 dipole split with displacement, radiance) and applies the
 //                 chain rule by hand, in reverse order of the forward; the
 //                 per-record sums (cell parameters, detail-site positions and
-//                 displacements) are reduced over the wave with DPP.  Lane =
+//                 displacements) are reduced over the wave two at a time
+//                 (a permlane32 swap, then DPP).  Lane =
 //                 (detail site k, axis m): the 6 Spherical-Voronoi gradients
 //                 of (k, m) accumulate in registers over the chunk, reading
 //                 each record's direction, dL/dc and per-site softmax terms
@@ -253,6 +254,25 @@ __device__ inline void sum_to(float* acc, int i, bool valid, float v) {
 }
 
 
+// Two wave sums at once: acc[i0], acc[i1] += sum over the wave of
+// (valid ? v : 0).  A permlane32 swap leaves partial sums of v0 in the lower
+// half and of v1 in the upper half; the DPP row sums and the row-15
+// broadcasts finish them in lanes 31 and 63.
+__device__ inline void sum2_to(float* acc, int i0, int i1, bool valid, float v0, float v1) {
+  v0 = valid ? v0 : 0.0f;
+  v1 = valid ? v1 : 0.0f;
+  const auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(v0), __float_as_uint(v1), false, false);
+  float t = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+  t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0xB1, 0xf, 0xf, false));  // quad [1,0,3,2]
+  t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x4E, 0xf, 0xf, false));  // quad [2,3,0,1]
+  t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x141, 0xf, 0xf, false)); // row half mirror
+  t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x140, 0xf, 0xf, false)); // row mirror
+  t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x142, 0xa, 0xf, false)); // row bcast 15
+  const int lane = threadIdx.x & 63;
+  if (lane == 31) acc[i0] += t;
+  if (lane == 63) acc[i1] += t;
+}
+
 __device__ inline float softplus_b(float x) { return x > 20.0f ? x : log1pf(expf(x)); }
 
 // A wave-uniform double moved to scalar registers.
@@ -315,8 +335,7 @@ __device__ inline void sv_backward(const float* __restrict__ tx, double ux, doub
     }
     gux += ge[k] * lx;
     guy += ge[k] * ly;
-    sum_to(acc, NCELL + 3 * k, valid, (float)(-ge[k] * ex * rd));
-    sum_to(acc, NCELL + 3 * k + 1, valid, (float)(-ge[k] * ey * rd));
+    sum2_to(acc, NCELL + 3 * k, NCELL + 3 * k + 1, valid, (float)(-ge[k] * ex * rd), (float)(-ge[k] * ey * rd));
   }
 }
 
@@ -525,9 +544,13 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
       g_den -= g_sx * sxx * idn;
       double sum_w = 0.0;
       double gw[KD];
+      static_assert(KD % 2 == 0 && NCELL % 2 == 0, "wave sums go two at a time");
+#pragma unroll
+      for (int k = 0; k < KD; k += 2)
+        sum2_to(acc, NCELL + 3 * k + 2, NCELL + 3 * k + 5, valid, (float)(g_delta * (double)wd[k]),
+                (float)(g_delta * (double)wd[k + 1]));
 #pragma unroll
       for (int k = 0; k < KD; ++k) {
-        sum_to(acc, NCELL + 3 * k + 2, valid, (float)(g_delta * (double)wd[k]));
         gw[k] = g_delta * (double)tx[k * TEXW + 2];
         sum_w += (double)wd[k] * gw[k];
       }
@@ -645,7 +668,7 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     {
       const float cellv[NCELL] = {gpx, gpy, gpz, g_wi, g_r, gnx, gny, gnz, g_lam, gcr, gcg, gcb};
 #pragma unroll
-      for (int i = 0; i < NCELL; ++i) sum_to(acc, i, valid, cellv[i]);
+      for (int i = 0; i < NCELL; i += 2) sum2_to(acc, i, i + 1, valid, cellv[i], cellv[i + 1]);
       if (contribution) sum_to(acc, ISTAT, valid, ta);
     }
 
@@ -657,9 +680,9 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
       const float4 dd = st_dir[r];
       const float4 gc = st_gc[r];
       const float2 kk = st_k[km][r];
-      const float vw = __builtin_amdgcn_exp2f(ax * dd.x + ay * dd.y + az * dd.z - kk.x);
-      const float gcm = gc.x * ccr + gc.y * ccg + gc.z * ccb;
-      const float gl = vw * (gcm - kk.y);
+      // (the shift and dL/dw_k enter as the addends of the fused chains)
+      const float vw = __builtin_amdgcn_exp2f(fmaf(az, dd.z, fmaf(ay, dd.y, fmaf(ax, dd.x, -kk.x))));
+      const float gl = vw * fmaf(gc.z, ccb, fmaf(gc.y, ccg, fmaf(gc.x, ccr, -kk.y)));
       gax += gl * dd.x;
       gay += gl * dd.y;
       gaz += gl * dd.z;
