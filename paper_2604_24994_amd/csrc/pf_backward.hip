@@ -442,8 +442,8 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     const float a1 = fx * pl1.x + fy * pl1.y + fz * pl1.z;
     const float s0 = (b0 == -1) ? -sq
                      : (b0 == -2) ? L.beta
-                                  : (pl0.w - (L.qx * pl0.x + L.qy * pl0.y + L.qz * pl0.z)) * frcp(a0);
-    const float s1 = (b1 == -1) ? sq : (pl1.w - (L.qx * pl1.x + L.qy * pl1.y + L.qz * pl1.z)) * frcp(a1);
+                                  : face_offset(pl0, -L.qx, -L.qy, -L.qz) * frcp(a0);
+    const float s1 = (b1 == -1) ? sq : face_offset(pl1, -L.qx, -L.qy, -L.qz) * frcp(a1);
     const double ddx = R.dx, ddy = R.dy, ddz = R.dz;
     const double qdx = L.dqx, qdy = L.dqy, qdz = L.dqz;
     // (an opaque offset, so that the frame is read here, not hoisted)

@@ -754,7 +754,7 @@ k_trace(ViewArgs v, int64_t tile_first, SceneDev S, const int32_t* __restrict__ 
         const float4 pl = S.plane[f];
         const float a = R.fx * pl.x + R.fy * pl.y + R.fz * pl.z;
         if (!(a > 0.0f)) continue;
-        const float s = (pl.w - (L.qx * pl.x + L.qy * pl.y + L.qz * pl.z)) * frcp(a);
+        const float s = face_offset(pl, -L.qx, -L.qy, -L.qz) * frcp(a);
         if (s < best_any) { best_any = s; bf_any = f; }
         if (s >= s_cur - 1e-6f * (1.0f + fabsf(s_cur)) && s < best) { best = s; bf = f; }
       }

@@ -117,6 +117,12 @@ __device__ inline Local make_local(const RayD& R, float px, float py, float pz) 
   return L;
 }
 
+// h - q.m of face plane (m, h) = pl as one fused chain from h, given -q: the
+// ray x = p_i + q + s d meets the plane at s = (h - q.m) / (d.m).
+__device__ inline float face_offset(const float4 pl, float nqx, float nqy, float nqz) {
+  return fmaf(nqz, pl.z, fmaf(nqy, pl.y, fmaf(nqx, pl.x, pl.w)));
+}
+
 // Duff et al., "Building an Orthonormal Basis, Revisited" (JCGT 2017).
 __device__ inline void onb(float nx, float ny, float nz, float& t1x, float& t1y, float& t1z, float& t2x,
                            float& t2y, float& t2z) {
@@ -244,30 +250,34 @@ __device__ inline Piece piece_geometry(const RayD& R, const Local& L, float r, c
   float s0 = -sq, s1 = sq;
   int b0 = -1, b1 = -1;
   const float fx = R.fx, fy = R.fy, fz = R.fz;
-  // exit (a > 0) and entry (a < 0) bounds by selects rather than branches;
-  // a face parallel to the ray (a = 0) empties the interval when the ray
-  // lies on its outer side.  Once empty, an interval stays empty.
+  // exit (a >= 0) and entry (a < 0) bounds by selects rather than branches.
+  // a = d.m + 0 is never -0, so a face parallel to the ray (a = +0) gives
+  // s = bb * (1/+0): -inf when the ray lies on its outer side (bb < 0),
+  // which empties the interval, +inf (or NaN for bb = 0) otherwise, which
+  // leaves it.  Once empty, an interval stays empty.
+  const float nqx = -L.qx, nqy = -L.qy, nqz = -L.qz;
   auto clip = [&](const float4 pl, int f) {
-    const float a = fx * pl.x + fy * pl.y + fz * pl.z;
-    const float bb = pl.w - (L.qx * pl.x + L.qy * pl.y + L.qz * pl.z);
-    const float s = bb * frcp(a);
-    const bool out = a > 0.0f && s < s1;
-    const bool in = a < 0.0f && s > s0;
+    const float a = (fx * pl.x + fy * pl.y + fz * pl.z) + 0.0f;
+    const float s = face_offset(pl, nqx, nqy, nqz) * frcp(a);
+    const bool exits = a >= 0.0f;
+    const bool out = exits && s < s1;
+    const bool in = !exits && s > s0;
     s1 = out ? s : s1;
     b1 = out ? f : b1;
     s0 = in ? s : s0;
     b0 = in ? f : b0;
-    s1 = (a == 0.0f && bb < 0.0f) ? -INFINITY : s1;
   };
   if constexpr (WAVE_CELL) {
     // two faces per step from one wave-uniform (scalar) address
     int f = 0;
-    for (; f + 2 <= nfaces; f += 2) {
+    bool more = nfaces >= 2;
+    while (more) {
       const float4* fp = faces + __builtin_amdgcn_readfirstlane(f);
       const float4 p0 = fp[0], p1 = fp[1];
       clip(p0, f);
       clip(p1, f + 1);
-      if (!__any(s0 < s1)) break;
+      f += 2;
+      more = f + 2 <= nfaces && __any(s0 < s1);
     }
     if (f + 1 == nfaces) clip(faces[__builtin_amdgcn_readfirstlane(f)], f);
   } else {
