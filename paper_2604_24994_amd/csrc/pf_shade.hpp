@@ -271,12 +271,22 @@ __device__ inline Piece piece_geometry(const RayD& R, const Local& L, float r, c
     // two faces per step from one wave-uniform (scalar) address
     int f = 0;
     bool more = nfaces >= 2;
+    float4 c0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), c1 = c0;
+    if (more) {
+      c0 = faces[0];
+      c1 = faces[1];
+    }
     while (more) {
-      const float4* fp = faces + __builtin_amdgcn_readfirstlane(f);
-      const float4 p0 = fp[0], p1 = fp[1];
+      const float4 p0 = c0, p1 = c1;
+      const int fn = f + 2;
+      if (fn + 2 <= nfaces) {   // the next pair is loaded while this one is tested
+        const float4* fp = faces + __builtin_amdgcn_readfirstlane(fn);
+        c0 = fp[0];
+        c1 = fp[1];
+      }
       clip(p0, f);
       clip(p1, f + 1);
-      f += 2;
+      f = fn;
       more = f + 2 <= nfaces && __any(s0 < s1);
     }
     if (f + 1 == nfaces) clip(faces[__builtin_amdgcn_readfirstlane(f)], f);
