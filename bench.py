@@ -422,7 +422,7 @@ def main():
         extra["recompute"] = {"ms_per_step": round(rms, 3), "mrays_s": round(rays / (rms * 1e-3) / 1e6, 3),
                               "steps": args.recompute_steps,
                               "library_peak_bytes": mem["recompute"], "store_library_peak_bytes": mem["store"],
-                              "window_bytes": 1 << 30}
+                              "window_bytes": 2 << 30}
         log(f"recompute: {extra['recompute']}")
 
     # side measurements on one built scene (not part of the timed step)

@@ -120,7 +120,7 @@ typedef struct {
                                 whose records exceed it keeps only the cameras
                                 (the state becomes a recompute-mode state).
                                 Recompute mode: the backward's replay window
-                                (0: 1 GiB).                                   */
+                                (0: 2 GiB).                                   */
   unsigned long long* counters; /* device, may be NULL: work counters of the
                                 call's kernels, accumulated (+=) over every
                                 composite / walk launch of the call (a store
@@ -286,7 +286,7 @@ typedef struct {
    store-mode state is consumed (its records are overwritten): a second
    pf_backward on it fails with INVALID.  A recompute-mode state replays its
    forward in windows of consecutive 16x16 tiles: each window's records are
-   written into one pool of at most the state's workspace_limit bytes (1 GiB
+   written into one pool of at most the state's workspace_limit bytes (2 GiB
    without a limit), differentiated, and dropped before the next window is
    replayed, so the memory does not grow with the number of contributions
    (a window whose records do not fit is halved and replayed).  It

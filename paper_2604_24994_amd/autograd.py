@@ -80,7 +80,7 @@ def render_raster_diff(scene: Scene, cams, t_min: float = 1e-6, state_mode: int 
     flows into ``scene.params`` (build the scene from leaf tensors with
     requires_grad=True).  state_mode RECOMPUTE keeps no records between the
     forward and the backward, which replays the forward in windows of at most
-    ``workspace_limit`` bytes of records (0: 1 GiB); in STORE mode a forward
+    ``workspace_limit`` bytes of records (0: 2 GiB); in STORE mode a forward
     whose records exceed a non-zero ``workspace_limit`` falls back to that.
     ``lambda_normal`` adds the normal loss of the rendered rays to the
     objective (its gradient joins the backward); a

@@ -465,7 +465,7 @@ k_raster(const ViewDev* __restrict__ views, int nview, SceneDev S, const unsigne
       if (hit) {
         P = piece_geometry<true>(R, L, g.w, S.plane + __builtin_amdgcn_readfirstlane(s_row[q]),
                            __builtin_amdgcn_readfirstlane(s_nr[q]), s_nrm[q], tx, S.tau);
-        if (P.alpha > 0.0f) radiance(tx, S.rgb + 3 * (int64_t)ci, P.ux, P.uy, R.fx, R.fy, R.fz, S.tau, r, gg, b);
+        if (P.alpha > 0.0f) radiance<true>(tx, S.rgb + 3 * (int64_t)ci, P.ux, P.uy, R.fx, R.fy, R.fz, S.tau, r, gg, b);
       }
       const bool contrib = hit && P.alpha > 0.0f;
       if constexpr (COUNT) {
@@ -693,7 +693,7 @@ k_trace(ViewArgs v, int64_t tile_first, SceneDev S, const int32_t* __restrict__ 
         const int r0 = S.row[cell];
         P = piece_geometry<false>(R, L, g.w, S.plane + r0, S.nrast[cell], S.nrm[cell], tx, S.tau);
         if (P.alpha > 0.0f) {
-          radiance(tx, S.rgb + 3 * (int64_t)cell, P.ux, P.uy, R.fx, R.fy, R.fz, S.tau, r, gg, b);
+          radiance<false>(tx, S.rgb + 3 * (int64_t)cell, P.ux, P.uy, R.fx, R.fy, R.fz, S.tau, r, gg, b);
           contrib = true;
         }
         if constexpr (COUNT) {

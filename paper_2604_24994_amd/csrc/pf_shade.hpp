@@ -1,6 +1,9 @@
 // Per-(ray, cell) device math shared by the rasteriser, the ray walk and the
-// backward pass, so that the two renderers evaluate every contribution with
-// the same instructions.
+// backward pass, so that the two renderers evaluate every contribution's
+// geometry with the same instructions (the radiance's lobe softmaxes are
+// taken without the max shift in the rasteriser and with it in the walk,
+// which holds the texture per lane in fewer registers; the two agree up to
+// rounding).
 //
 // Numerics: the ray is generated in float64 and, per cell, re-expressed in
 // the cell's local frame in float64: q = closest-approach offset from p_i,
@@ -368,12 +371,15 @@ __device__ inline Piece piece_geometry(const RayD& R, const Local& L, float r, c
 }
 
 // Radiance at texture point u for direction d: base colour plus the
-// soft-Voronoi blend of the detail sites' Spherical-Voronoi colours.  The
-// lobes are exponentiated in base 2 without the max shift; if any site's sum
-// leaves [2^-100, 2^100], the colour is evaluated again with each site's
-// logits shifted by their largest (as in softmax2_sum).  That rare pass runs
-// over the sites in a loop that is not unrolled, so that its texture reads
-// are its own and the common pass holds no texture values for it.
+// soft-Voronoi blend of the detail sites' Spherical-Voronoi colours.
+// WAVE_CELL = true (the rasteriser, one cell per wave, texture in scalar
+// registers): the lobes are exponentiated in base 2 without the max shift;
+// if any site's sum leaves [2^-100, 2^100], the colour is evaluated again
+// with each site's logits shifted by their largest (as in softmax2_sum).
+// That rare pass runs over the sites in a loop that is not unrolled, so that
+// its texture reads are its own and the common pass holds no texture values
+// for it.
+template <bool WAVE_CELL>
 __device__ inline void radiance(const float* __restrict__ tx, const float* __restrict__ rgb, float ux, float uy,
                                 float fx, float fy, float fz, float tau, float& cr, float& cg, float& cb) {
   float w[KD];
@@ -427,6 +433,46 @@ __device__ inline void radiance(const float* __restrict__ tx, const float* __res
       cg += sc * sg;
       cb += sc * sb;
     }
+  }
+}
+
+
+// WAVE_CELL = false (the walk: a cell per lane, the texture read per lane):
+// every softmax shifted by its largest logit, which keeps fewer values live
+// than the unshifted form with its rare shifted pass (the walk is held to 80
+// VGPRs).
+template <>
+__device__ inline void radiance<false>(const float* __restrict__ tx, const float* __restrict__ rgb, float ux, float uy,
+                                       float fx, float fy, float fz, float tau, float& cr, float& cg, float& cb) {
+  float w[KD];
+  sv_weights(tx, ux, uy, tau, w);
+  cr = rgb[0];
+  cg = rgb[1];
+  cb = rgb[2];
+#pragma unroll
+  for (int k = 0; k < KD; ++k) {
+    const float* t = tx + k * TEXW;
+    float lg[MA];
+    float mx = -INFINITY;
+#pragma unroll
+    for (int m = 0; m < MA; ++m) {
+      lg[m] = t[3 + 3 * m] * fx + t[4 + 3 * m] * fy + t[5 + 3 * m] * fz;
+      mx = fmaxf(mx, lg[m]);
+    }
+    float sum = 0.0f, sr = 0.0f, sg = 0.0f, sb = 0.0f;
+    const float mxl = mx * LOG2E_F;
+#pragma unroll
+    for (int m = 0; m < MA; ++m) {
+      const float e = exp_shifted(lg[m], mxl);
+      sum += e;
+      sr += e * t[3 + 3 * MA + 3 * m];
+      sg += e * t[4 + 3 * MA + 3 * m];
+      sb += e * t[5 + 3 * MA + 3 * m];
+    }
+    const float sc = w[k] * frcp(sum);
+    cr += sc * sr;
+    cg += sc * sg;
+    cb += sc * sb;
   }
 }
 

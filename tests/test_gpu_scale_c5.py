@@ -69,7 +69,7 @@ def test_c5_training_while_serving():
 
     # the step alone; the recompute-mode backward keeps no records between
     # forward and backward and replays the forward in windows of at most
-    # 1 GiB of records, so the library's own memory stays a few GiB
+    # 2 GiB of records, so the library's own memory stays a few GiB
     t1 = time.time()
     pf.memory_stats(reset_peak=True)
     scene, imgs, g_alone = _train_step(pf, params, sc, cams, tgt)
