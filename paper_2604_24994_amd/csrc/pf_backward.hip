@@ -339,7 +339,10 @@ __device__ inline void sv_backward(const float* __restrict__ tx, double ux, doub
   }
 }
 
-__global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3))) k_bwd_cell(
+// Two waves per SIMD: at most 256 VGPRs, which the per-record float64
+// chain fills without spilling (at three waves, 168 VGPRs, it spilled and ran
+// 5% slower).
+__global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) k_bwd_cell(
     const pf_camera* __restrict__ cams, const int4* __restrict__ ri, const float4* __restrict__ rf,
     const int32_t* __restrict__ order, const int4* __restrict__ chunks, const float* __restrict__ prm_p,
     const float* __restrict__ radius, const float* __restrict__ normal, const float* __restrict__ lamv,
@@ -352,6 +355,12 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
   __shared__ float acc[NSUM + 1];
   __shared__ float4 facc[FMAX_B];
   __shared__ double s_fr[12];            // the cell's face frame (wave-uniform)
+  // zeros, read back as a per-batch offset that the compiler cannot see
+  // through: values derived from it are recomputed in every batch instead of
+  // being hoisted out of the record loop and held (an LDS load, unlike an
+  // empty asm statement, is no memory write, so the texture reads stay
+  // scalar loads)
+  __shared__ int s_zero[64];
 
   const int4 ch = chunks[blockIdx.x];
   const int ci = ch.x;
@@ -361,6 +370,7 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
   const int nfl = min(nf, FMAX_B);
   const float* __restrict__ txc = tex + (int64_t)ci * KD * TEXW;
   for (int t = lane; t < NSUM + 1; t += BWD_THREADS) acc[t] = 0.0f;
+  s_zero[lane] = 0;
   for (int t = lane; t < nfl; t += BWD_THREADS) facc[t] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 
   // cell constants, computed exactly as the build's per-cell record
@@ -397,10 +407,10 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
   float gax = 0.0f, gay = 0.0f, gaz = 0.0f, gcr_a = 0.0f, gcg_a = 0.0f, gcb_a = 0.0f;
 
   for (int base = ch.y; base < ch.z; base += 64) {
-    // the texture is re-read per record batch (scalar loads) rather than
-    // held in registers across the loop
-    const float* __restrict__ tx = txc;
-    asm volatile("" : "+s"(tx));
+    // the texture is re-read per record batch (scalar loads, offset by the
+    // opaque zero) rather than held in registers across the loop
+    const int zo = s_zero[(base >> 6) & 63];   // 0
+    const float* __restrict__ tx = txc + __builtin_amdgcn_readfirstlane(zo);
     const int idx = base + lane;
     const bool valid = idx < ch.z;
     const int nvalid = min(64, ch.z - base);
@@ -431,8 +441,8 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     // the cell's site and radius pass an opaque copy, so that their float64
     // conversions are made here rather than hoisted out of the loop (and
     // spilled)
-    float cpx = px, cpy = py, cpz = pz, crad = rad;
-    asm volatile("" : "+s"(cpx), "+s"(cpy), "+s"(cpz), "+s"(crad));
+    const float fz0 = __int_as_float(zo);   // +0
+    const float cpx = px + fz0, cpy = py + fz0, cpz = pz + fz0, crad = rad + fz0;
     const Local L = make_local(R, cpx, cpy, cpz);
     const double Dd = (double)crad * (double)crad - L.qq;
     const float sq = fsqrt((float)fmax(Dd, 1e-30));
@@ -447,8 +457,7 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     const double ddx = R.dx, ddy = R.dy, ddz = R.dz;
     const double qdx = L.dqx, qdy = L.dqy, qdz = L.dqz;
     // (an opaque offset, so that the frame is read here, not hoisted)
-    int fo = 0;
-    asm volatile("" : "+v"(fo));
+    int fo = zo;
     double dnx = s_fr[fo], dny = s_fr[fo + 1], dnz = s_fr[fo + 2];
     double d1x = s_fr[fo + 3], d1y = s_fr[fo + 4], d1z = s_fr[fo + 5];
     double d2x = s_fr[fo + 6], d2y = s_fr[fo + 7], d2z = s_fr[fo + 8];
@@ -572,7 +581,7 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     }
 
     // ---------------- frame: q.nhat, d.nhat, q.t1, d.t1, q.t2, d.t2 (float64)
-    asm volatile("" : "+v"(fo));
+    fo = s_zero[(base >> 6) & 63];
     dnx = s_fr[fo]; dny = s_fr[fo + 1]; dnz = s_fr[fo + 2];
     d1x = s_fr[fo + 3]; d1y = s_fr[fo + 4]; d1z = s_fr[fo + 5];
     d2x = s_fr[fo + 6]; d2y = s_fr[fo + 7]; d2z = s_fr[fo + 8];
