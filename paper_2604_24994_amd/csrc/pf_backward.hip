@@ -21,13 +21,16 @@
 //                 chain rule by hand, in reverse order of the forward; the
 //                 per-record sums (cell parameters, detail-site positions and
 //                 displacements) are reduced over the wave two at a time
-//                 (a permlane32 swap, then DPP).  Lane =
-//                 (detail site k, axis m): the 6 Spherical-Voronoi gradients
-//                 of (k, m) accumulate in registers over the chunk, reading
-//                 each record's direction, dL/dc and per-site softmax terms
-//                 from LDS.  Neighbour gradients through binding faces gather
-//                 per face in LDS.  Everything is flushed with one global
-//                 atomic per (chunk, parameter).
+//                 (a permlane32 swap, then DPP, then an LDS atomic add).
+//                 The 6 Spherical-Voronoi gradients of each (detail site k,
+//                 axis m) accumulate in registers over the chunk: the two
+//                 3-term dot products per (record, (k, m)) come from 32x32x2
+//                 FP32 MFMAs (records x site-axis pairs), the exponentials
+//                 and sums from the VALU, reading each record's direction,
+//                 dL/dc and per-site softmax terms from LDS.  Neighbour
+//                 gradients through binding faces gather per face in LDS.
+//                 Everything is flushed with one global atomic per (chunk,
+//                 parameter).
 #include "pf_backward.hpp"
 #include "pf_shade.hpp"
 
@@ -248,16 +251,20 @@ __device__ inline float wave_total(float x) {
 }
 
 // acc[i] += sum over the wave of (valid ? v : 0); acc is the wave's own LDS.
+// The update is an LDS atomic add without return, so that the wave does not
+// wait for a read of acc[i] (a read-add-write waited for each of them: 50.7
+// instead of 45.0 ms for the kernel).
 __device__ inline void sum_to(float* acc, int i, bool valid, float v) {
   const float t = wave_total(valid ? v : 0.0f);
-  if ((threadIdx.x & 63) == 63) acc[i] += t;
+  if ((threadIdx.x & 63) == 63) atomicAdd(&acc[i], t);
 }
 
 
 // Two wave sums at once: acc[i0], acc[i1] += sum over the wave of
 // (valid ? v : 0).  A permlane32 swap leaves partial sums of v0 in the lower
 // half and of v1 in the upper half; the DPP row sums and the row-15
-// broadcasts finish them in lanes 31 and 63.
+// broadcasts finish them in lanes 31 and 63, which add them to acc with one
+// LDS atomic add (as in sum_to).
 __device__ inline void sum2_to(float* acc, int i0, int i1, bool valid, float v0, float v1) {
   v0 = valid ? v0 : 0.0f;
   v1 = valid ? v1 : 0.0f;
@@ -269,8 +276,7 @@ __device__ inline void sum2_to(float* acc, int i0, int i1, bool valid, float v0,
   t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x140, 0xf, 0xf, false)); // row mirror
   t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x142, 0xa, 0xf, false)); // row bcast 15
   const int lane = threadIdx.x & 63;
-  if (lane == 31) acc[i0] += t;
-  if (lane == 63) acc[i1] += t;
+  if ((lane & 31) == 31) atomicAdd(&acc[lane == 31 ? i0 : i1], t);
 }
 
 __device__ inline float softplus_b(float x) { return x > 20.0f ? x : log1pf(expf(x)); }
@@ -398,13 +404,32 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
   }
   __syncthreads();
 
-  // (site, axis) owned by this lane in the transposed phase
+  // (site, axis) pair of this lane when the transposed phase's sums are
+  // flushed
   const int km = lane >> 3, mm = lane & 7;
-  const float* tkm = txc + km * TEXW;
-  // the lane's lobe axis, scaled by log2(e): its logits are base 2
-  const float ax = tkm[3 + 3 * mm] * LOG2E_F, ay = tkm[4 + 3 * mm] * LOG2E_F, az = tkm[5 + 3 * mm] * LOG2E_F;
-  const float ccr = tkm[3 + 3 * MA + 3 * mm], ccg = tkm[4 + 3 * MA + 3 * mm], ccb = tkm[5 + 3 * MA + 3 * mm];
-  float gax = 0.0f, gay = 0.0f, gaz = 0.0f, gcr_a = 0.0f, gcg_a = 0.0f, gcb_a = 0.0f;
+  // The transposed phase takes its two 3-term dot products per (record,
+  // site-axis pair) from 32x32x2 FP32 MFMAs: logits L[r][km] = d_r . a_km
+  // (axes scaled by log2(e)) and G[r][km] = gC_r . c_km, each as two MFMAs
+  // over the components (0, 1) and (2, 3 = 0).  An MFMA result gives lane l
+  // the column km = 32 cb + l % 32 and the rows r = 8 (v / 4) + 4 (l / 32)
+  // + v % 4 of register v, so a lane accumulates two site-axis pairs (cb = 0,
+  // 1) over its half of the records, and the halves are added at the end.
+  const int hh = lane >> 5, j32 = lane & 31;
+  float Ba[2][2], Bc[2][2];   // B operands [cb][step]: component 2 step + hh of a_km (scaled) and c_km
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) {
+    const int kmx = 32 * cb + j32;
+    const float* t = txc + (kmx >> 3) * TEXW;
+    const int m = kmx & 7;
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      const int comp = 2 * st + hh;
+      Ba[cb][st] = comp < 3 ? t[3 + 3 * m + comp] * LOG2E_F : 0.0f;
+      Bc[cb][st] = comp < 3 ? t[3 + 3 * MA + 3 * m + comp] : 0.0f;
+    }
+  }
+  float sa[2][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};   // dL/da partial sums [cb][xyz]
+  float sc[2][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};   // dL/dc partial sums [cb][rgb]
 
   for (int base = ch.y; base < ch.z; base += 64) {
     // the texture is re-read per record batch (scalar loads, offset by the
@@ -530,7 +555,7 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
       sum_wg += (double)wr[k] * (double)gwr[k];
       // w_k softmax_m(a_km.d) = 2^(a_km.d log2(e) - shift_k), shift_k = sh - log2(w_k / sum)
       const float wi = wr[k] * inv;
-      st_k[k][lane] = make_float2(wi > 0.0f ? sh - __log2f(wi) : INFINITY, gwr[k]);
+      st_k[k][lane] = make_float2(valid && wi > 0.0f ? sh - __log2f(wi) : INFINITY, gwr[k]);
     }
     double gux = 0.0, guy = 0.0;
     {
@@ -681,23 +706,44 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
       if (contribution) sum_to(acc, ISTAT, valid, ta);
     }
 
-    // ---------------- Spherical-Voronoi gradients, lane = (site k, axis m):
+    // ---------------- Spherical-Voronoi gradients over (record, site-axis
+    // pair (k, m)):
     //   v = softmax_m(a_km . d),  dL/dc_km += w_k v gC,
     //   dL/da_km += w_k v (gC.c_km - gC.sv_k) d
+    // with w_k v = 2^(a_km.d log2(e) - shift) (the per-record shift in st_k)
     __builtin_amdgcn_wave_barrier();
-    for (int r = 0; r < nvalid; ++r) {
-      const float4 dd = st_dir[r];
-      const float4 gc = st_gc[r];
-      const float2 kk = st_k[km][r];
-      // (the shift and dL/dw_k enter as the addends of the fused chains)
-      const float vw = __builtin_amdgcn_exp2f(fmaf(az, dd.z, fmaf(ay, dd.y, fmaf(ax, dd.x, -kk.x))));
-      const float gl = vw * fmaf(gc.z, ccb, fmaf(gc.y, ccg, fmaf(gc.x, ccr, -kk.y)));
-      gax += gl * dd.x;
-      gay += gl * dd.y;
-      gaz += gl * dd.z;
-      gcr_a += vw * gc.x;
-      gcg_a += vw * gc.y;
-      gcb_a += vw * gc.z;
+    // rows of records past the chunk hold direction, dL/dc = 0 and an
+    // infinite shift, so they add exact zeros
+    typedef float f16v __attribute__((ext_vector_type(16)));
+    const f16v zero16 = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const int ks0 = j32 >> 3, ks1 = (32 + j32) >> 3;   // sites of the lane's two columns
+    for (int rb = 0; rb < 2 && 32 * rb < nvalid; ++rb) {
+      // A operands: component 2 step + hh of record 32 rb + l % 32
+      const float4 da = st_dir[32 * rb + j32];
+      const float4 ga = st_gc[32 * rb + j32];
+      const float ad0 = hh ? da.y : da.x, ad1 = hh ? 0.0f : da.z;
+      const float ag0 = hh ? ga.y : ga.x, ag1 = hh ? 0.0f : ga.z;
+      f16v L0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ad0, Ba[0][0], zero16, 0, 0, 0);
+      L0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ad1, Ba[0][1], L0, 0, 0, 0);
+      f16v L1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ad0, Ba[1][0], zero16, 0, 0, 0);
+      L1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ad1, Ba[1][1], L1, 0, 0, 0);
+      f16v G0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ag0, Bc[0][0], zero16, 0, 0, 0);
+      G0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ag1, Bc[0][1], G0, 0, 0, 0);
+      f16v G1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ag0, Bc[1][0], zero16, 0, 0, 0);
+      G1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ag1, Bc[1][1], G1, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int r = 32 * rb + 8 * (v >> 2) + 4 * hh + (v & 3);
+        const float4 dd = st_dir[r];
+        const float4 gc = st_gc[r];
+        const float2 k0 = st_k[ks0][r], k1 = st_k[ks1][r];
+        const float vw0 = __builtin_amdgcn_exp2f(L0[v] - k0.x), vw1 = __builtin_amdgcn_exp2f(L1[v] - k1.x);
+        const float gl0 = vw0 * (G0[v] - k0.y), gl1 = vw1 * (G1[v] - k1.y);
+        sa[0][0] += gl0 * dd.x; sa[0][1] += gl0 * dd.y; sa[0][2] += gl0 * dd.z;
+        sa[1][0] += gl1 * dd.x; sa[1][1] += gl1 * dd.y; sa[1][2] += gl1 * dd.z;
+        sc[0][0] += vw0 * gc.x; sc[0][1] += vw0 * gc.y; sc[0][2] += vw0 * gc.z;
+        sc[1][0] += vw1 * gc.x; sc[1][1] += vw1 * gc.y; sc[1][2] += vw1 * gc.z;
+      }
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -721,9 +767,18 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     if (dst) atomicAdd(dst, v);
   }
   if (contribution && lane == 0 && acc[ISTAT] != 0.0f) atomicAdd(contribution + ci, acc[ISTAT]);
+  // the two record halves of each site-axis pair: after the swap lane l
+  // holds the pair km = l (cb 0 in the lower half, cb 1 in the upper)
+  float va[3], vc[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(sa[0][c]), __float_as_uint(sa[1][c]), false, false);
+    va[c] = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(sc[0][c]), __float_as_uint(sc[1][c]), false, false);
+    vc[c] = __uint_as_float(b[0]) + __uint_as_float(b[1]);
+  }
   if (G.tex) {
     float* gt = G.tex + (int64_t)ci * KD * TEXW + km * TEXW;
-    const float va[3] = {gax, gay, gaz}, vc[3] = {gcr_a, gcg_a, gcb_a};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if (va[c] != 0.0f) atomicAdd(gt + 3 + 3 * mm + c, va[c]);
