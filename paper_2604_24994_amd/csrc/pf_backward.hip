@@ -139,7 +139,9 @@ __global__ void __launch_bounds__(256) k_suffix_seg(const int4* __restrict__ seg
     base += (int64_t)cams[v].width * cams[v].height;
   }
   const int W = cams[v].width, H = cams[v].height, tiles_x = (W + TILE - 1) / TILE;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // (the wave index made visibly wave-uniform, so that the wave's segments
+  // are read through scalar loads: 3.4 -> 3.0 ms)
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int px = (int)(tile % tiles_x) * TILE + (w & 1) * 8 + (lane & 7);
   const int py = (int)(tile / tiles_x) * TILE + (w >> 1) * 8 + (lane >> 3);
   const bool inside = px < W && py < H;
