@@ -49,16 +49,16 @@ FLOPS_BWD_PER_CONTRIB = 5100
 # (FETCH_SIZE reads 0.5 GiB: x2.0; WRITE_SIZE reads 1 GiB: x1.0).  Valid only
 # for the kernel sources with these hashes; otherwise the bench reports null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
-_SRC_SHADE = {"pf_shade.hpp": "a6941abe41bd58ca", "pf_internal.hpp": "cf1b6d1fee18a09d",
+_SRC_SHADE = {"pf_shade.hpp": "fafcd449bb434a34", "pf_internal.hpp": "cf1b6d1fee18a09d",
               "pf_record.hpp": "d8db4e8267ff8479"}
 TRAFFIC = {
-    "k_bwd_cell": {"fetch_kib": 8093849.2, "write_kib": 3984548.9,
-                   "sources": {"pf_backward.hip": "e2adef89187752bc", **_SRC_SHADE}},
-    "k_raster_store": {"fetch_kib": 16542742.0, "write_kib": 11314482.6,
-                       "sources": {"pf_render.hip": "6e14c345d96e4a68", **_SRC_SHADE}},
-    "k_trace": {"fetch_kib": 8345572.3, "write_kib": 33312.5,
-                "sources": {"pf_render.hip": "6e14c345d96e4a68", **_SRC_SHADE}},
-    "k_clip": {"fetch_kib": 409414.4, "write_kib": 180395.2,
+    "k_bwd_cell": {"fetch_kib": 7867405.2, "write_kib": 2407154.7,
+                   "sources": {"pf_backward.hip": "10b412baaff6b7e6", **_SRC_SHADE}},
+    "k_raster_store": {"fetch_kib": 17664597.3, "write_kib": 11373101.4,
+                       "sources": {"pf_render.hip": "a67c4fc69285267c", **_SRC_SHADE}},
+    "k_trace": {"fetch_kib": 8360759.4, "write_kib": 46637.5,
+                "sources": {"pf_render.hip": "a67c4fc69285267c", **_SRC_SHADE}},
+    "k_clip": {"fetch_kib": 409452.2, "write_kib": 180425.5,
                "sources": {"pf_build.hip": "60ddab952277c61e", "pf_internal.hpp": "cf1b6d1fee18a09d",
                            "pf_record.hpp": "d8db4e8267ff8479"}},
 }
