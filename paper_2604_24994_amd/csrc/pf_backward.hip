@@ -20,8 +20,9 @@
 //                 dipole split with displacement, radiance) and applies the
 //                 chain rule by hand, in reverse order of the forward; the
 //                 per-record sums (cell parameters, detail-site positions and
-//                 displacements) are reduced over the wave two at a time
-//                 (a permlane32 swap, then DPP, then an LDS atomic add).
+//                 displacements) are reduced over the wave two or four at
+//                 a time (permlane32 / permlane16 swaps, then DPP, then an
+//                 LDS atomic add).
 //                 The 6 Spherical-Voronoi gradients of each (detail site k,
 //                 axis m) accumulate in registers over the chunk: the two
 //                 3-term dot products per (record, (k, m)) come from 32x32x2
@@ -279,6 +280,34 @@ __device__ inline void sum2_to(float* acc, int i0, int i1, bool valid, float v0,
   t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x142, 0xa, 0xf, false)); // row bcast 15
   const int lane = threadIdx.x & 63;
   if ((lane & 31) == 31) atomicAdd(&acc[lane == 31 ? i0 : i1], t);
+}
+
+// Four wave sums at once: acc[i0..i3] += sum over the wave of (valid ? v : 0).
+// permlane32 swaps pair v0 with v1 and v2 with v3, a permlane16 swap pairs
+// the results, so that after two adds rows 0..3 of the wave hold partial sums
+// of v0, v2, v1, v3; four DPP steps finish the row sums, and the first lane
+// of each row adds its value to acc (LDS atomic).
+__device__ inline void sum4_to(float* acc, int i0, int i1, int i2, int i3, bool valid, float v0, float v1, float v2,
+                               float v3) {
+  v0 = valid ? v0 : 0.0f;
+  v1 = valid ? v1 : 0.0f;
+  v2 = valid ? v2 : 0.0f;
+  v3 = valid ? v3 : 0.0f;
+  const auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(v0), __float_as_uint(v1), false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(v2), __float_as_uint(v3), false, false);
+  const float s01 = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+  const float s23 = __uint_as_float(b[0]) + __uint_as_float(b[1]);
+  const auto c = __builtin_amdgcn_permlane16_swap(__float_as_uint(s01), __float_as_uint(s23), false, false);
+  float t = __uint_as_float(c[0]) + __uint_as_float(c[1]);
+  t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0xB1, 0xf, 0xf, false));  // quad [1,0,3,2]
+  t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x4E, 0xf, 0xf, false));  // quad [2,3,0,1]
+  t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x141, 0xf, 0xf, false)); // row half mirror
+  t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x140, 0xf, 0xf, false)); // row mirror
+  const int lane = threadIdx.x & 63;
+  if ((lane & 15) == 0) {
+    const int row = lane >> 4;
+    atomicAdd(&acc[row == 0 ? i0 : row == 1 ? i2 : row == 2 ? i1 : i3], t);
+  }
 }
 
 __device__ inline float softplus_b(float x) { return x > 20.0f ? x : log1pf(expf(x)); }
@@ -587,11 +616,12 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
       g_den -= g_sx * sxx * idn;
       double sum_w = 0.0;
       double gw[KD];
-      static_assert(KD % 2 == 0 && NCELL % 2 == 0, "wave sums go two at a time");
+      static_assert(KD % 4 == 0 && NCELL % 4 == 0, "these wave sums go four at a time");
 #pragma unroll
-      for (int k = 0; k < KD; k += 2)
-        sum2_to(acc, NCELL + 3 * k + 2, NCELL + 3 * k + 5, valid, (float)(g_delta * (double)wd[k]),
-                (float)(g_delta * (double)wd[k + 1]));
+      for (int k = 0; k < KD; k += 4)
+        sum4_to(acc, NCELL + 3 * k + 2, NCELL + 3 * k + 5, NCELL + 3 * k + 8, NCELL + 3 * k + 11, valid,
+                (float)(g_delta * (double)wd[k]), (float)(g_delta * (double)wd[k + 1]),
+                (float)(g_delta * (double)wd[k + 2]), (float)(g_delta * (double)wd[k + 3]));
 #pragma unroll
       for (int k = 0; k < KD; ++k) {
         gw[k] = g_delta * (double)tx[k * TEXW + 2];
@@ -711,7 +741,8 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     {
       const float cellv[NCELL] = {gpx, gpy, gpz, g_wi, g_r, gnx, gny, gnz, g_lam, gcr, gcg, gcb};
 #pragma unroll
-      for (int i = 0; i < NCELL; i += 2) sum2_to(acc, i, i + 1, valid, cellv[i], cellv[i + 1]);
+      for (int i = 0; i < NCELL; i += 4)
+        sum4_to(acc, i, i + 1, i + 2, i + 3, valid, cellv[i], cellv[i + 1], cellv[i + 2], cellv[i + 3]);
       if (contribution) sum_to(acc, ISTAT, valid, ta);
     }
 
