@@ -20,9 +20,10 @@
 //                 dipole split with displacement, radiance) and applies the
 //                 chain rule by hand, in reverse order of the forward; the
 //                 per-record sums (cell parameters, detail-site positions and
-//                 displacements) are reduced over the wave two or four at
-//                 a time (permlane32 / permlane16 swaps, then DPP, then an
-//                 LDS atomic add).
+//                 displacements) are reduced over the wave four at a time
+//                 (permlane32 / permlane16 swaps, then DPP, then an LDS
+//                 atomic add).  The next batch's records are loaded while a
+//                 batch is processed.
 //                 The 6 Spherical-Voronoi gradients of each (detail site k,
 //                 axis m) accumulate in registers over the chunk: the two
 //                 3-term dot products per (record, (k, m)) come from 32x32x2
@@ -263,32 +264,17 @@ __device__ inline void sum_to(float* acc, int i, bool valid, float v) {
 }
 
 
-// Two wave sums at once: acc[i0], acc[i1] += sum over the wave of
-// (valid ? v : 0).  A permlane32 swap leaves partial sums of v0 in the lower
-// half and of v1 in the upper half; the DPP row sums and the row-15
-// broadcasts finish them in lanes 31 and 63, which add them to acc with one
-// LDS atomic add (as in sum_to).
-__device__ inline void sum2_to(float* acc, int i0, int i1, bool valid, float v0, float v1) {
-  v0 = valid ? v0 : 0.0f;
-  v1 = valid ? v1 : 0.0f;
-  const auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(v0), __float_as_uint(v1), false, false);
-  float t = __uint_as_float(a[0]) + __uint_as_float(a[1]);
-  t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0xB1, 0xf, 0xf, false));  // quad [1,0,3,2]
-  t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x4E, 0xf, 0xf, false));  // quad [2,3,0,1]
-  t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x141, 0xf, 0xf, false)); // row half mirror
-  t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x140, 0xf, 0xf, false)); // row mirror
-  t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x142, 0xa, 0xf, false)); // row bcast 15
-  const int lane = threadIdx.x & 63;
-  if ((lane & 31) == 31) atomicAdd(&acc[lane == 31 ? i0 : i1], t);
-}
+// Four wave sums at once: acc[dst] += sum over the wave of (valid ? v_j : 0)
+// for j = sum4_value(lane), in the first lane of each row of 16.  permlane32
+// swaps pair v0 with v1 and v2 with v3, a permlane16 swap pairs the results,
+// so that after two adds rows 0..3 of the wave hold partial sums of v0, v2,
+// v1, v3; four DPP steps finish the row sums, and the first lane of each row
+// adds its value to acc[dst] (LDS atomic).  dst is computed by the caller from
+// sum4_value(lane), a per-lane constant, so that the choice of the
+// destination costs no branch.
+__device__ inline int sum4_value(int lane) { return ((lane >> 4) & 1) * 2 + (lane >> 5); }
 
-// Four wave sums at once: acc[i0..i3] += sum over the wave of (valid ? v : 0).
-// permlane32 swaps pair v0 with v1 and v2 with v3, a permlane16 swap pairs
-// the results, so that after two adds rows 0..3 of the wave hold partial sums
-// of v0, v2, v1, v3; four DPP steps finish the row sums, and the first lane
-// of each row adds its value to acc (LDS atomic).
-__device__ inline void sum4_to(float* acc, int i0, int i1, int i2, int i3, bool valid, float v0, float v1, float v2,
-                               float v3) {
+__device__ inline void sum4_to(float* acc, int dst, bool valid, float v0, float v1, float v2, float v3) {
   v0 = valid ? v0 : 0.0f;
   v1 = valid ? v1 : 0.0f;
   v2 = valid ? v2 : 0.0f;
@@ -303,11 +289,7 @@ __device__ inline void sum4_to(float* acc, int i0, int i1, int i2, int i3, bool 
   t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x4E, 0xf, 0xf, false));  // quad [2,3,0,1]
   t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x141, 0xf, 0xf, false)); // row half mirror
   t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x140, 0xf, 0xf, false)); // row mirror
-  const int lane = threadIdx.x & 63;
-  if ((lane & 15) == 0) {
-    const int row = lane >> 4;
-    atomicAdd(&acc[row == 0 ? i0 : row == 1 ? i2 : row == 2 ? i1 : i3], t);
-  }
+  if ((threadIdx.x & 15) == 0) atomicAdd(&acc[dst], t);
 }
 
 __device__ inline float softplus_b(float x) { return x > 20.0f ? x : log1pf(expf(x)); }
@@ -359,27 +341,36 @@ __device__ inline void sv_backward(const float* __restrict__ tx, double ux_d, do
   const float u2 = ux * ux + uy * uy;
   const float iun = u2 > 0.0f ? __builtin_amdgcn_rsqf(u2) : 0.0f;
   const float un = u2 * iun;
+  const int j4 = sum4_value(threadIdx.x);   // site k0 + j4 / 2, coordinate j4 % 2
+  static_assert(KD % 2 == 0, "the site sums go two sites at a time");
 #pragma unroll
-  for (int k = 0; k < KD; ++k) {
-    const float sx = tx[k * TEXW], sy = tx[k * TEXW + 1];
-    const float ex = ux - sx, ey = uy - sy;
-    const float d2 = ex * ex + ey * ey;
-    const float rd = d2 > 0.0f ? __builtin_amdgcn_rsqf(d2) : 0.0f;
-    const float dist = d2 * rd;
-    float lx, ly;
-    if (un > 0.0f && dist > 0.0f) {
-      const float e = (sx * sx + sy * sy - 2.0f * (ux * sx + uy * sy)) * frcp(dist + un);   // |u - s| - |u|
-      const float f = rd * iun;
-      lx = (-ux * e - sx * un) * f;
-      ly = (-uy * e - sy * un) * f;
-    } else {
-      lx = ex * rd;
-      ly = ey * rd;
+  for (int k0 = 0; k0 < KD; k0 += 2) {
+    float vx[2], vy[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = k0 + h;
+      const float sx = tx[k * TEXW], sy = tx[k * TEXW + 1];
+      const float ex = ux - sx, ey = uy - sy;
+      const float d2 = ex * ex + ey * ey;
+      const float rd = d2 > 0.0f ? __builtin_amdgcn_rsqf(d2) : 0.0f;
+      const float dist = d2 * rd;
+      float lx, ly;
+      if (un > 0.0f && dist > 0.0f) {
+        const float e = (sx * sx + sy * sy - 2.0f * (ux * sx + uy * sy)) * frcp(dist + un);   // |u - s| - |u|
+        const float f = rd * iun;
+        lx = (-ux * e - sx * un) * f;
+        ly = (-uy * e - sy * un) * f;
+      } else {
+        lx = ex * rd;
+        ly = ey * rd;
+      }
+      gux += ge[k] * (double)lx;
+      guy += ge[k] * (double)ly;
+      const float gk = (float)ge[k];
+      vx[h] = -gk * ex * rd;
+      vy[h] = -gk * ey * rd;
     }
-    gux += ge[k] * (double)lx;
-    guy += ge[k] * (double)ly;
-    const float gk = (float)ge[k];
-    sum2_to(acc, NCELL + 3 * k, NCELL + 3 * k + 1, valid, -gk * ex * rd, -gk * ey * rd);
+    sum4_to(acc, NCELL + 3 * k0 + j4 + (j4 >> 1), valid, vx[0], vy[0], vx[1], vy[1]);
   }
 }
 
@@ -469,6 +460,18 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
   float sa[2][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};   // dL/da partial sums [cb][xyz]
   float sc[2][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};   // dL/dc partial sums [cb][rgb]
 
+  // the records of the next batch are loaded while this one is processed:
+  // its order entries at the start of a batch, the records themselves once
+  // the batch's own camera and face loads have returned
+  int4 n_rec = make_int4(0, 0, -1, 0);
+  float4 n_gf = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  float n_ta = 0.0f;
+  if (ch.y + lane < ch.z) {
+    const int ridx = order[ch.y + lane];
+    n_rec = ri[ridx];
+    n_gf = rf[ridx];
+    n_ta = rta[ridx];
+  }
   for (int base = ch.y; base < ch.z; base += 64) {
     // the texture is re-read per record batch (scalar loads, offset by the
     // opaque zero) rather than held in registers across the loop
@@ -477,18 +480,20 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     const int idx = base + lane;
     const bool valid = idx < ch.z;
     const int nvalid = min(64, ch.z - base);
-    int4 rec = make_int4(0, 0, -1, 0);
-    float4 gf = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    float ta = 0.0f;   // the contribution T a
-    if (valid) {
-      const int ridx = order[idx];
-      rec = ri[ridx];
-      gf = rf[ridx];
-      ta = rta[ridx];
-    }
+    const int4 rec = n_rec;
+    const float4 gf = n_gf;
+    const float ta = n_ta;   // the contribution T a
+    const int nidx = idx + 64;
+    const bool n_valid = nidx < ch.z;
+    const int n_ridx = order[min(nidx, ch.z - 1)];   // (in the chunk; used only if n_valid)
     const int view = rec_view(rec.w);
     const int b0 = rec_bind0(rec.w), b1 = rec_bind1(rec.w);
-    const pf_camera& cam = cams[valid ? view : 0];
+    // the binding faces' planes, loaded before the ray set-up
+    const float4 pl0 = (b0 >= 0 && b0 < nf) ? plane[r0 + b0] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const float4 pl1 = (b1 >= 0 && b1 < nf) ? plane[r0 + b1] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    // the camera is copied at once (its loads issued together) rather than
+    // read field by field behind the branches of the ray set-up
+    const pf_camera cam = cams[valid ? view : 0];
     const int pxl = rec.y % cam.width, pyl = rec.y / cam.width;
     const RayD R = make_ray(cam, pxl + 0.5, pyl + 0.5);
     const float fx = R.fx, fy = R.fy, fz = R.fz;
@@ -509,14 +514,20 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
     const Local L = make_local(R, cpx, cpy, cpz);
     const double Dd = (double)crad * (double)crad - L.qq;
     const float sq = fsqrt((float)fmax(Dd, 1e-30));
-    const float4 pl0 = (b0 >= 0 && b0 < nf) ? plane[r0 + b0] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    const float4 pl1 = (b1 >= 0 && b1 < nf) ? plane[r0 + b1] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const float a0 = fx * pl0.x + fy * pl0.y + fz * pl0.z;
     const float a1 = fx * pl1.x + fy * pl1.y + fz * pl1.z;
     const float s0 = (b0 == -1) ? -sq
                      : (b0 == -2) ? L.beta
                                   : face_offset(pl0, -L.qx, -L.qy, -L.qz) * frcp(a0);
     const float s1 = (b1 == -1) ? sq : face_offset(pl1, -L.qx, -L.qy, -L.qz) * frcp(a1);
+    n_rec = make_int4(0, 0, -1, 0);
+    n_gf = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    n_ta = 0.0f;
+    if (n_valid) {
+      n_rec = ri[n_ridx];
+      n_gf = rf[n_ridx];
+      n_ta = rta[n_ridx];
+    }
     const double ddx = R.dx, ddy = R.dy, ddz = R.dz;
     const double qdx = L.dqx, qdy = L.dqy, qdz = L.dqz;
     // (an opaque offset, so that the frame is read here, not hoisted)
@@ -619,7 +630,7 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
       static_assert(KD % 4 == 0 && NCELL % 4 == 0, "these wave sums go four at a time");
 #pragma unroll
       for (int k = 0; k < KD; k += 4)
-        sum4_to(acc, NCELL + 3 * k + 2, NCELL + 3 * k + 5, NCELL + 3 * k + 8, NCELL + 3 * k + 11, valid,
+        sum4_to(acc, NCELL + 3 * (k + sum4_value(lane)) + 2, valid,
                 (float)(g_delta * (double)wd[k]), (float)(g_delta * (double)wd[k + 1]),
                 (float)(g_delta * (double)wd[k + 2]), (float)(g_delta * (double)wd[k + 3]));
 #pragma unroll
@@ -742,7 +753,7 @@ __global__ void __launch_bounds__(BWD_THREADS) __attribute__((amdgpu_waves_per_e
       const float cellv[NCELL] = {gpx, gpy, gpz, g_wi, g_r, gnx, gny, gnz, g_lam, gcr, gcg, gcb};
 #pragma unroll
       for (int i = 0; i < NCELL; i += 4)
-        sum4_to(acc, i, i + 1, i + 2, i + 3, valid, cellv[i], cellv[i + 1], cellv[i + 2], cellv[i + 3]);
+        sum4_to(acc, i + sum4_value(lane), valid, cellv[i], cellv[i + 1], cellv[i + 2], cellv[i + 3]);
       if (contribution) sum_to(acc, ISTAT, valid, ta);
     }
 
