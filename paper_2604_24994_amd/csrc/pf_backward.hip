@@ -214,15 +214,30 @@ __global__ void k_seg_hist(const int4* __restrict__ seg, int64_t nseg, uint32_t*
   }
 }
 
+// A lane per segment reserves the segment's run of its cell's order list;
+// the wave then writes its segments' runs one after the other, a lane per
+// entry (a segment holds at most 64 records), so that every store is
+// contiguous across the wave.
 __global__ void k_seg_scatter(const int4* __restrict__ seg, int64_t nseg, const uint32_t* __restrict__ off,
                               uint32_t* __restrict__ fill, int32_t* __restrict__ order) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nseg) return;
-  const int4 g = seg[i];
-  const int c = seg_count(g);
-  if (c == 0) return;   // block header or unused slot
-  const uint32_t at = off[g.x] + atomicAdd(&fill[g.x], (uint32_t)c);
-  for (int j = 0; j < c; ++j) order[at + j] = g.y + j;
+  const int lane = threadIdx.x & 63;
+  int c = 0, first = 0;
+  uint32_t at = 0;
+  if (i < nseg) {
+    const int4 g = seg[i];
+    c = seg_count(g);   // 0: block header or unused slot
+    if (c > 0) {
+      at = off[g.x] + atomicAdd(&fill[g.x], (uint32_t)c);
+      first = g.y;
+    }
+  }
+  for (uint64_t m = __ballot(c > 0); m; m &= m - 1) {
+    const int src = __ffsll((long long)m) - 1;
+    const int cs = __builtin_amdgcn_readlane(c, src), fs = __builtin_amdgcn_readlane(first, src);
+    const uint32_t as = (uint32_t)__builtin_amdgcn_readlane((int)at, src);
+    if (lane < cs) order[as + lane] = fs + lane;
+  }
 }
 
 __global__ void k_chunk_count(const uint32_t* __restrict__ cnt, int64_t n, uint32_t* __restrict__ nch) {
