@@ -52,12 +52,12 @@ FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 _SRC_SHADE = {"pf_shade.hpp": "fafcd449bb434a34", "pf_internal.hpp": "cf1b6d1fee18a09d",
               "pf_record.hpp": "d8db4e8267ff8479"}
 TRAFFIC = {
-    "k_bwd_cell": {"fetch_kib": 7866010.0, "write_kib": 2408130.0,
+    "k_bwd_cell": {"fetch_kib": 7865956.2, "write_kib": 2407854.8,
                    "sources": {"pf_backward.hip": "0f3845d019c4e4df", **_SRC_SHADE}},
-    "k_raster_store": {"fetch_kib": 17664597.3, "write_kib": 11373101.4,
-                       "sources": {"pf_render.hip": "a67c4fc69285267c", **_SRC_SHADE}},
-    "k_trace": {"fetch_kib": 8360759.4, "write_kib": 46637.5,
-                "sources": {"pf_render.hip": "a67c4fc69285267c", **_SRC_SHADE}},
+    "k_raster_store": {"fetch_kib": 17658935.2, "write_kib": 11376420.5,
+                       "sources": {"pf_render.hip": "1e3097ce83ad03bf", **_SRC_SHADE}},
+    "k_trace": {"fetch_kib": 8362485.9, "write_kib": 46637.5,
+                "sources": {"pf_render.hip": "1e3097ce83ad03bf", **_SRC_SHADE}},
     "k_clip": {"fetch_kib": 409452.2, "write_kib": 180425.5,
                "sources": {"pf_build.hip": "60ddab952277c61e", "pf_internal.hpp": "cf1b6d1fee18a09d",
                            "pf_record.hpp": "d8db4e8267ff8479"}},

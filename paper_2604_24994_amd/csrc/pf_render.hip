@@ -202,28 +202,71 @@ __global__ void k_view_count(const ViewDev* __restrict__ views, const float4* __
   key[o] = order_key((float)(ex * ex + ey * ey + ez * ez - (double)power[i]));
 }
 
-__global__ void k_view_emit(const ViewDev* __restrict__ views, const float4* __restrict__ geo,
-                            const float* __restrict__ cull, int64_t n, const uint32_t* __restrict__ off,
-                            const uint32_t* __restrict__ key, uint32_t* __restrict__ ptile,
-                            unsigned long long* __restrict__ pval, uint32_t* __restrict__ tile_cnt) {
+// blockIdx.y = view; a lane per (view, cell).  A wave emits its cells'
+// pixel rectangles together: after a scan of the pair counts over the wave,
+// it writes 64 pairs at a time, pair p taken by the lane whose run holds p,
+// so that a cell whose footprint covers many tiles is spread over the wave
+// rather than holding it, and the stores of a step are contiguous.  A
+// cell's pairs keep the order of its rectangle (rows of tiles, then tiles).
+__global__ void __launch_bounds__(256) k_view_emit(const ViewDev* __restrict__ views, const float4* __restrict__ geo,
+                                                   const float* __restrict__ cull, int64_t n,
+                                                   const uint32_t* __restrict__ off, const uint32_t* __restrict__ key,
+                                                   uint32_t* __restrict__ ptile, unsigned long long* __restrict__ pval,
+                                                   uint32_t* __restrict__ tile_cnt) {
+  __shared__ int s_end[4][64];   // end of each lane's run of the wave's pairs
+  __shared__ int s_x0[4][64], s_y0[4][64], s_w[4][64];
+  __shared__ uint32_t s_o[4][64];
+  __shared__ unsigned long long s_val[4][64];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const ViewDev& vd = views[blockIdx.y];
-  const int64_t oi = (int64_t)blockIdx.y * n + i;
-  int x0, x1, y0, y1;
-  Cone k;
-  const int mode = cell_rect(vd.v, geo[i], cull[i], x0, x1, y0, y1, k);
-  if (mode != 1) return;   // cone footprints: k_cone_emit
-  uint32_t o = off[oi];
-  const unsigned long long val = ((unsigned long long)key[oi] << 32) | (uint32_t)i;
-  for (int ty = y0; ty <= y1; ++ty)
-    for (int tx = x0; tx <= x1; ++tx) {
-      const uint32_t t = (uint32_t)(vd.tile_base + ty * vd.v.tiles_x + tx);
-      ptile[o] = t;
-      pval[o] = val;
-      atomicAdd(&tile_cnt[t], 1u);
-      ++o;
+  int nt = 0, x0 = 0, x1 = -1, y0 = 0, y1 = -1;
+  uint32_t o = 0;
+  unsigned long long val = 0;
+  if (i < n) {
+    const int64_t oi = (int64_t)blockIdx.y * n + i;
+    Cone k;
+    const int mode = cell_rect(vd.v, geo[i], cull[i], x0, x1, y0, y1, k);
+    if (mode == 1) {   // (cone footprints: k_cone_emit)
+      nt = (x1 - x0 + 1) * (y1 - y0 + 1);
+      o = off[oi];
+      val = ((unsigned long long)key[oi] << 32) | (uint32_t)i;
     }
+  }
+  int end = nt;
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(end, d, 64);
+    if (lane >= d) end += t;
+  }
+  const int total = __shfl(end, 63, 64);
+  s_end[wv][lane] = end;
+  s_x0[wv][lane] = x0;
+  s_y0[wv][lane] = y0;
+  s_w[wv][lane] = x1 - x0 + 1;
+  s_o[wv][lane] = o;
+  s_val[wv][lane] = val;
+  __syncthreads();
+  const uint32_t tbase = (uint32_t)vd.tile_base;
+  const int tiles_x = vd.v.tiles_x;
+  for (int base = 0; base < total; base += 64) {
+    const int p = base + lane;
+    if (p >= total) break;
+    // owner: the first lane whose run ends after p
+    int lo = 0, hi = 63;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (s_end[wv][mid] > p) hi = mid;
+      else lo = mid + 1;
+    }
+    const int r = p - (lo == 0 ? 0 : s_end[wv][lo - 1]);
+    const int w = s_w[wv][lo];
+    const int ty = s_y0[wv][lo] + r / w, tx = s_x0[wv][lo] + r % w;
+    const uint32_t t = tbase + (uint32_t)(ty * tiles_x + tx);
+    const uint32_t at = s_o[wv][lo] + (uint32_t)r;
+    ptile[at] = t;
+    pval[at] = s_val[wv][lo];
+    atomicAdd(&tile_cnt[t], 1u);
+  }
 }
 
 // One workgroup per listed (view, cell): its threads test the tiles of the
