@@ -13,6 +13,7 @@
 //                 k_suffix_seg walks each wave's segments in reverse append
 //                 order; walk records: k_suffix follows the pixel chains
 //   k_seg_hist /  records grouped by cell through the forward's segment list
+//                 (raster records: counted per cell by k_suffix_seg)
 //   k_seg_scatter (one atomic per segment of <= 64 contiguous records)
 //   k_bwd_cell    one wave per chunk of a cell's records, 64 records at a
 //                 time.  Lane = record: re-derives the piece (bounded
@@ -126,12 +127,15 @@ __global__ void __launch_bounds__(256) k_suffix(const int32_t* __restrict__ head
 // to front as along its chain (the arithmetic is the same, in the same
 // order).  A segment's records are contiguous and its cell is uniform: the
 // loads and stores are coalesced and no record waits for the one behind it.
+// The pass also adds each segment's record count to cnt[cell] (zeroed by
+// the caller), the histogram that groups the records by cell.
 __global__ void __launch_bounds__(256) k_suffix_seg(const int4* __restrict__ seg, const int2* __restrict__ wtail,
                                                     int ncam, int64_t tile0, const float* __restrict__ d_rgba,
                                                     float4* __restrict__ rf, float* __restrict__ rt,
                                                     const pf_camera* __restrict__ cams, const float4* __restrict__ nrm,
                                                     float lambda_n, double* __restrict__ normal_loss,
-                                                    const float* __restrict__ pix_err, float* __restrict__ rte) {
+                                                    const float* __restrict__ pix_err, float* __restrict__ rte,
+                                                    uint32_t* __restrict__ cnt) {
   int64_t tile = tile0 + blockIdx.x, base = 0;
   int v = 0;
   for (; v < ncam - 1; ++v) {
@@ -172,6 +176,9 @@ __global__ void __launch_bounds__(256) k_suffix_seg(const int4* __restrict__ seg
     for (int j = top - 1; j >= 1; --j) {   // slot 0 is the block's header
       const int4 g = seg[(int64_t)blk + j];
       const uint64_t m = (uint64_t)(uint32_t)g.z | ((uint64_t)(uint32_t)g.w << 32);
+      // the per-cell record counts of the grouping by cell (every segment
+      // lies on exactly one wave's chain)
+      if (lane == 0 && m) atomicAdd(&cnt[g.x], (uint32_t)__popcll(m));
       if (!((m >> lane) & 1ull)) continue;
       const int64_t k = (int64_t)g.y + __popcll(m & lt);
       const float4 f = rf[k];
@@ -905,13 +912,17 @@ pf_status backward_impl(const Scene& sc, const BwdState& st, const float* d_rgba
   // indexed like the records: slots are reserved per wave in blocks, so
   // indices run up to the pool capacity, not to the record count
   if (want_err) PF_HIP_TRY(rte.alloc(st.rec.cap));
+  Buf<uint32_t> cnt(s), off(s), fill(s), nch(s), choff(s);
+  Buf<int32_t> order(s);
+  PF_HIP_TRY(cnt.alloc(n + 1));
+  PF_HIP_TRY(hipMemsetAsync(cnt.p, 0, sizeof(uint32_t) * (n + 1), s));
   {
     ProfScope ps("k_suffix", s);
-    if (st.rec.wtail)   // raster records: walk the waves' segments
+    if (st.rec.wtail)   // raster records: walk the waves' segments (and count the records per cell)
       k_suffix_seg<<<gp, 256, 0, s>>>(st.rec.seg, st.rec.wtail, st.ncam, st.tile0, d_rgba, st.rec.rf, st.rec.rt,
                                       st.cams_dev,
                                       sc.nrm, opt.lambda_normal, opt.normal_loss,
-                                      want_err ? opt.pixel_error : nullptr, want_err ? rte.p : nullptr);
+                                      want_err ? opt.pixel_error : nullptr, want_err ? rte.p : nullptr, cnt.p);
     else                // ray-walk records: follow the per-pixel chains
       k_suffix<<<gp, 256, 0, s>>>(st.rec.head, st.ncam, st.tile0, d_rgba, st.rec.ri, st.rec.rf, st.rec.rt, st.cams_dev,
                                   sc.nrm,
@@ -919,18 +930,14 @@ pf_status backward_impl(const Scene& sc, const BwdState& st, const float* d_rgba
                                   want_err ? rte.p : nullptr);
   }
   PF_HIP_TRY(hipGetLastError());
-  Buf<uint32_t> cnt(s), off(s), fill(s), nch(s), choff(s);
-  Buf<int32_t> order(s);
-  PF_HIP_TRY(cnt.alloc(n + 1));
   PF_HIP_TRY(off.alloc(n + 1));
   PF_HIP_TRY(fill.alloc(n));
   PF_HIP_TRY(nch.alloc(n + 1));
   PF_HIP_TRY(choff.alloc(n + 1));
   PF_HIP_TRY(order.alloc(nrec));
-  PF_HIP_TRY(hipMemsetAsync(cnt.p, 0, sizeof(uint32_t) * (n + 1), s));
   PF_HIP_TRY(hipMemsetAsync(fill.p, 0, sizeof(uint32_t) * n, s));
   const unsigned gsg = (unsigned)((st.nseg + 255) / 256), gc = (unsigned)((n + 255) / 256);
-  if (st.nseg) {
+  if (st.nseg && !st.rec.wtail) {   // (raster records were counted by k_suffix_seg)
     ProfScope ps("k_seg_hist", s);
     k_seg_hist<<<gsg, 256, 0, s>>>(st.rec.seg, st.nseg, cnt.p);
   }
