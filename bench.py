@@ -52,11 +52,11 @@ FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 _SRC_SHADE = {"pf_shade.hpp": "fafcd449bb434a34", "pf_internal.hpp": "cf1b6d1fee18a09d",
               "pf_record.hpp": "d8db4e8267ff8479"}
 TRAFFIC = {
-    "k_bwd_cell": {"fetch_kib": 7865956.2, "write_kib": 2407854.8,
-                   "sources": {"pf_backward.hip": "0f3845d019c4e4df", **_SRC_SHADE}},
-    "k_raster_store": {"fetch_kib": 17658935.2, "write_kib": 11376420.5,
+    "k_bwd_cell": {"fetch_kib": 7865870.9, "write_kib": 2407941.7,
+                   "sources": {"pf_backward.hip": "fb3e4556d9e14fb8", **_SRC_SHADE}},
+    "k_raster_store": {"fetch_kib": 17647219.1, "write_kib": 11375718.7,
                        "sources": {"pf_render.hip": "1e3097ce83ad03bf", **_SRC_SHADE}},
-    "k_trace": {"fetch_kib": 8362485.9, "write_kib": 46637.5,
+    "k_trace": {"fetch_kib": 8362805.2, "write_kib": 46637.5,
                 "sources": {"pf_render.hip": "1e3097ce83ad03bf", **_SRC_SHADE}},
     "k_clip": {"fetch_kib": 409452.2, "write_kib": 180425.5,
                "sources": {"pf_build.hip": "60ddab952277c61e", "pf_internal.hpp": "cf1b6d1fee18a09d",
